@@ -1,0 +1,26 @@
+"""FP64 CPU oracle for the asynchrony-tolerant (AT) compressible-flow solver.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import anything from this package.  The
+product path (the HIP library and its Python binding) never imports, links or
+calls it, and shares no code with it.
+
+The oracle is a plain, slow, readable restatement of the method of
+arXiv 2506.03027 (Arumugam, Goswami, Vadlamani, Aditya):
+
+* ``rk``      -- classical RK4 and the 2N-storage LSERK2/LSERK4 schemes
+                 (Sec. 2, Eq. 3, App. B Table 4) and their stage polynomials.
+* ``at``      -- asynchrony-tolerant coefficients: PE-boundary extrapolation
+                 (Eq. 7, Eqs. 14-15), buffer temporal derivatives (Eqs. 8-13,
+                 App. C Table 5) and the per-stage halo weights W.
+* ``delays``  -- delay schedules of the communication-avoiding (Alg. 2) and
+                 synchronization-avoiding (Alg. 3) algorithms.
+* ``flow``    -- Euler / Navier-Stokes fluxes (Eq. 1, App. A) and the explicit
+                 CD4 derivative (Eq. 2, App. B).
+* ``solver``  -- blocks (processing elements), delayed history, halo filling
+                 in SA / AS / AT modes and the RK step (Sec. 3.2, Alg. 1-3).
+* ``diagnostics`` -- conserved totals, kinetic energy and enstrophy (Sec. 5.2).
+* ``mlp``     -- FP64 reference of the learned-halo MLP (forward, backward).
+
+Everything is float64 numpy or exact ``fractions.Fraction`` arithmetic.
+"""

@@ -1,0 +1,144 @@
+"""Seeded, synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module only *generates* inputs: analytic initial fields, seeded smooth
+random fields and the time step from a CFL number.  It holds none of the
+method's arithmetic (no fluxes, no stencils, no asynchrony-tolerant weights,
+no time integration) and imports neither the HIP binding nor the oracle.
+
+Analytic cases
+--------------
+* Isentropic vortex (the paper's first test case, Sec. 5.1).  The workloads
+  use the standard translating isentropic vortex on a periodic box:
+  rho_inf = p_inf = T_inf = 1, p = rho T, strength beta, centre (5, 5) of
+  [0, 10]^2, freestream 0.5*sqrt(gamma) (Mach 0.5) along the diagonal --
+  (1, 1)/sqrt(2) in 2D and (1, 1, 1)/sqrt(3) in 3D with the vortex axis along
+  z.  With r the minimum-image distance to the translated centre,
+      du = -(beta/2pi) (y-yc) exp((1-r^2)/2),   dv = (beta/2pi) (x-xc) exp((1-r^2)/2),
+      T  = 1 - (gamma-1) beta^2 exp(1-r^2) / (8 gamma pi^2),   rho = T^(1/(gamma-1)).
+  It is an exact Euler solution on the infinite plane; on the periodic box the
+  tail of the perturbation (about 2.4e-5 in velocity at r = 5) sets a floor
+  on the error against the translated initial field.
+* Taylor-Green vortex (Sec. 5.2, Eq. 16) with rho0 = U0 = L0 = 1 on
+  [0, 2pi]^3.  The printed v has the sign that makes the field divergent; the
+  divergence-free form v = -U0 cos x sin y cos z is used.  The initial
+  temperature is uniform, T0 = 1, so rho = gamma M0^2 p.
+"""
+import math
+
+import numpy as np
+
+
+def grid_axes(n, length):
+    """x_i = i * len / N, i = 0..N-1 (periodic, no duplicated endpoint)."""
+    return [np.arange(n[d]) * (length[d] / n[d]) for d in range(3)]
+
+
+def spacing(n, length):
+    return tuple(length[d] / n[d] for d in range(3))
+
+
+def to_conserved(rho, u, v, w, p, gamma):
+    et = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, et]).astype(np.float64)
+
+
+def vortex_freestream(ndim, gamma, mach=0.5):
+    speed = mach * math.sqrt(gamma)
+    if ndim == 2:
+        return (speed / math.sqrt(2.0), speed / math.sqrt(2.0), 0.0)
+    s = speed / math.sqrt(3.0)
+    return (s, s, s)
+
+
+def vortex_state(n, length, ndim, t=0.0, gamma=1.4, beta=5.0,
+                 center=(5.0, 5.0), mach=0.5):
+    """Conserved isentropic-vortex field (5, nz, ny, nx) at time t."""
+    xs, ys, zs = grid_axes(n, length)
+    uinf = vortex_freestream(ndim, gamma, mach)
+    xc = center[0] + uinf[0] * t
+    yc = center[1] + uinf[1] * t
+    Lx, Ly = length[0], length[1]
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    dx = (X - xc + 0.5 * Lx) % Lx - 0.5 * Lx
+    dy = (Y - yc + 0.5 * Ly) % Ly - 0.5 * Ly
+    r2 = dx * dx + dy * dy
+    f = np.exp(0.5 * (1.0 - r2))
+    u = uinf[0] - beta / (2 * math.pi) * dy * f
+    v = uinf[1] + beta / (2 * math.pi) * dx * f
+    w = np.full_like(u, uinf[2])
+    T = 1.0 - (gamma - 1.0) * beta ** 2 * np.exp(1.0 - r2) / (8.0 * gamma * math.pi ** 2)
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho * T
+    return to_conserved(rho, u, v, w, p, gamma)
+
+
+def tgv_state(n, mach=0.1, gamma=1.4):
+    """Conserved Taylor-Green field on [0, 2pi]^3 (5, nz, ny, nx)."""
+    length = (2 * math.pi,) * 3
+    xs, ys, zs = grid_axes(n, length)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    u = np.sin(X) * np.cos(Y) * np.cos(Z)
+    v = -np.cos(X) * np.sin(Y) * np.cos(Z)
+    w = np.zeros_like(u)
+    p = 1.0 / (gamma * mach ** 2) + (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0) / 16.0
+    rho = gamma * mach ** 2 * p
+    return to_conserved(rho, u, v, w, p, gamma)
+
+
+def smooth_random_state(n, length, seed, amp=0.05, modes=3, gamma=1.4, ndim=3,
+                        mach=0.3):
+    """A seeded smooth periodic field: uniform state plus a few random
+    Fourier modes in every primitive variable."""
+    rng = np.random.default_rng(seed)
+    xs, ys, zs = grid_axes(n, length)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    prims = []
+    base = [1.0, mach * math.sqrt(gamma), -0.5 * mach * math.sqrt(gamma),
+            0.25 * mach * math.sqrt(gamma) if ndim == 3 else 0.0, 1.0]
+    for var in range(5):
+        f = np.full(X.shape, base[var])
+        if var == 3 and ndim == 2:
+            prims.append(f)
+            continue
+        for _ in range(modes):
+            kx, ky = rng.integers(1, 3, size=2)
+            kz = rng.integers(1, 3) if ndim == 3 else 0
+            ph = rng.uniform(0, 2 * math.pi)
+            a = amp * rng.uniform(0.5, 1.0)
+            f = f + a * np.sin(2 * math.pi * (kx * X / length[0] + ky * Y / length[1]
+                                                + kz * Z / length[2]) + ph)
+        prims.append(f)
+    rho, u, v, w, p = prims
+    return to_conserved(rho, u, v, w, p, gamma)
+
+
+def cfl_dt(U, n, length, ndim, gamma, cfl):
+    """dt = CFL / max_x sum_d (|u_d| + c) / h_d, from the given field."""
+    h = spacing(n, length)
+    rho = U[0]
+    vel = [U[1] / rho, U[2] / rho, U[3] / rho]
+    p = (gamma - 1.0) * (U[4] - 0.5 * rho * (vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2))
+    c = np.sqrt(gamma * p / rho)
+    s = np.zeros_like(rho)
+    for d in range(ndim):
+        s = s + (np.abs(vel[d]) + c) / h[d]
+    return float(cfl / s.max())
+
+
+# The workloads of the benchmark and parity tests, named by what they are.
+WORKLOADS = {
+    "vortex2d_64": dict(n=(64, 64, 1), length=(10.0, 10.0, 1.0), ndim=2,
+                        nblk=(1, 1, 1), physics="euler", rk="rk4", mode="sa",
+                        L=1, cfl=0.5, steps=200, precision="f64"),
+    "vortex3d_128": dict(n=(128, 128, 128), length=(10.0, 10.0, 10.0), ndim=3,
+                         nblk=(4, 4, 4), physics="euler", rk="rk4", mode="at",
+                         algo="saa", L=4, cfl=0.25, precision="f32"),
+    "tgv_256": dict(n=(256, 256, 256), length=(2 * math.pi,) * 3, ndim=3,
+                    nblk=(16, 16, 8), physics="ns", rk="rk4", mode="at",
+                    algo="saa", L=4, re=1600.0, mach=0.1, cfl=0.25,
+                    steps=2000, precision="f32"),
+    "tgv_512": dict(n=(512, 512, 512), length=(2 * math.pi,) * 3, ndim=3,
+                    nblk=(16, 16, 16), physics="ns", rk="rk4", mode="at",
+                    algo="saa", L=5, re=1600.0, mach=0.1, cfl=0.25,
+                    precision="f32"),
+}
