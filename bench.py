@@ -1,0 +1,227 @@
+"""Throughput benchmark of the AT compressible-flow hot path on one MI355X.
+
+Metric: grid-point x RK-stage updates per second of the FP32 asynchrony-
+tolerant solver (one "step" = one RK step of the whole hot path: delay draw,
+AT halo assembly from the delayed-level ring, CD4 flux divergence, RK stage
+updates, ring write of the new boundary layers), with inputs resident in HBM.
+Reported beside it: the plain FP64 synchronous (SA) path on the same grid,
+the roofline of the dominant (fused stage) kernel from HIP events recorded
+around each of its launches, and the FP64 oracle timed on the host CPU on a
+bounded sample of the same workload (with the FP32 GPU result's L2 error
+against it).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2506_03027_amd import atns, inputs  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
+C_LEVELS = 5
+
+
+def algorithmic_bytes_per_point_stage(w, stages, esz):
+    """Bytes the method must move per owned point per RK stage: the state in
+    and out plus one RK register (80 B at FP32, averaged over the stages),
+    plus, for delayed halos, C ring levels (AT; one level for AS) of 5
+    values per halo point, plus the ring write of the boundary layers once
+    per step.  f = halo points per owned point of a block."""
+    n, nb, ndim = w["n"], w["nblk"], w["ndim"]
+    H = 4 if w["physics"] == "ns" else 2
+    b = [n[d] // nb[d] for d in range(3)]
+    own = b[0] * b[1] * (b[2] if ndim == 3 else 1)
+    dims = range(ndim)
+    halo = 0
+    for d in dims:
+        face = 1
+        for e in dims:
+            if e != d:
+                face *= b[e]
+        halo += 2 * H * face
+    if w["physics"] == "ns":
+        for d in dims:
+            for e in dims:
+                if e > d:
+                    other = [x for x in dims if x not in (d, e)]
+                    length = b[other[0]] if other else 1
+                    halo += 4 * 4 * length
+    f = halo / own
+    scale = esz / 4.0
+    if w["mode"] == "sa":
+        return 80.0 * scale, f
+    levels = C_LEVELS if w["mode"] == "at" else 1
+    return (80.0 + 20.0 * levels * f + 20.0 * f / stages) * scale, f
+
+
+def make_solver(w, precision, mode=None):
+    phys = atns.NS if w["physics"] == "ns" else atns.EULER
+    m = {"sa": atns.SA, "as": atns.AS, "at": atns.AT}[mode or w["mode"]]
+    algo = atns.SAA if w.get("algo", "saa") == "saa" else atns.CAA
+    return atns.Solver(n=w["n"], length=w["length"], ndim=w["ndim"], nblk=w["nblk"], physics=phys,
+                       mach=w.get("mach", 0.1), re=w.get("re", 1600.0),
+                       rk=atns.RK4 if w["rk"] == "rk4" else atns.LSERK4, mode=m, algo=algo,
+                       L=w["L"], seed=w.get("seed", 1), precision=precision)
+
+
+def initial_state(w):
+    if w["physics"] == "ns":
+        return inputs.tgv_state(w["n"], mach=w.get("mach", 0.1))
+    return inputs.vortex_state(w["n"], w["length"], w["ndim"])
+
+
+def time_steps(torch, g, steps):
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def gpu_run(torch, w, precision, mode, steps, warmup, U0, dt):
+    g = make_solver(w, precision, mode)
+    g.set_dt(dt)
+    g.set_state(torch.from_numpy(U0))
+    g.step(warmup)
+    ms = time_steps(torch, g, steps)
+    # per-launch durations of the fused stage kernel, from HIP events on the
+    # library's stream, over a second pass of the same length
+    g.profile(True)
+    g.step(steps)
+    launches, kms = g.profile_read()
+    g.profile(False)
+    diag, finite = g.reduce()
+    g.close()
+    return ms, launches, kms, finite
+
+
+def cpu_baseline(torch, w, budget_s=20.0):
+    """The FP64 oracle on a bounded sample of the workload: the same block
+    shape and halo scheme on a smaller grid, started from a delayed history
+    of the translating vortex so that every timed step is asynchronous.  The
+    FP32 GPU path runs the same sample for the L2 error."""
+    from oracle import solver
+    scale = 2 if w["n"][0] >= 128 else 1
+    n = tuple(max(16, x // scale) for x in w["n"])
+    nblk = tuple(max(1, b // scale) for b in w["nblk"])
+    s = dict(w, n=n, nblk=nblk)
+    length = w["length"]
+    stages = 4 if w["rk"] == "rk4" else 5
+    cfg = solver.Config(n, length, w["ndim"], nblk, w["physics"], mach=w.get("mach", 0.1),
+                        re=w.get("re", 1600.0), rk=w["rk"], mode=w["mode"], algo=w.get("algo", "saa"),
+                        L=w["L"], seed=w.get("seed", 1))
+    U0 = initial_state(s)
+    dt = inputs.cfl_dt(U0, n, length, w["ndim"], 1.4, w["cfl"])
+    cfg.dt = dt
+    o = solver.Oracle(cfg)
+    D = C_LEVELS + w["L"]
+    n0 = 2 * D
+    hist = {}
+    for m in range(n0 - D + 1, n0 + 1):
+        if w["physics"] == "ns":
+            hist[m] = U0
+        else:
+            hist[m] = inputs.vortex_state(n, length, w["ndim"], t=(m - n0) * dt)
+        o.set_state(hist[m], step=m)
+    t0 = time.perf_counter()
+    done = 0
+    while done < 1 or (time.perf_counter() - t0 < budget_s * 0.5 and done < 4):
+        o.step(1)
+        done += 1
+    elapsed = time.perf_counter() - t0
+    npts = n[0] * n[1] * n[2]
+    value = npts * stages * done / elapsed
+    # the same sample through the FP32 GPU path
+    g = make_solver(s, atns.F32)
+    g.set_dt(dt)
+    for m in sorted(hist):
+        g.set_state(torch.from_numpy(hist[m]), step=m)
+    g.step(done)
+    G = g.get_state().double().cpu().numpy()
+    g.close()
+    l2 = float(np.linalg.norm(G - o.U) / np.linalg.norm(o.U))
+    linf = float(np.abs(G - o.U).max() / np.abs(o.U).max())
+    return {"value": value, "unit": "grid-point-stage/s", "cores": 1, "kind": "oracle",
+            "sample": "%s grid %dx%dx%d, %d blocks, %d asynchronous RK steps from a delayed "
+                      "history, FP64 numpy on one host core" % (
+                          w["physics"], n[0], n[1], n[2], nblk[0] * nblk[1] * nblk[2], done),
+            "seconds": elapsed, "fp32_gpu_rel_l2_vs_oracle": l2, "fp32_gpu_rel_linf_vs_oracle": linf}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="vortex3d_128")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus 1 only)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    w = inputs.WORKLOADS[a.workload]
+    stages = 4 if w["rk"] == "rk4" else 5
+    npts = w["n"][0] * w["n"][1] * w["n"][2]
+    U0 = initial_state(w)
+    dt = inputs.cfl_dt(U0, w["n"], w["length"], w["ndim"], 1.4, w["cfl"])
+    warmup = max(a.warmup, C_LEVELS + 1)   # the first C steps are synchronous
+
+    ms, launches, kms, finite = gpu_run(torch, w, atns.F32, None, a.steps, warmup, U0, dt)
+    value = npts * stages * a.steps / (ms * 1e-3)
+    bpp, f = algorithmic_bytes_per_point_stage(w, stages, 4)
+    avg_launch_ms = kms / max(1, launches)
+    achieved = bpp * npts / (avg_launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": "grid-point-stage updates/s (FP32 AT vs FP64 SA)",
+        "value": value,
+        "unit": "grid-point-stage/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": warmup,
+        "ms_per_step": ms / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "grid": list(w["n"]), "blocks": list(w["nblk"]),
+                   "physics": w["physics"], "scheme": "CD4 + %s halos, %s" % (w["mode"].upper(),
+                                                                             w["rk"].upper()),
+                   "algo": w.get("algo", "saa").upper(), "L": w["L"], "cfl": w["cfl"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "%s_stage_kernel" % ("ns" if w["physics"] == "ns" else "euler"),
+                     "bytes_per_point_stage": bpp, "halo_points_per_point": f,
+                     "avg_launch_ms": avg_launch_ms, "launches": launches},
+        "finite": finite,
+    }
+    if not a.no_fp64:
+        ms64, l64, k64, fin64 = gpu_run(torch, w, atns.F64, "sa", a.steps, warmup, U0, dt)
+        b64, _ = algorithmic_bytes_per_point_stage(dict(w, mode="sa"), stages, 8)
+        out["fp64_sa"] = {"value": npts * stages * a.steps / (ms64 * 1e-3),
+                          "ms_per_step": ms64 / a.steps,
+                          "avg_launch_ms": k64 / max(1, l64),
+                          "hbm_frac": b64 * npts / (k64 / max(1, l64) * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out["speedup_vs_fp64_sa"] = out["value"] / out["fp64_sa"]["value"]
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(torch, w)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

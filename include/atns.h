@@ -1,0 +1,190 @@
+/*
+ * atns.h -- C ABI of the asynchrony-tolerant (AT) compressible-flow
+ * right-hand-side library for AMD MI355X (gfx950).
+ *
+ * The library advances the compressible Euler / Navier-Stokes equations
+ * (Sec. 2, Eq. 1 and App. A of arXiv 2506.03027) on a uniform periodic
+ * Cartesian grid with the explicit fourth-order central difference (Eq. 2,
+ * CD4 of App. B).  The grid is split into a tensor product of blocks -- the
+ * processing elements (PEs) of Sec. 3 -- that all live on one GPU.  Each
+ * block reads the points it does not own (its halo, the "buffer points" of
+ * Sec. 3) either synchronously (SA, Alg. 1) or from a ring of delayed time
+ * levels, as the communication-avoiding (CAA, Alg. 2) or the
+ * synchronization-avoiding (SAA, Alg. 3) algorithm would deliver them, with
+ * the asynchrony-tolerant buffer extrapolation and updates of Sec. 3.1-3.2
+ * (Eqs. 7-15, App. C) or with plain stale data (AS).
+ *
+ * Conventions
+ * -----------
+ * - Every function returns an atns_status; no function throws or aborts.
+ *   ATNS_EINVAL reports a bad argument or configuration, ATNS_EHIP a failed
+ *   HIP runtime call, ATNS_ENOMEM a failed device allocation, ATNS_ESTATE a
+ *   call in the wrong state (e.g. stepping before a state is set).
+ *   atns_last_error() returns a message for the last failure on a context.
+ * - The library owns every device allocation it makes and frees it in
+ *   atns_destroy().  Pointers passed in by the caller are borrowed for the
+ *   duration of the call only.
+ * - "dev" pointers are device (HIP) pointers on the context's device;
+ *   "host" pointers are ordinary host memory.
+ * - Field layout: structure of arrays, 5 conserved variables
+ *   (rho, rho u, rho v, rho w, rho E_t), each a contiguous [nz][ny][nx]
+ *   array with x fastest: element (v, k, j, i) at ((v*nz + k)*ny + j)*nx + i.
+ *   The element type is float (ATNS_F32) or double (ATNS_F64).
+ * - Work is enqueued on the stream given to atns_create() (NULL = the null
+ *   stream).  Only atns_reduce(), atns_get_state(on_host=1) and
+ *   atns_get_delays() synchronize with the host.
+ * - Steps are numbered n = 0, 1, ...; step n advances U^n to U^{n+1}.
+ *
+ * Neighbour slots (index into delay arrays):
+ *   0 -x   1 +x   2 -y   3 +y   4 -z   5 +z
+ *   6 (-x,-y)  7 (+x,-y)  8 (-x,+y)  9 (+x,+y)
+ *  10 (-x,-z) 11 (+x,-z) 12 (-x,+z) 13 (+x,+z)
+ *  14 (-y,-z) 15 (+y,-z) 16 (-y,+z) 17 (+y,+z)
+ * Euler uses the six faces (halo depth 2).  Navier-Stokes uses faces of
+ * depth 4 and the twelve 2x2 edge regions (viscous terms as repeated first
+ * derivatives).  Delays are int8 arrays [nblocks][ATNS_NSLOTS].
+ */
+#ifndef ATNS_H
+#define ATNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ATNS_NSLOTS 18
+#define ATNS_NDIAG 7
+
+typedef struct atns_ctx atns_ctx;
+
+typedef enum {
+  ATNS_OK = 0,
+  ATNS_EINVAL = -1,
+  ATNS_ENOMEM = -2,
+  ATNS_EHIP = -3,
+  ATNS_ESTATE = -4,
+  ATNS_ENONFINITE = -5
+} atns_status;
+
+enum { ATNS_EULER = 0, ATNS_NS = 1 };                 /* physics          */
+enum { ATNS_RK4 = 0, ATNS_LSERK4 = 1 };               /* time integrator  */
+enum { ATNS_SA = 0, ATNS_AS = 1, ATNS_AT = 2 };       /* halo treatment   */
+enum { ATNS_CAA = 0, ATNS_SAA = 1 };                  /* delay algorithm  */
+enum { ATNS_F32 = 0, ATNS_F64 = 1 };                  /* state precision  */
+
+typedef struct {
+  int32_t ndim;          /* 2 or 3; ndim == 2 requires n[2] == 1, nblk[2] == 1 */
+  int32_t n[3];          /* global points nx, ny, nz                          */
+  double len[3];         /* periodic box lengths; h_d = len[d] / n[d]         */
+  int32_t nblk[3];       /* blocks per direction                              */
+  const int32_t* split[3]; /* optional host arrays of nblk[d] block sizes
+                              summing to n[d]; NULL = even split (the first
+                              n % nblk blocks get one extra point)            */
+  int32_t physics;       /* ATNS_EULER | ATNS_NS                              */
+  double gamma, mach, re, pr; /* gas: p = (gamma-1)(rho E - rho|u|^2/2),
+                              T = gamma M^2 p / rho, mu = 1,
+                              kappa = 1/((gamma-1) M^2 Pr); re, pr NS only    */
+  int32_t rk;            /* ATNS_RK4 | ATNS_LSERK4 (Eq. 3, Table 4)           */
+  int32_t mode;          /* ATNS_SA | ATNS_AS | ATNS_AT                       */
+  int32_t algo;          /* ATNS_CAA | ATNS_SAA                               */
+  int32_t L;             /* delay bound: delays are 0..L-1 (Alg. 2, 3)        */
+  uint64_t seed;         /* SAA delay stream seed                             */
+  int32_t precision;     /* ATNS_F32 | ATNS_F64                               */
+} atns_config;
+
+/* Library version string (static storage). */
+const char* atns_version(void);
+
+/* Create a context on the current HIP device.  Validates the configuration
+ * (EINVAL: block smaller than the halo depth in an active direction, split
+ * not summing to n, L < 1 or L > 16, unknown enums, ndim == 2 with nz != 1)
+ * before any device call.  stream: a hipStream_t, or NULL.  On success *out
+ * owns all device buffers: state and RK registers, the delayed-level ring
+ * (C + L levels of each block's boundary layers, C = 5 for AT4) and tables. */
+atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out);
+
+/* Free every resource of the context.  NULL is accepted. */
+atns_status atns_destroy(atns_ctx* ctx);
+
+/* Message of the last failure on ctx (never NULL). */
+const char* atns_last_error(const atns_ctx* ctx);
+
+/* Set U^step := dev_U (borrowed device array in the field layout) and make
+ * `step` the current step.  The state is also recorded as history level
+ * `step` (its boundary layers go into ring slot step mod D), so calling this
+ * for consecutive steps m0..m1 builds a delayed history ending at m1. */
+atns_status atns_set_state(atns_ctx* ctx, const void* dev_U, int64_t step);
+
+/* Copy the current state into dst (device pointer if on_host == 0, host
+ * pointer otherwise; host copies synchronize). */
+atns_status atns_get_state(const atns_ctx* ctx, void* dst, int32_t on_host);
+
+/* Current step number n. */
+atns_status atns_get_step(const atns_ctx* ctx, int64_t* step);
+
+/* Fixed time step (dt > 0).  The AT weights assume a constant dt (Sec. 3.1). */
+atns_status atns_set_dt(atns_ctx* ctx, double dt);
+
+/* Inject delays for steps step0 .. step0+nsteps-1 (host int8 array
+ * [nsteps][nblocks][ATNS_NSLOTS]); they replace the CAA/SAA draws for those
+ * steps.  The guard of Alg. 3 still applies: a delay above L-1, or one that
+ * needs a level older than the history (k > n - C + 1), becomes 0.  nsteps
+ * == 0 clears all injected delays. */
+atns_status atns_set_delays(atns_ctx* ctx, int64_t step0, int32_t nsteps, const int8_t* host_k);
+
+/* The delays (after the guard) that step `step` uses, into a host int8
+ * array [nblocks][ATNS_NSLOTS].  Synchronous steps (SA mode, or step < C)
+ * report all zeros and set *synchronous = 1. */
+atns_status atns_get_delays(atns_ctx* ctx, int64_t step, int8_t* host_k, int32_t* synchronous);
+
+/* Right-hand side R(U^n) of the current state with the halo of stage 0 of
+ * the current step (synchronous, AS or AT as configured), into dev_R (field
+ * layout, context precision).  Does not advance the step. */
+atns_status atns_rhs(atns_ctx* ctx, void* dev_R);
+
+/* Advance nsteps steps (asynchronous on the context stream).  Each step: the
+ * delay draw, s fused stencil + RK-stage kernels (the halo of stage e from
+ * the ring with the FP64 weights W[e][k][:]), and the ring write of U^{n+1}
+ * in the last stage. */
+atns_status atns_rk_step(atns_ctx* ctx, int32_t nsteps);
+
+/* FP64 diagnostics of the current state (Sec. 5.2), into host_out[7]:
+ * the five conserved totals sum U_v dV, the volume-averaged kinetic energy
+ * (1/2V) int rho|u|^2 dV and enstrophy (1/2V) int rho|w|^2 dV, vorticity
+ * by CD4 on the synchronous global field.  Synchronizes.  Returns
+ * ATNS_ENONFINITE (with the values still written) if any value is not
+ * finite. */
+atns_status atns_reduce(atns_ctx* ctx, double* host_out);
+
+/* Number of blocks, and the ring depth D (levels kept), of a context. */
+atns_status atns_get_layout(const atns_ctx* ctx, int32_t* nblocks, int32_t* ring_depth);
+
+/* Per-kernel timing of the fused stage kernels.  While enabled (on != 0),
+ * every stage-kernel launch of atns_rk_step is bracketed by a pair of HIP
+ * events recorded on the context stream.  atns_profile_read synchronizes,
+ * returns the number of timed launches and their summed duration in ms, and
+ * clears the record.  Disabling also clears it. */
+atns_status atns_profile_enable(atns_ctx* ctx, int32_t on);
+atns_status atns_profile_read(atns_ctx* ctx, int64_t* launches, double* total_ms);
+
+/* ---- host-only helpers (no device needed) -------------------------------
+ * The FP64 per-stage halo weight table the kernels use: out[e][k][l] for
+ * stages e < s (s = 4 for RK4, 5 for LSERK4), delays k < L and levels
+ * l < C (C = 5).  AT: the AT4 buffer extrapolation (stage 0, Eq. 15) and
+ * the RK-consistent buffer updates (Eqs. 8-13) in closed form; AS: 1 at
+ * l = 0.  out must hold s*L*C doubles. */
+atns_status atns_host_weights(int32_t rk, int32_t mode, int32_t L, double* out);
+
+/* The delays step n would draw (after the guard), without a device, into
+ * out[nblocks][ATNS_NSLOTS]; *synchronous = 1 (and zeros) when n < C.
+ * CAA: k = (n - C) mod L everywhere.  SAA: SplitMix64 draw number
+ * (n*nblocks + b)*ATNS_NSLOTS + v of stream `seed`, modulo L. */
+atns_status atns_host_delays(int32_t algo, int64_t n, int32_t nblocks, int32_t L,
+                             uint64_t seed, int8_t* out, int32_t* synchronous);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ATNS_H */

@@ -1,0 +1,218 @@
+"""ctypes binding of libatns.so (include/atns.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies device memory (tensors whose data_ptr() is passed through)
+and the HIP stream.  If the library is missing this module raises at import
+of the library (``lib()``) -- there is no fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libatns.so")
+
+EULER, NS = 0, 1
+RK4, LSERK4 = 0, 1
+SA, AS, AT = 0, 1, 2
+CAA, SAA = 0, 1
+F32, F64 = 0, 1
+NSLOTS = 18
+NDIAG = 7
+C_LEVELS = 5
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE"}
+
+EXPORTS = ["atns_version", "atns_create", "atns_destroy", "atns_last_error", "atns_set_state",
+           "atns_get_state", "atns_get_step", "atns_set_dt", "atns_set_delays", "atns_get_delays",
+           "atns_rhs", "atns_rk_step", "atns_reduce", "atns_get_layout", "atns_profile_enable",
+           "atns_profile_read", "atns_host_weights", "atns_host_delays"]
+
+
+class AtnsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("len", ctypes.c_double * 3),
+                ("nblk", ctypes.c_int32 * 3), ("split", ctypes.POINTER(ctypes.c_int32) * 3),
+                ("physics", ctypes.c_int32), ("gamma", ctypes.c_double), ("mach", ctypes.c_double),
+                ("re", ctypes.c_double), ("pr", ctypes.c_double), ("rk", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("algo", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libatns.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "atns_version": ([], ctypes.c_char_p),
+            "atns_create": ([ctypes.POINTER(Config), vp, ctypes.POINTER(vp)], i32),
+            "atns_destroy": ([vp], i32),
+            "atns_last_error": ([vp], ctypes.c_char_p),
+            "atns_set_state": ([vp, vp, i64], i32),
+            "atns_get_state": ([vp, vp, i32], i32),
+            "atns_get_step": ([vp, ctypes.POINTER(i64)], i32),
+            "atns_set_dt": ([vp, dbl], i32),
+            "atns_set_delays": ([vp, i64, i32, vp], i32),
+            "atns_get_delays": ([vp, i64, vp, ctypes.POINTER(i32)], i32),
+            "atns_rhs": ([vp, vp], i32),
+            "atns_rk_step": ([vp, i32], i32),
+            "atns_reduce": ([vp, vp], i32),
+            "atns_get_layout": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+            "atns_profile_enable": ([vp, i32], i32),
+            "atns_profile_read": ([vp, ctypes.POINTER(i64), ctypes.POINTER(dbl)], i32),
+            "atns_host_weights": ([i32, i32, i32, vp], i32),
+            "atns_host_delays": ([i32, i64, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(i32)], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        msg = lib().atns_last_error(ctx).decode()
+        raise AtnsError(status, msg)
+
+
+def host_weights(rk, mode, L):
+    s = 4 if rk == RK4 else 5
+    out = np.zeros((s, L, C_LEVELS), dtype=np.float64)
+    _check(lib().atns_host_weights(rk, mode, L, out.ctypes.data))
+    return out
+
+
+def host_delays(algo, n, nblocks, L, seed):
+    out = np.zeros((nblocks, NSLOTS), dtype=np.int8)
+    sync = ctypes.c_int32(0)
+    _check(lib().atns_host_delays(algo, n, nblocks, L, ctypes.c_uint64(seed), out.ctypes.data,
+                                  ctypes.byref(sync)))
+    return out, bool(sync.value)
+
+
+def make_config(n, length, ndim=3, nblk=(1, 1, 1), physics=EULER, gamma=1.4, mach=0.1, re=1600.0,
+                pr=0.71, rk=RK4, mode=SA, algo=CAA, L=1, seed=0, precision=F32, split=None):
+    cfg = Config()
+    cfg.ndim = ndim
+    for d in range(3):
+        cfg.n[d] = int(n[d])
+        cfg.len[d] = float(length[d])
+        cfg.nblk[d] = int(nblk[d])
+    keep = []
+    if split is not None:
+        for d in range(3):
+            arr = (ctypes.c_int32 * len(split[d]))(*split[d])
+            keep.append(arr)
+            cfg.split[d] = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+    cfg.physics, cfg.gamma, cfg.mach, cfg.re, cfg.pr = physics, gamma, mach, re, pr
+    cfg.rk, cfg.mode, cfg.algo, cfg.L, cfg.seed, cfg.precision = rk, mode, algo, L, seed, precision
+    return cfg, keep
+
+
+class Solver:
+    """One context of the library; state tensors live on the current device."""
+
+    def __init__(self, stream=None, **kw):
+        import torch
+        self.torch = torch
+        self.kw = dict(kw)
+        self.cfg, keep = make_config(**kw)
+        self.n = tuple(kw["n"])
+        self.dtype = torch.float64 if kw.get("precision", F32) == F64 else torch.float32
+        ctx = ctypes.c_void_p()
+        st = lib().atns_create(ctypes.byref(self.cfg), stream, ctypes.byref(ctx))
+        if st != 0:
+            raise AtnsError(st, lib().atns_last_error(None).decode())
+        self.ctx = ctx
+        nb, D = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().atns_get_layout(ctx, ctypes.byref(nb), ctypes.byref(D)), ctx)
+        self.nblocks, self.ring_depth = nb.value, D.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().atns_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (5, self.n[2], self.n[1], self.n[0])
+
+    def set_state(self, U, step=0):
+        U = U.to(device="cuda", dtype=self.dtype).contiguous()
+        if tuple(U.shape) != self.shape:
+            raise ValueError("state shape %s, expected %s" % (tuple(U.shape), self.shape))
+        self.torch.cuda.synchronize()
+        _check(lib().atns_set_state(self.ctx, ctypes.c_void_p(U.data_ptr()), int(step)), self.ctx)
+        self.torch.cuda.synchronize()      # U may be freed after return
+
+    def get_state(self):
+        out = self.torch.empty(self.shape, dtype=self.dtype, device="cuda")
+        _check(lib().atns_get_state(self.ctx, ctypes.c_void_p(out.data_ptr()), 0), self.ctx)
+        self.torch.cuda.synchronize()
+        return out
+
+    def set_dt(self, dt):
+        _check(lib().atns_set_dt(self.ctx, float(dt)), self.ctx)
+
+    def set_delays(self, step0, k):
+        k = np.ascontiguousarray(k, dtype=np.int8)
+        nsteps = 0 if k.size == 0 else k.shape[0]
+        _check(lib().atns_set_delays(self.ctx, int(step0), nsteps, k.ctypes.data if nsteps else None),
+               self.ctx)
+
+    def get_delays(self, step):
+        out = np.zeros((self.nblocks, NSLOTS), dtype=np.int8)
+        sync = ctypes.c_int32(0)
+        _check(lib().atns_get_delays(self.ctx, int(step), out.ctypes.data, ctypes.byref(sync)), self.ctx)
+        return None if sync.value else out
+
+    def step_number(self):
+        s = ctypes.c_int64()
+        _check(lib().atns_get_step(self.ctx, ctypes.byref(s)), self.ctx)
+        return s.value
+
+    def rhs(self):
+        out = self.torch.empty(self.shape, dtype=self.dtype, device="cuda")
+        self.torch.cuda.synchronize()
+        _check(lib().atns_rhs(self.ctx, ctypes.c_void_p(out.data_ptr())), self.ctx)
+        self.torch.cuda.synchronize()
+        return out
+
+    def step(self, nsteps=1):
+        _check(lib().atns_rk_step(self.ctx, int(nsteps)), self.ctx)
+
+    def profile(self, on):
+        _check(lib().atns_profile_enable(self.ctx, 1 if on else 0), self.ctx)
+
+    def profile_read(self):
+        """(number of timed stage-kernel launches, their total ms)."""
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        _check(lib().atns_profile_read(self.ctx, ctypes.byref(n), ctypes.byref(ms)), self.ctx)
+        return n.value, ms.value
+
+    def reduce(self):
+        out = np.zeros(NDIAG, dtype=np.float64)
+        st = lib().atns_reduce(self.ctx, out.ctypes.data)
+        if st not in (0, -5):
+            _check(st, self.ctx)
+        return out, st == 0

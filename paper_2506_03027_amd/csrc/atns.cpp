@@ -1,0 +1,590 @@
+// C ABI of the AT compressible-flow library: context, layout, scheduling.
+#include "atns.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "coeffs.hpp"
+#include "launch.hpp"
+#include "layout.hpp"
+
+using namespace atns;
+
+struct atns_ctx {
+  atns_config cfg{};
+  std::vector<int> split[3];
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  int H = 2;
+  RKScheme rk{};
+  int nb = 0;
+  std::vector<BlockDev> blocks;
+  std::vector<TileDev> tiles;
+  size_t esz = 4;
+  long long field = 0;
+  // RK registers: RK4 uses X[0] = U, X[1] = Ya, X[2] = Yb, X[3] = acc.
+  // LSERK uses X[cur] = U, X[1-cur] = the other stage buffer, X[3] = Q.
+  void* X[4] = {nullptr, nullptr, nullptr, nullptr};
+  int cur = 0;
+  void* ring = nullptr;
+  int D = 0;
+  long long slot_stride = 0;
+  BlockDev* d_blocks = nullptr;
+  TileDev* d_tiles = nullptr;
+  int8_t* d_delays = nullptr;
+  int8_t* d_probe = nullptr;
+  int8_t* d_inject = nullptr;
+  int64_t inject0 = 0;
+  int inject_n = 0;
+  double* d_W = nullptr;
+  double* d_partials = nullptr;
+  double* d_diag = nullptr;
+  int nparts = 1024;
+  double dt = 0.0;
+  int64_t step = 0;
+  bool state_set = false;
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;   // reusable events
+  size_t ev_used = 0;                // events recorded since the last read
+  std::string err;
+};
+
+namespace {
+
+std::string g_err;
+
+atns_status fail(atns_ctx* c, atns_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(ctx, ATNS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+bool slot_used(const atns_ctx* c, int s) {
+  int d[3];
+  slot_dir(s, d);
+  if (c->cfg.ndim == 2 && d[2] != 0) return false;
+  const int nz = (d[0] != 0) + (d[1] != 0) + (d[2] != 0);
+  return nz == 1 || (nz == 2 && c->cfg.physics == ATNS_NS);
+}
+
+atns_status validate(const atns_config* cfg, std::vector<int> split[3], atns_ctx* c) {
+  if (!cfg) return fail(c, ATNS_EINVAL, "null config");
+  if (cfg->ndim != 2 && cfg->ndim != 3) return fail(c, ATNS_EINVAL, "ndim must be 2 or 3");
+  if (cfg->physics != ATNS_EULER && cfg->physics != ATNS_NS) return fail(c, ATNS_EINVAL, "bad physics");
+  if (cfg->rk != ATNS_RK4 && cfg->rk != ATNS_LSERK4) return fail(c, ATNS_EINVAL, "bad rk");
+  if (cfg->mode != ATNS_SA && cfg->mode != ATNS_AS && cfg->mode != ATNS_AT)
+    return fail(c, ATNS_EINVAL, "bad mode");
+  if (cfg->algo != ATNS_CAA && cfg->algo != ATNS_SAA) return fail(c, ATNS_EINVAL, "bad algo");
+  if (cfg->precision != ATNS_F32 && cfg->precision != ATNS_F64) return fail(c, ATNS_EINVAL, "bad precision");
+  if (cfg->L < 1 || cfg->L > 16) return fail(c, ATNS_EINVAL, "L must be in 1..16");
+  if (!(cfg->gamma > 1.0)) return fail(c, ATNS_EINVAL, "gamma must exceed 1");
+  if (cfg->physics == ATNS_NS && (!(cfg->mach > 0) || !(cfg->re > 0) || !(cfg->pr > 0)))
+    return fail(c, ATNS_EINVAL, "Navier-Stokes needs mach, re, pr > 0");
+  const int H = cfg->physics == ATNS_NS ? 4 : 2;
+  for (int d = 0; d < 3; ++d) {
+    if (cfg->n[d] < 1 || cfg->nblk[d] < 1 || cfg->nblk[d] > cfg->n[d])
+      return fail(c, ATNS_EINVAL, "bad grid or block count");
+    if (!(cfg->len[d] > 0)) return fail(c, ATNS_EINVAL, "box lengths must be positive");
+    if (cfg->n[d] > 32767) return fail(c, ATNS_EINVAL, "grid too large in one direction");
+    split[d].clear();
+    if (cfg->split[d]) {
+      long long tot = 0;
+      for (int i = 0; i < cfg->nblk[d]; ++i) {
+        split[d].push_back(cfg->split[d][i]);
+        tot += cfg->split[d][i];
+      }
+      if (tot != cfg->n[d]) return fail(c, ATNS_EINVAL, "split does not sum to n");
+    } else {
+      const int base = cfg->n[d] / cfg->nblk[d], rem = cfg->n[d] % cfg->nblk[d];
+      for (int i = 0; i < cfg->nblk[d]; ++i) split[d].push_back(base + (i < rem ? 1 : 0));
+    }
+    const bool active = d < cfg->ndim;
+    for (int s : split[d]) {
+      if (s < 1) return fail(c, ATNS_EINVAL, "empty block");
+      if (active && s < H) return fail(c, ATNS_EINVAL, "block smaller than the halo depth");
+    }
+  }
+  if (cfg->ndim == 2 && (cfg->n[2] != 1 || cfg->nblk[2] != 1))
+    return fail(c, ATNS_EINVAL, "2D needs nz == 1 and one block in z");
+  return ATNS_OK;
+}
+
+void build_layout(atns_ctx* c) {
+  const atns_config& cfg = c->cfg;
+  const int nbx = cfg.nblk[0], nby = cfg.nblk[1], nbz = cfg.nblk[2];
+  std::vector<int> start[3];
+  for (int d = 0; d < 3; ++d) {
+    int s = 0;
+    for (int v : c->split[d]) {
+      start[d].push_back(s);
+      s += v;
+    }
+  }
+  c->nb = nbx * nby * nbz;
+  c->blocks.assign(c->nb, BlockDev{});
+  auto bid = [&](int ix, int iy, int iz) {
+    ix = (ix + nbx) % nbx;
+    iy = (iy + nby) % nby;
+    iz = (iz + nbz) % nbz;
+    return (iz * nby + iy) * nbx + ix;
+  };
+  long long off = 0;
+  for (int iz = 0; iz < nbz; ++iz)
+    for (int iy = 0; iy < nby; ++iy)
+      for (int ix = 0; ix < nbx; ++ix) {
+        BlockDev& B = c->blocks[bid(ix, iy, iz)];
+        const int idx[3] = {ix, iy, iz};
+        for (int d = 0; d < 3; ++d) {
+          B.o[d] = start[d][idx[d]];
+          B.s[d] = c->split[d][idx[d]];
+        }
+        for (int s = 0; s < kNumSlots; ++s) {
+          int dir[3];
+          slot_dir(s, dir);
+          B.nbr[s] = bid(ix + dir[0], iy + dir[1], iz + dir[2]);
+          B.lay[s] = -1;
+        }
+      }
+  // ring layers, block-major so a block's layers are adjacent
+  for (int b = 0; b < c->nb; ++b) {
+    BlockDev& B = c->blocks[b];
+    for (int s = 0; s < kNumSlots; ++s) {
+      if (!slot_used(c, s)) continue;
+      int dir[3];
+      slot_dir(s, dir);
+      const int dep = s < 6 ? c->H : 2;
+      long long cnt = 5;
+      for (int d = 0; d < 3; ++d) cnt *= dir[d] ? dep : B.s[d];
+      B.lay[s] = off;
+      off += cnt;
+    }
+  }
+  c->slot_stride = off;
+}
+
+void build_tiles(atns_ctx* c, int TX, int TY, int TZ) {
+  std::vector<TileDev> nat;
+  for (int b = 0; b < c->nb; ++b) {
+    const BlockDev& B = c->blocks[b];
+    for (int z0 = 0; z0 < B.s[2]; z0 += TZ)
+      for (int y0 = 0; y0 < B.s[1]; y0 += TY)
+        for (int x0 = 0; x0 < B.s[0]; x0 += TX) {
+          TileDev t;
+          t.blk = b;
+          t.x0 = (short)x0;
+          t.y0 = (short)y0;
+          t.z0 = (short)z0;
+          t.nx = (short)std::min(TX, B.s[0] - x0);
+          t.ny = (short)std::min(TY, B.s[1] - y0);
+          t.nz = (short)std::min(TZ, B.s[2] - z0);
+          nat.push_back(t);
+        }
+  }
+  // XCD-aware order: workgroup w runs on XCD w % 8, so give XCD x the
+  // contiguous chunk x of the natural (block-major) order.
+  const int nx = 8;
+  const size_t chunk = (nat.size() + nx - 1) / nx;
+  c->tiles.assign(chunk * nx, TileDev{0, 0, 0, 0, 0, 0, 0});
+  for (size_t j = 0; j < nat.size(); ++j) {
+    const size_t x = j / chunk, pos = j % chunk;
+    c->tiles[pos * nx + x] = nat[j];
+  }
+}
+
+template <typename T>
+StageParams<T> base_params(const atns_ctx* c) {
+  StageParams<T> p{};
+  p.ring = (T*)c->ring;
+  p.blocks = c->d_blocks;
+  p.tiles = c->d_tiles;
+  p.delays = c->d_delays;
+  for (int d = 0; d < 3; ++d) {
+    p.n[d] = c->n[d];
+    p.inv12h[d] = 1.0 / (12.0 * c->h[d]);
+  }
+  p.field = c->field;
+  p.slot_stride = c->slot_stride;
+  p.D = c->D;
+  p.L = c->cfg.L;
+  p.H = c->H;
+  p.ndim = c->cfg.ndim;
+  p.gamma = c->cfg.gamma;
+  p.mach2_gamma = c->cfg.gamma * c->cfg.mach * c->cfg.mach;
+  if (c->cfg.physics == ATNS_NS) {
+    p.kappa = 1.0 / ((c->cfg.gamma - 1.0) * c->cfg.mach * c->cfg.mach * c->cfg.pr);
+    p.inv_re = 1.0 / c->cfg.re;
+  }
+  p.dt = c->dt;
+  return p;
+}
+
+hipError_t next_event(atns_ctx* c, hipEvent_t* ev) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    c->ev_pool.push_back(e);
+  }
+  *ev = c->ev_pool[c->ev_used++];
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_stage(atns_ctx* c, const StageParams<T>& p, int kind) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profiling) {
+    hipError_t r = next_event(c, &e0);
+    if (r == hipSuccess) r = next_event(c, &e1);
+    if (r == hipSuccess) r = hipEventRecord(e0, c->stream);
+    if (r != hipSuccess) return r;
+  }
+  hipError_t r = (c->cfg.physics == ATNS_NS)
+                     ? launch_ns_stage<T>(p, (int)c->tiles.size(), kind, c->stream)
+                     : launch_euler_stage<T>(p, (int)c->tiles.size(), kind, c->stream);
+  if (r == hipSuccess && c->profiling) r = hipEventRecord(e1, c->stream);
+  return r;
+}
+
+bool is_async(const atns_ctx* c, int64_t step) { return c->cfg.mode != ATNS_SA && step >= kC; }
+
+atns_status draw_delays(atns_ctx* c, int64_t step, int8_t* dst) {
+  const int8_t* inj = nullptr;
+  if (c->inject_n > 0 && step >= c->inject0 && step < c->inject0 + c->inject_n)
+    inj = c->d_inject + (size_t)(step - c->inject0) * c->nb * kNumSlots;
+  HIP_TRY(c, launch_delays(dst, inj, step, c->nb, c->cfg.L, c->cfg.seed, c->cfg.algo, c->stream));
+  return ATNS_OK;
+}
+
+template <typename T>
+atns_status do_steps(atns_ctx* c, int nsteps) {
+  const RKScheme& rk = c->rk;
+  const int L = c->cfg.L;
+  for (int it = 0; it < nsteps; ++it) {
+    const bool async = is_async(c, c->step);
+    if (async) {
+      atns_status st = draw_delays(c, c->step, c->d_delays);
+      if (st != ATNS_OK) return st;
+    }
+    StageParams<T> p = base_params<T>(c);
+    p.halo = !async ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
+    p.slot_now = c->D ? (int)(c->step % c->D) : 0;
+    for (int e = 0; e < rk.stages; ++e) {
+      p.W = c->d_W ? c->d_W + (size_t)e * L * kC : nullptr;
+      p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
+      int kind;
+      if (!rk.low_storage) {
+        T* U = (T*)c->X[0];
+        T* Ya = (T*)c->X[1];
+        T* Yb = (T*)c->X[2];
+        p.U0 = U;
+        p.acc = (T*)c->X[3];
+        const T* ins[4] = {U, Ya, Yb, Ya};
+        T* outs[4] = {Ya, Yb, Ya, U};
+        p.Y = ins[e];
+        p.Yout = outs[e];
+        kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
+        p.cA = rk.b[e];
+        p.cB = e < 3 ? rk.a[e + 1][e] : 0.0;
+      } else {
+        p.Y = (const T*)c->X[c->cur];
+        p.Yout = (T*)c->X[1 - c->cur];
+        p.acc = (T*)c->X[3];
+        kind = e == 0 ? kLSFirst : kLSMid;
+        p.cA = rk.A[e];
+        p.cB = rk.B[e];
+      }
+      HIP_TRY(c, launch_stage<T>(c, p, kind));
+      if (rk.low_storage) c->cur = 1 - c->cur;
+    }
+    c->step += 1;
+  }
+  return ATNS_OK;
+}
+
+void* state_ptr(const atns_ctx* c) { return c->rk.low_storage ? c->X[c->cur] : c->X[0]; }
+
+void release(atns_ctx* c) {
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  c->ev_pool.clear();
+  for (void*& x : c->X)
+    if (x) {
+      (void)hipFree(x);
+      x = nullptr;
+    }
+  void* ptrs[] = {c->ring, c->d_blocks, c->d_tiles, c->d_delays, c->d_probe,
+                  c->d_inject, c->d_W, c->d_partials, c->d_diag};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  c->ring = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* atns_version(void) { return "atns 0.1 gfx950"; }
+
+const char* atns_last_error(const atns_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
+  if (!out) return fail(nullptr, ATNS_EINVAL, "null output pointer");
+  *out = nullptr;
+  auto* c = new atns_ctx();
+  std::vector<int> split[3];
+  atns_status st = validate(cfg, split, c);
+  if (st != ATNS_OK) {
+    delete c;
+    return st;
+  }
+  c->cfg = *cfg;
+  for (int d = 0; d < 3; ++d) {
+    c->split[d] = split[d];
+    c->cfg.split[d] = nullptr;
+    c->n[d] = cfg->n[d];
+    c->h[d] = cfg->len[d] / cfg->n[d];
+  }
+  c->stream = (hipStream_t)stream;
+  c->H = cfg->physics == ATNS_NS ? 4 : 2;
+  c->rk = make_rk(cfg->rk);
+  c->esz = cfg->precision == ATNS_F64 ? 8 : 4;
+  c->field = (long long)c->n[0] * c->n[1] * c->n[2];
+  build_layout(c);
+  build_tiles(c, 16, 16, 16);
+  c->D = cfg->mode == ATNS_SA ? 0 : kC + cfg->L;
+
+  auto fail_free = [&](atns_status s, const std::string& m) {
+    release(c);
+    g_err = m;
+    delete c;
+    return s;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return fail_free(ATNS_EHIP, "no HIP device");
+  const size_t fbytes = (size_t)c->field * 5 * c->esz;
+  for (int i = 0; i < 4; ++i)
+    if (hipMalloc(&c->X[i], fbytes) != hipSuccess) return fail_free(ATNS_ENOMEM, "state allocation failed");
+  if (c->D) {
+    if (hipMalloc(&c->ring, (size_t)c->slot_stride * c->D * c->esz) != hipSuccess)
+      return fail_free(ATNS_ENOMEM, "ring allocation failed");
+    const std::vector<double> W = halo_weights(cfg->rk, cfg->mode == ATNS_AS ? ATNS_AS : ATNS_AT, cfg->L);
+    if (hipMalloc((void**)&c->d_W, W.size() * sizeof(double)) != hipSuccess ||
+        hipMemcpy(c->d_W, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return fail_free(ATNS_EHIP, "weight table upload failed");
+  }
+  const size_t dcount = (size_t)c->nb * kNumSlots;
+  if (hipMalloc((void**)&c->d_blocks, c->blocks.size() * sizeof(BlockDev)) != hipSuccess ||
+      hipMalloc((void**)&c->d_tiles, c->tiles.size() * sizeof(TileDev)) != hipSuccess ||
+      hipMalloc((void**)&c->d_delays, dcount) != hipSuccess || hipMalloc((void**)&c->d_probe, dcount) != hipSuccess ||
+      hipMalloc((void**)&c->d_partials, (size_t)c->nparts * 7 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&c->d_diag, 7 * sizeof(double)) != hipSuccess)
+    return fail_free(ATNS_ENOMEM, "table allocation failed");
+  if (hipMemcpy(c->d_blocks, c->blocks.data(), c->blocks.size() * sizeof(BlockDev), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(c->d_tiles, c->tiles.data(), c->tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemset(c->d_delays, 0, dcount) != hipSuccess)
+    return fail_free(ATNS_EHIP, "table upload failed");
+  *out = c;
+  return ATNS_OK;
+}
+
+atns_status atns_destroy(atns_ctx* ctx) {
+  if (!ctx) return ATNS_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  release(ctx);
+  delete ctx;
+  return ATNS_OK;
+}
+
+atns_status atns_set_state(atns_ctx* c, const void* dev_U, int64_t step) {
+  if (!c || !dev_U) return fail(c, ATNS_EINVAL, "null argument");
+  if (step < 0) return fail(c, ATNS_EINVAL, "negative step");
+  void* dst = state_ptr(c);
+  HIP_TRY(c, hipMemcpyAsync(dst, dev_U, (size_t)c->field * 5 * c->esz, hipMemcpyDeviceToDevice, c->stream));
+  c->step = step;
+  c->state_set = true;
+  if (c->ring) {
+    const int slot = (int)(step % c->D);
+    if (c->esz == 4) {
+      StageParams<float> p = base_params<float>(c);
+      HIP_TRY(c, launch_ring_fill<float>(p, (const float*)dst, slot, c->nb, c->stream));
+    } else {
+      StageParams<double> p = base_params<double>(c);
+      HIP_TRY(c, launch_ring_fill<double>(p, (const double*)dst, slot, c->nb, c->stream));
+    }
+  }
+  return ATNS_OK;
+}
+
+atns_status atns_get_state(const atns_ctx* c, void* dst, int32_t on_host) {
+  if (!c || !dst) return fail(const_cast<atns_ctx*>(c), ATNS_EINVAL, "null argument");
+  atns_ctx* m = const_cast<atns_ctx*>(c);
+  const size_t bytes = (size_t)c->field * 5 * c->esz;
+  if (on_host) {
+    HIP_TRY(m, hipMemcpyAsync(dst, state_ptr(c), bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(m, hipStreamSynchronize(c->stream));
+  } else {
+    HIP_TRY(m, hipMemcpyAsync(dst, state_ptr(c), bytes, hipMemcpyDeviceToDevice, c->stream));
+  }
+  return ATNS_OK;
+}
+
+atns_status atns_get_step(const atns_ctx* c, int64_t* step) {
+  if (!c || !step) return fail(const_cast<atns_ctx*>(c), ATNS_EINVAL, "null argument");
+  *step = c->step;
+  return ATNS_OK;
+}
+
+atns_status atns_set_dt(atns_ctx* c, double dt) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(c, ATNS_EINVAL, "dt must be positive and finite");
+  c->dt = dt;
+  return ATNS_OK;
+}
+
+atns_status atns_set_delays(atns_ctx* c, int64_t step0, int32_t nsteps, const int8_t* host_k) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  if (nsteps < 0 || (nsteps > 0 && !host_k)) return fail(c, ATNS_EINVAL, "bad delay injection");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->d_inject) {
+    HIP_TRY(c, hipFree(c->d_inject));
+    c->d_inject = nullptr;
+  }
+  c->inject_n = 0;
+  if (nsteps == 0) return ATNS_OK;
+  const size_t bytes = (size_t)nsteps * c->nb * kNumSlots;
+  if (hipMalloc((void**)&c->d_inject, bytes) != hipSuccess) return fail(c, ATNS_ENOMEM, "inject allocation");
+  HIP_TRY(c, hipMemcpy(c->d_inject, host_k, bytes, hipMemcpyHostToDevice));
+  c->inject0 = step0;
+  c->inject_n = nsteps;
+  return ATNS_OK;
+}
+
+atns_status atns_get_delays(atns_ctx* c, int64_t step, int8_t* host_k, int32_t* synchronous) {
+  if (!c || !host_k) return fail(c, ATNS_EINVAL, "null argument");
+  const size_t cnt = (size_t)c->nb * kNumSlots;
+  if (!is_async(c, step)) {
+    std::memset(host_k, 0, cnt);
+    if (synchronous) *synchronous = 1;
+    return ATNS_OK;
+  }
+  atns_status st = draw_delays(c, step, c->d_probe);
+  if (st != ATNS_OK) return st;
+  HIP_TRY(c, hipMemcpyAsync(host_k, c->d_probe, cnt, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (synchronous) *synchronous = 0;
+  return ATNS_OK;
+}
+
+atns_status atns_rhs(atns_ctx* c, void* dev_R) {
+  if (!c || !dev_R) return fail(c, ATNS_EINVAL, "null argument");
+  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+  const bool async = is_async(c, c->step);
+  if (async) {
+    atns_status st = draw_delays(c, c->step, c->d_delays);
+    if (st != ATNS_OK) return st;
+  }
+  auto go = [&](auto tag) -> atns_status {
+    using T = decltype(tag);
+    StageParams<T> p = base_params<T>(c);
+    p.halo = !async ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
+    p.slot_now = c->D ? (int)(c->step % c->D) : 0;
+    p.W = c->d_W;
+    p.ring_write = 0;
+    p.Y = (const T*)state_ptr(c);
+    p.Yout = (T*)dev_R;
+    HIP_TRY(c, launch_stage<T>(c, p, kRhsOnly));
+    return ATNS_OK;
+  };
+  return c->esz == 4 ? go(float{}) : go(double{});
+}
+
+atns_status atns_rk_step(atns_ctx* c, int32_t nsteps) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  if (nsteps < 0) return fail(c, ATNS_EINVAL, "negative step count");
+  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+  if (!(c->dt > 0)) return fail(c, ATNS_ESTATE, "dt not set");
+  return c->esz == 4 ? do_steps<float>(c, nsteps) : do_steps<double>(c, nsteps);
+}
+
+atns_status atns_reduce(atns_ctx* c, double* host_out) {
+  if (!c || !host_out) return fail(c, ATNS_EINVAL, "null argument");
+  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+  double inv12h[3];
+  for (int d = 0; d < 3; ++d) inv12h[d] = 1.0 / (12.0 * c->h[d]);
+  const double dV = c->h[0] * c->h[1] * (c->cfg.ndim == 3 ? c->h[2] : c->cfg.len[2]);
+  if (c->esz == 4) {
+    HIP_TRY(c, launch_diag<float>((const float*)state_ptr(c), c->n, c->cfg.ndim, inv12h, dV, c->d_partials,
+                                  c->nparts, c->d_diag, c->stream));
+  } else {
+    HIP_TRY(c, launch_diag<double>((const double*)state_ptr(c), c->n, c->cfg.ndim, inv12h, dV, c->d_partials,
+                                   c->nparts, c->d_diag, c->stream));
+  }
+  HIP_TRY(c, hipMemcpyAsync(host_out, c->d_diag, 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 7; ++i)
+    if (!std::isfinite(host_out[i])) return fail(c, ATNS_ENONFINITE, "non-finite diagnostic");
+  return ATNS_OK;
+}
+
+atns_status atns_get_layout(const atns_ctx* c, int32_t* nblocks, int32_t* ring_depth) {
+  if (!c) return fail(nullptr, ATNS_EINVAL, "null context");
+  if (nblocks) *nblocks = c->nb;
+  if (ring_depth) *ring_depth = c->D;
+  return ATNS_OK;
+}
+
+atns_status atns_profile_enable(atns_ctx* c, int32_t on) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->profiling = on != 0;
+  c->ev_used = 0;
+  return ATNS_OK;
+}
+
+atns_status atns_profile_read(atns_ctx* c, int64_t* launches, double* total_ms) {
+  if (!c || !launches || !total_ms) return fail(c, ATNS_EINVAL, "null argument");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]));
+    tot += ms;
+  }
+  *launches = (int64_t)(c->ev_used / 2);
+  *total_ms = tot;
+  c->ev_used = 0;
+  return ATNS_OK;
+}
+
+atns_status atns_host_weights(int32_t rk, int32_t mode, int32_t L, double* out) {
+  if (!out || L < 1 || L > 16 || (rk != ATNS_RK4 && rk != ATNS_LSERK4) || (mode != ATNS_AT && mode != ATNS_AS))
+    return fail(nullptr, ATNS_EINVAL, "bad weight-table request");
+  const std::vector<double> W = halo_weights(rk, mode, L);
+  std::memcpy(out, W.data(), W.size() * sizeof(double));
+  return ATNS_OK;
+}
+
+atns_status atns_host_delays(int32_t algo, int64_t n, int32_t nblocks, int32_t L, uint64_t seed, int8_t* out,
+                             int32_t* synchronous) {
+  if (!out || nblocks < 1 || L < 1 || L > 16 || (algo != ATNS_CAA && algo != ATNS_SAA) || n < 0)
+    return fail(nullptr, ATNS_EINVAL, "bad delay request");
+  const bool async = step_delays(algo, n, nblocks, L, seed, nullptr, out);
+  if (synchronous) *synchronous = async ? 0 : 1;
+  return ATNS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,36 @@
+// Host-side tables of the AT method: RK coefficients, per-stage halo
+// weights and the delay schedules.  Plain C++, no device code.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace atns {
+
+constexpr int kC = 5;          // AT4: C = 5 delayed levels, (d, q, r) = (1, 4, 1)
+constexpr int kSlots = 18;     // 6 faces + 12 edges
+
+struct RKScheme {
+  int stages;                  // s
+  // Classical RK4: stage e input Y_e = U + dt * sum_{j<e} a[e][j] k_j,
+  // U^{n+1} = U + dt * sum b_j k_j.  LSERK (Eq. 3): A[m], B[m], m = 0..s-1.
+  double a[5][5];
+  double b[5];
+  double A[5];
+  double B[5];
+  bool low_storage;
+};
+
+RKScheme make_rk(int rk);      // rk: ATNS_RK4 or ATNS_LSERK4
+
+// W[e][k][l], e < s, k < L, l < kC.  mode: ATNS_AT or ATNS_AS.
+std::vector<double> halo_weights(int rk, int mode, int L);
+
+// SplitMix64 draw i of stream `seed`.
+uint64_t splitmix64(uint64_t seed, uint64_t i);
+
+// Delays of step n after the Alg. 3 guard (override may be null).
+// Returns false (and zeros) for a synchronous step (n < kC).
+bool step_delays(int algo, int64_t n, int nblocks, int L, uint64_t seed,
+                 const int8_t* override_k, int8_t* out);
+
+}  // namespace atns

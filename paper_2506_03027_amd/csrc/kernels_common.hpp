@@ -1,0 +1,154 @@
+// Device helpers shared by the stage kernels: halo-aware point fetch, the
+// ring write and the RK epilogues.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "layout.hpp"
+
+namespace atns {
+
+constexpr int kLevels = 5;  // AT4: C = 5
+
+__device__ __forceinline__ int wrap(int g, int n) {
+  g += (g < 0) ? n : 0;
+  g -= (g >= n) ? n : 0;
+  return g;
+}
+
+// Conserved variables at block-local point (lx, ly, lz) of block B as seen by
+// that block in the current stage:
+//  * owned points, and every point under synchronous halos: the stage field
+//    Y at the periodic global position;
+//  * halo points (outside the block): for stale halos (AS) the ring level
+//    n-k; for AT the FP64 combination sum_l W[k][l] ring[n-k-l], rounded to T.
+// k is the delay the block sees from the neighbour owning the point.
+template <typename T>
+__device__ __forceinline__ void fetch(const StageParams<T>& p, const BlockDev* __restrict__ B,
+                                      int blk, int lx, int ly, int lz, T u[5]) {
+  const int sx = (lx < 0) ? -1 : (lx >= B->s[0] ? 1 : 0);
+  const int sy = (ly < 0) ? -1 : (ly >= B->s[1] ? 1 : 0);
+  const int sz = (lz < 0) ? -1 : (lz >= B->s[2] ? 1 : 0);
+  if (((sx | sy | sz) == 0) || p.halo == kHaloSync) {
+    const int gx = wrap(B->o[0] + lx, p.n[0]);
+    const int gy = wrap(B->o[1] + ly, p.n[1]);
+    const int gz = wrap(B->o[2] + lz, p.n[2]);
+    const long long g = ((long long)gz * p.n[1] + gy) * p.n[0] + gx;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = p.Y[v * p.field + g];
+    return;
+  }
+  const int s = slot_index(sx, sy, sz);
+  const BlockDev* Bn = p.blocks + B->nbr[s];
+  const long long base = Bn->lay[slot_opposite(s)];
+  const int dep = ((sx != 0) + (sy != 0) + (sz != 0) == 1) ? p.H : 2;
+  const int ix = sx < 0 ? lx + dep : (sx > 0 ? lx - B->s[0] : lx);
+  const int iy = sy < 0 ? ly + dep : (sy > 0 ? ly - B->s[1] : ly);
+  const int iz = sz < 0 ? lz + dep : (sz > 0 ? lz - B->s[2] : lz);
+  const int ex = sx ? dep : B->s[0];
+  const int ey = sy ? dep : B->s[1];
+  const int ez = sz ? dep : B->s[2];
+  const long long li = ((long long)iz * ey + iy) * ex + ix;
+  const long long vs = (long long)ex * ey * ez;
+  const int k = p.delays[blk * kNumSlots + s];
+  if (p.halo == kHaloStale) {
+    int sl = p.slot_now - k;
+    sl += (sl < 0) ? p.D : 0;
+    const T* r = p.ring + (long long)sl * p.slot_stride + base + li;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = r[v * vs];
+    return;
+  }
+  double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const double* w = p.W + k * kLevels;
+#pragma unroll
+  for (int l = 0; l < kLevels; ++l) {
+    int sl = p.slot_now - k - l;
+    sl += (sl < 0) ? p.D : 0;
+    const T* r = p.ring + (long long)sl * p.slot_stride + base + li;
+    const double wl = w[l];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) a[v] = fma(wl, (double)r[v * vs], a[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u[v] = (T)a[v];
+}
+
+// Write the values of owned point (lx, ly, lz) into every boundary layer of
+// block B that contains it, in ring slot `slot`.
+template <typename T>
+__device__ __forceinline__ void ring_store(const StageParams<T>& p, const BlockDev* __restrict__ B,
+                                           int lx, int ly, int lz, const T u[5], T* slot) {
+  const int l[3] = {lx, ly, lz};
+  const int ns = (p.H == 4) ? kNumSlots : 6;
+  for (int s = 0; s < ns; ++s) {
+    const long long off = B->lay[s];
+    if (off < 0) continue;
+    int d[3];
+    slot_dir(s, d);
+    const int dep = (s < 6) ? p.H : 2;
+    int idx[3], ext[3];
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (d[a] == 0) {
+        idx[a] = l[a];
+        ext[a] = B->s[a];
+      } else if (d[a] > 0) {
+        idx[a] = l[a] - (B->s[a] - dep);
+        ext[a] = dep;
+        in = in && idx[a] >= 0;
+      } else {
+        idx[a] = l[a];
+        ext[a] = dep;
+        in = in && l[a] < dep;
+      }
+    }
+    if (!in) continue;
+    const long long li = ((long long)idx[2] * ext[1] + idx[1]) * ext[0] + idx[0];
+    const long long vs = (long long)ext[0] * ext[1] * ext[2];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) slot[off + li + v * vs] = u[v];
+  }
+}
+
+// RK epilogue at global index g; Y is the stage input at the point, R the
+// right-hand side.  Returns the written next value in out[] (for the ring).
+template <typename T, int KIND>
+__device__ __forceinline__ void epilogue(const StageParams<T>& p, long long g, const T Y[5],
+                                         const T R[5], T out[5]) {
+  const T dt = (T)p.dt, cA = (T)p.cA, cB = (T)p.cB;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const long long i = v * p.field + g;
+    const T r = R[v];
+    if (KIND == kRhsOnly) {
+      out[v] = r;
+      p.Yout[i] = r;
+    } else if (KIND == kRK4First) {
+      const T dr = dt * r;
+      p.acc[i] = Y[v] + cA * dr;
+      out[v] = Y[v] + cB * dr;
+      p.Yout[i] = out[v];
+    } else if (KIND == kRK4Mid) {
+      const T dr = dt * r;
+      p.acc[i] = p.acc[i] + cA * dr;
+      out[v] = p.U0[i] + cB * dr;
+      p.Yout[i] = out[v];
+    } else if (KIND == kRK4Last) {
+      out[v] = p.acc[i] + cA * (dt * r);
+      p.Yout[i] = out[v];
+    } else if (KIND == kLSFirst) {
+      const T q = dt * r;
+      p.acc[i] = q;
+      out[v] = Y[v] + cB * q;
+      p.Yout[i] = out[v];
+    } else {  // kLSMid
+      const T q = cA * p.acc[i] + dt * r;
+      p.acc[i] = q;
+      out[v] = Y[v] + cB * q;
+      p.Yout[i] = out[v];
+    }
+  }
+}
+
+}  // namespace atns

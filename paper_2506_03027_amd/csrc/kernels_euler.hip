@@ -1,0 +1,164 @@
+// Fused Euler right-hand side + RK stage kernel.
+//
+// R = -(D_x F + D_y G + D_z H) with the explicit CD4 derivative
+// (Eq. 2 with a = 4/3, b = -1/3: D phi_i = [8(phi_{i+1} - phi_{i-1})
+// - (phi_{i+2} - phi_{i-2})] / (12 h)) of the inviscid fluxes of App. A on a
+// Cartesian grid, followed in the same kernel by the RK update of the stage
+// (Eq. 3 / classical RK4) and, in the last stage, by the write of the new
+// boundary layers into the delayed-level ring.
+//
+// Work decomposition (2.5D): a workgroup owns a TX x TY column tile of one
+// block and walks it along z.  Each thread keeps the five z-levels
+// z-2..z+2 of its column in registers; the x- and y-fluxes of the current
+// plane (tile plus a 2-point apron) are staged in LDS, double-buffered so one
+// barrier per plane suffices.  Points outside the block -- the apron at a
+// block face and the z-levels beyond it -- come from fetch(), which applies
+// the halo rule of the stage (synchronous, stale, or AT-weighted levels).
+#include "kernels_common.hpp"
+
+namespace atns {
+
+template <typename T>
+__device__ __forceinline__ void euler_prims(const T u[5], T gm1, T& iv_rho, T& p) {
+  iv_rho = T(1) / u[0];
+  const T ke = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * iv_rho;
+  p = gm1 * (u[4] - ke);
+}
+
+// Inviscid flux along direction d (0, 1, 2) of conserved state u.
+template <typename T>
+__device__ __forceinline__ void euler_flux(const T u[5], int d, T gm1, T f[5]) {
+  T ir, p;
+  euler_prims(u, gm1, ir, p);
+  const T vel = u[1 + d] * ir;
+  f[0] = u[1 + d];
+  f[1] = u[1] * vel;
+  f[2] = u[2] * vel;
+  f[3] = u[3] * vel;
+  f[1 + d] += p;
+  f[4] = (u[4] + p) * vel;
+}
+
+template <typename T, int TX, int TY, int KIND>
+__global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T> p) {
+  const TileDev t = p.tiles[blockIdx.x];
+  if (t.nx == 0) return;
+  const BlockDev* __restrict__ B = p.blocks + t.blk;
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const bool act = (tx < t.nx) && (ty < t.ny);
+  const int lx = t.x0 + tx, ly = t.y0 + ty;
+  const bool three = (p.ndim == 3);
+  const T gm1 = (T)(p.gamma - 1.0);
+  const T ihx = (T)p.inv12h[0], ihy = (T)p.inv12h[1], ihz = (T)p.inv12h[2];
+
+  __shared__ T sF[2][5][TY][TX + 4];
+  __shared__ T sG[2][5][TY + 4][TX];
+
+  // Apron role: x-apron columns {-2,-1,nx,nx+1} x ny rows, then the y-apron.
+  const int nxa = 4 * t.ny, nya = 4 * t.nx;
+  int arole = 0, ax = 0, ay = 0;
+  if (tid < nxa) {
+    const int code = tid / t.ny;
+    ay = tid % t.ny;
+    ax = (code < 2) ? code - 2 : t.nx + code - 2;
+    arole = 1;
+  } else if (tid < nxa + nya) {
+    const int b = tid - nxa;
+    const int code = b / t.nx;
+    ax = b % t.nx;
+    ay = (code < 2) ? code - 2 : t.ny + code - 2;
+    arole = 2;
+  }
+
+  T q[5][5];
+  if (act && three) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) fetch(p, B, t.blk, lx, ly, t.z0 - 2 + j, q[j + 1]);
+  }
+
+  T* ring_slot = nullptr;
+  if (p.ring_write) ring_slot = p.ring + (long long)((p.slot_now + 1) % p.D) * p.slot_stride;
+
+  for (int iz = 0; iz < t.nz; ++iz) {
+    const int lz = t.z0 + iz;
+    const int buf = iz & 1;
+    if (act) {
+      if (three) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 5; ++v) q[j][v] = q[j + 1][v];
+        fetch(p, B, t.blk, lx, ly, lz + 2, q[4]);
+      } else {
+        fetch(p, B, t.blk, lx, ly, lz, q[2]);
+      }
+      T f[5];
+      euler_flux(q[2], 0, gm1, f);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sF[buf][v][ty][tx + 2] = f[v];
+      euler_flux(q[2], 1, gm1, f);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sG[buf][v][ty + 2][tx] = f[v];
+    }
+    if (arole) {
+      T u[5], f[5];
+      fetch(p, B, t.blk, t.x0 + ax, t.y0 + ay, lz, u);
+      if (arole == 1) {
+        euler_flux(u, 0, gm1, f);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sF[buf][v][ay][ax + 2] = f[v];
+      } else {
+        euler_flux(u, 1, gm1, f);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sG[buf][v][ay + 2][ax] = f[v];
+      }
+    }
+    __syncthreads();
+    if (act) {
+      T R[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const T dx = (T(8) * (sF[buf][v][ty][tx + 3] - sF[buf][v][ty][tx + 1]) -
+                      (sF[buf][v][ty][tx + 4] - sF[buf][v][ty][tx])) * ihx;
+        const T dy = (T(8) * (sG[buf][v][ty + 3][tx] - sG[buf][v][ty + 1][tx]) -
+                      (sG[buf][v][ty + 4][tx] - sG[buf][v][ty][tx])) * ihy;
+        R[v] = -(dx + dy);
+      }
+      if (three) {
+        T h0[5], h1[5], h3[5], h4[5];
+        euler_flux(q[0], 2, gm1, h0);
+        euler_flux(q[1], 2, gm1, h1);
+        euler_flux(q[3], 2, gm1, h3);
+        euler_flux(q[4], 2, gm1, h4);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) R[v] -= (T(8) * (h3[v] - h1[v]) - (h4[v] - h0[v])) * ihz;
+      }
+      const int gx = B->o[0] + lx, gy = B->o[1] + ly, gz = B->o[2] + lz;
+      const long long g = ((long long)gz * p.n[1] + gy) * p.n[0] + gx;
+      T out[5];
+      epilogue<T, KIND>(p, g, q[2], R, out);
+      if (ring_slot) ring_store(p, B, lx, ly, lz, out, ring_slot);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_euler_stage(const StageParams<T>& p, int ntiles, int kind, hipStream_t s) {
+  constexpr int TX = 16, TY = 16;
+  dim3 grid(ntiles), block(TX * TY);
+  switch (kind) {
+    case kRhsOnly: euler_stage_kernel<T, TX, TY, kRhsOnly><<<grid, block, 0, s>>>(p); break;
+    case kRK4First: euler_stage_kernel<T, TX, TY, kRK4First><<<grid, block, 0, s>>>(p); break;
+    case kRK4Mid: euler_stage_kernel<T, TX, TY, kRK4Mid><<<grid, block, 0, s>>>(p); break;
+    case kRK4Last: euler_stage_kernel<T, TX, TY, kRK4Last><<<grid, block, 0, s>>>(p); break;
+    case kLSFirst: euler_stage_kernel<T, TX, TY, kLSFirst><<<grid, block, 0, s>>>(p); break;
+    default: euler_stage_kernel<T, TX, TY, kLSMid><<<grid, block, 0, s>>>(p); break;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_euler_stage<float>(const StageParams<float>&, int, int, hipStream_t);
+template hipError_t launch_euler_stage<double>(const StageParams<double>&, int, int, hipStream_t);
+
+}  // namespace atns

@@ -1,0 +1,175 @@
+// Small kernels: the per-step delay draw, the ring fill of a given state, and
+// the FP64 diagnostics (conserved totals, kinetic energy, enstrophy).
+#include "kernels_common.hpp"
+
+namespace atns {
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output i of the stream
+// seeded with `seed` is mix(seed + (i + 1) * golden).
+__device__ __forceinline__ unsigned long long sm64(unsigned long long seed, unsigned long long i) {
+  unsigned long long z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Delays of step n (n >= C) for every (block, slot): CAA (n - C) mod L,
+// SAA SplitMix64 draw mod L, or the injected value; then the Alg. 3 guard.
+__global__ void delays_kernel(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
+                              unsigned long long seed, int algo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nblocks * kNumSlots) return;
+  long long k;
+  if (inject) {
+    k = inject[i];
+  } else if (algo == 0) {
+    k = (n - kLevels) % L;
+  } else {
+    const unsigned long long draw = (unsigned long long)n * (unsigned long long)nblocks * kNumSlots + i;
+    k = (long long)(sm64(seed, draw) % (unsigned long long)L);
+  }
+  if (k < 0 || k > L - 1 || k > n - kLevels + 1) k = 0;
+  out[i] = (int8_t)k;
+}
+
+hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
+                         unsigned long long seed, int algo, hipStream_t s) {
+  const int cnt = nblocks * kNumSlots;
+  delays_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(out, inject, n, nblocks, L, seed, algo);
+  return hipGetLastError();
+}
+
+// Copy the boundary layers of every block of field U into ring slot `slot`.
+template <typename T>
+__global__ void ring_fill_kernel(const StageParams<T> p, const T* U, int slot) {
+  const int b = blockIdx.y;
+  const BlockDev* B = p.blocks + b;
+  const long long cnt = (long long)B->s[0] * B->s[1] * B->s[2];
+  T* dst = p.ring + (long long)slot * p.slot_stride;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int lx = (int)(i % B->s[0]);
+    const int ly = (int)((i / B->s[0]) % B->s[1]);
+    const int lz = (int)(i / ((long long)B->s[0] * B->s[1]));
+    const long long g = ((long long)(B->o[2] + lz) * p.n[1] + (B->o[1] + ly)) * p.n[0] + (B->o[0] + lx);
+    T u[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = U[v * p.field + g];
+    ring_store(p, B, lx, ly, lz, u, dst);
+  }
+}
+
+template <typename T>
+hipError_t launch_ring_fill(const StageParams<T>& p, const T* U, int slot, int nblocks, hipStream_t s) {
+  dim3 grid(64, nblocks), block(256);
+  ring_fill_kernel<T><<<grid, block, 0, s>>>(p, U, slot);
+  return hipGetLastError();
+}
+template hipError_t launch_ring_fill<float>(const StageParams<float>&, const float*, int, int, hipStream_t);
+template hipError_t launch_ring_fill<double>(const StageParams<double>&, const double*, int, int, hipStream_t);
+
+// ----------------------------------------------------------------- diagnostics
+// Per-workgroup FP64 partial sums of: the five conserved variables, rho|u|^2
+// and rho|w|^2 with w = curl u by CD4 on the periodic global field.
+constexpr int kDiagThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ void vel_at(const T* U, long long field, long long g, double vel[3]) {
+  const double ir = 1.0 / (double)U[g];
+  vel[0] = (double)U[field + g] * ir;
+  vel[1] = (double)U[2 * field + g] * ir;
+  vel[2] = (double)U[3 * field + g] * ir;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kDiagThreads)
+    diag_partial_kernel(const T* U, int nx, int ny, int nz, int ndim, double ihx, double ihy,
+                        double ihz, double* partials) {
+  const long long field = (long long)nx * ny * nz;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < field;
+       g += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(g % nx);
+    const int y = (int)((g / nx) % ny);
+    const int z = (int)(g / ((long long)nx * ny));
+    double u[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = (double)U[v * field + g];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[v] += u[v];
+    acc[5] += (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+    // CD4 velocity derivatives along each direction: dv[d][c] = d u_c / d x_d
+    double dv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    const int nd = (ndim == 3) ? 3 : 2;
+    for (int d = 0; d < nd; ++d) {
+      const int n = (d == 0) ? nx : (d == 1 ? ny : nz);
+      const long long st = (d == 0) ? 1 : (d == 1 ? (long long)nx : (long long)nx * ny);
+      const int c = (d == 0) ? x : (d == 1 ? y : z);
+      const double ih = (d == 0) ? ihx : (d == 1 ? ihy : ihz);
+      double vm2[3], vm1[3], vp1[3], vp2[3];
+      vel_at(U, field, g + (wrap(c - 2, n) - c) * st, vm2);
+      vel_at(U, field, g + (wrap(c - 1, n) - c) * st, vm1);
+      vel_at(U, field, g + (wrap(c + 1, n) - c) * st, vp1);
+      vel_at(U, field, g + (wrap(c + 2, n) - c) * st, vp2);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dv[d][k] = (8.0 * (vp1[k] - vm1[k]) - (vp2[k] - vm2[k])) * ih;
+    }
+    const double wx = dv[1][2] - dv[2][1];
+    const double wy = dv[2][0] - dv[0][2];
+    const double wz = dv[0][1] - dv[1][0];
+    acc[6] += u[0] * (wx * wx + wy * wy + wz * wz);
+  }
+  // workgroup reduction in a fixed order
+  __shared__ double red[7][kDiagThreads];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) red[i][threadIdx.x] = acc[i];
+  __syncthreads();
+  for (int w = kDiagThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 7) partials[blockIdx.x * 7 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kDiagThreads)
+    diag_final_kernel(const double* partials, int nparts, double dV, double inv_npts, double* out) {
+  __shared__ double red[7][kDiagThreads];
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < 7; ++i) acc[i] += partials[b * 7 + i];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) red[i][threadIdx.x] = acc[i];
+  __syncthreads();
+  for (int w = kDiagThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0] * dV;
+  if (threadIdx.x == 5) out[5] = 0.5 * red[5][0] * inv_npts;
+  if (threadIdx.x == 6) out[6] = 0.5 * red[6][0] * inv_npts;
+}
+
+template <typename T>
+hipError_t launch_diag(const T* U, const int n[3], int ndim, const double inv12h[3], double dV,
+                       double* partials, int nparts, double* out, hipStream_t s) {
+  diag_partial_kernel<T><<<nparts, kDiagThreads, 0, s>>>(U, n[0], n[1], n[2], ndim, inv12h[0],
+                                                         inv12h[1], inv12h[2], partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const double npts = (double)n[0] * n[1] * n[2];
+  diag_final_kernel<<<1, kDiagThreads, 0, s>>>(partials, nparts, dV, 1.0 / npts, out);
+  return hipGetLastError();
+}
+template hipError_t launch_diag<float>(const float*, const int*, int, const double*, double, double*, int,
+                                       double*, hipStream_t);
+template hipError_t launch_diag<double>(const double*, const int*, int, const double*, double, double*, int,
+                                        double*, hipStream_t);
+
+}  // namespace atns

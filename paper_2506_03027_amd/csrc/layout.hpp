@@ -1,0 +1,108 @@
+// Data layout shared by the library's host code and its kernels.
+//
+// State: structure of arrays, [5][nz][ny][nx], x fastest.
+// Blocks: tensor-product index ranges of the global grid (the PEs).
+// Ring: D slots; slot m % D holds the boundary layers of U^m of every block.
+//   Within a slot, block b's layer for slot direction s (the points of b that
+//   the neighbour in direction s reads as its halo) starts at lay[b][s] and
+//   is stored [5][ez][ey][ex] with extent ed = depth where s has a nonzero
+//   component in d, else the block size.  Faces have depth H (2 Euler,
+//   4 Navier-Stokes), edges depth 2.  Readers find the values of their halo
+//   region s in the layer opposite(s) of neighbour nbr[b][s], so every halo
+//   read of a block face is one contiguous run.
+#pragma once
+#include <cstdint>
+
+namespace atns {
+
+constexpr int kNumSlots = 18;
+
+// Slot direction table (matches the slot numbering of atns.h).
+__host__ __device__ inline void slot_dir(int s, int d[3]) {
+  const signed char t[18][3] = {{-1, 0, 0}, {1, 0, 0},  {0, -1, 0},  {0, 1, 0},  {0, 0, -1}, {0, 0, 1},
+                                {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},  {1, 1, 0},  {-1, 0, -1}, {1, 0, -1},
+                                {-1, 0, 1}, {1, 0, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}, {0, 1, 1}};
+  d[0] = t[s][0];
+  d[1] = t[s][1];
+  d[2] = t[s][2];
+}
+
+// Slot index from per-axis signs (-1, 0, +1); -1 for the centre or a corner.
+__host__ __device__ inline int slot_index(int sx, int sy, int sz) {
+  const int nz = (sx != 0) + (sy != 0) + (sz != 0);
+  if (nz == 1) {
+    if (sx) return sx < 0 ? 0 : 1;
+    if (sy) return sy < 0 ? 2 : 3;
+    return sz < 0 ? 4 : 5;
+  }
+  if (nz == 2) {
+    if (sz == 0) return 6 + (sx > 0) + 2 * (sy > 0);
+    if (sy == 0) return 10 + (sx > 0) + 2 * (sz > 0);
+    return 14 + (sy > 0) + 2 * (sz > 0);
+  }
+  return -1;
+}
+
+__host__ __device__ inline int slot_opposite(int s) {
+  int d[3];
+  slot_dir(s, d);
+  return slot_index(-d[0], -d[1], -d[2]);
+}
+
+struct BlockDev {
+  int o[3];                 // origin (global index of local (0,0,0))
+  int s[3];                 // size
+  int nbr[kNumSlots];       // neighbour block in each slot direction
+  long long lay[kNumSlots]; // offset of this block's layer for slot s (-1: unused)
+};
+
+struct TileDev {
+  int blk;                  // block id
+  short x0, y0, z0;         // tile origin, block-local
+  short nx, ny, nz;         // tile extent (nx == 0: padding tile, no work)
+};
+
+// Stage epilogue kinds.
+enum StageKind {
+  kRhsOnly = 0,   // Yout = R
+  kRK4First = 1,  // acc = Y + cA dt R ; Yout = Y + cB dt R        (Y == U^n)
+  kRK4Mid = 2,    // acc += cA dt R    ; Yout = U0 + cB dt R
+  kRK4Last = 3,   // Yout = acc + cA dt R                          (Yout == U)
+  kLSFirst = 4,   // Q = dt R          ; Yout = Y + cB Q           (A_1 = 0)
+  kLSMid = 5      // Q = cA Q + dt R   ; Yout = Y + cB Q
+};
+
+enum HaloMode { kHaloSync = 0, kHaloStale = 1, kHaloAT = 2 };
+
+template <typename T>
+struct StageParams {
+  const T* Y;          // stage input, read with the stencil
+  const T* U0;         // RK4: U^n (pointwise)
+  T* Yout;             // next stage input / final state
+  T* acc;              // RK4 accumulator / LSERK Q register
+  T* ring;             // ring base
+  const BlockDev* blocks;
+  const TileDev* tiles;
+  const int8_t* delays;  // [nblocks][18] of this step
+  const double* W;       // this stage's weights [L][C]
+  int n[3];              // global sizes
+  long long field;       // nx*ny*nz, the variable stride
+  long long slot_stride; // elements per ring slot
+  int D;                 // ring depth
+  int slot_now;          // n % D
+  int halo;              // HaloMode for this stage
+  int L;
+  int H;                 // halo depth (faces)
+  int ndim;
+  double inv12h[3];      // 1 / (12 h_d)
+  double gamma;
+  double mach2_gamma;    // gamma * M^2          (T = gamma M^2 p / rho)
+  double kappa;          // 1/((gamma-1) M^2 Pr)
+  double inv_re;
+  double dt;
+  double cA;             // epilogue coefficients (see stage kinds)
+  double cB;
+  int ring_write;        // write the boundary layers of the result
+};
+
+}  // namespace atns

@@ -132,13 +132,13 @@ WORKLOADS = {
                         L=1, cfl=0.5, steps=200, precision="f64"),
     "vortex3d_128": dict(n=(128, 128, 128), length=(10.0, 10.0, 10.0), ndim=3,
                          nblk=(4, 4, 4), physics="euler", rk="rk4", mode="at",
-                         algo="saa", L=4, cfl=0.25, precision="f32"),
+                         algo="saa", L=4, cfl=0.02, precision="f32"),
     "tgv_256": dict(n=(256, 256, 256), length=(2 * math.pi,) * 3, ndim=3,
                     nblk=(16, 16, 8), physics="ns", rk="rk4", mode="at",
-                    algo="saa", L=4, re=1600.0, mach=0.1, cfl=0.25,
+                    algo="saa", L=4, re=1600.0, mach=0.1, cfl=0.02,
                     steps=2000, precision="f32"),
     "tgv_512": dict(n=(512, 512, 512), length=(2 * math.pi,) * 3, ndim=3,
                     nblk=(16, 16, 16), physics="ns", rk="rk4", mode="at",
-                    algo="saa", L=5, re=1600.0, mach=0.1, cfl=0.25,
+                    algo="saa", L=5, re=1600.0, mach=0.1, cfl=0.01,
                     precision="f32"),
 }

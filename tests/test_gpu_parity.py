@@ -1,0 +1,231 @@
+"""GPU parity of the HIP library (called through the C ABI) against the FP64
+oracle: right-hand side, delays, full RK steps in every halo mode, FP64
+diagnostics, and the 2D vortex workload."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import (EPS32, announce, flux_scale, need_gpu, pair, rel_l2, rel_max, set_both,
+                         to_np)
+from oracle import at as oat, diagnostics, delays as odl
+from paper_2506_03027_amd import atns, inputs
+
+pytestmark = pytest.mark.gpu
+
+BOX = (10.0, 10.0, 10.0)
+
+
+def f32(U):
+    return U.astype(np.float32).astype(np.float64)
+
+
+def rhs_tol(U, h, precision, wnorm=1.0):
+    """Bound on |R_gpu - R_oracle| from the arithmetic: every flux carries a
+    few ulps of rounding, CD4 sums 18/12 of them per direction over three
+    directions (x 2 margin -> 64 ulps of the largest flux / h).  FP64 AT
+    halos add the FP64 accumulation of the weighted levels (x ||W||_1)."""
+    eps = EPS32 if precision == "f32" else 2.0 ** -53
+    return 64 * eps * flux_scale(U) / min(h) * (wnorm if precision == "f64" else 1.0)
+
+
+# ------------------------------------------------------------- RHS parity
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("split", [None, ([10, 8, 6], [12, 8], [9, 7])])
+def test_rhs_synchronous(precision, split):
+    need_gpu()
+    announce("rhs sync", precision, split)
+    n = (24, 20, 16)
+    nblk = (3, 2, 2) if split else (2, 2, 2)
+    o, g = pair(dict(n=n, length=BOX, nblk=nblk, split=split), precision)
+    U = inputs.smooth_random_state(n, BOX, seed=4)
+    if precision == "f32":
+        U = f32(U)
+    set_both(o, g, U)
+    R = to_np(g.rhs())
+    ref = o.rhs(U)
+    tol = rhs_tol(U, o.cfg.h, precision)
+    assert np.abs(R - ref).max() < tol, (np.abs(R - ref).max(), tol)
+
+
+def smooth_history(n, steps, tau=0.05, ndim=3, seed=3):
+    """Levels U^m that vary smoothly in time (a translating vortex plus a
+    fixed perturbation), so that extrapolated halo values stay physical."""
+    pert = 0.02 * (inputs.smooth_random_state(n, BOX, seed=seed, ndim=ndim) - 1.0)
+    last = steps[-1]
+    return {m: inputs.vortex_state(n, BOX, ndim, t=(m - last) * tau) + pert for m in steps}
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("mode, algo, nstep", [("at", "saa", 13), ("at", "caa", 16),
+                                               ("as", "saa", 13)])
+def test_rhs_delayed_halos(precision, mode, algo, nstep):
+    need_gpu()
+    announce("rhs delayed", precision, mode, algo)
+    n = (32, 24, 20)
+    split = ([12, 12, 8], [14, 10], [10, 10])
+    o, g = pair(dict(n=n, length=BOX, nblk=(3, 2, 2), split=split, mode=mode, algo=algo, L=4,
+                     seed=21), precision)
+    D = g.ring_depth
+    hist = smooth_history(n, list(range(nstep - D + 1, nstep + 1)))
+    for m, U in sorted(hist.items()):
+        set_both(o, g, f32(U) if precision == "f32" else U, step=m)
+    k = o.delays()
+    assert k is not None and k.max() == 3
+    R = to_np(g.rhs())
+    ref = o.rhs(o.U, 0, k)
+    wn = max(np.abs(o.W[0, kk]).sum() for kk in range(4))
+    tol = rhs_tol(o.U, o.cfg.h, precision, wn)
+    assert np.abs(R - ref).max() < tol, (np.abs(R - ref).max(), tol)
+
+
+# ----------------------------------------------------------------- delays
+@pytest.mark.parametrize("algo", ["caa", "saa"])
+def test_device_delays_match_oracle(algo):
+    need_gpu()
+    announce("delays", algo)
+    n = (32, 32, 32)
+    o, g = pair(dict(n=n, length=BOX, nblk=(4, 2, 2), mode="at", algo=algo, L=4, seed=77))
+    for step in list(range(0, 12)) + [999, 123456]:
+        k = g.get_delays(step)
+        ref = o.delays(step)
+        if ref is None:
+            assert k is None
+        else:
+            assert np.array_equal(k.astype(np.int64), ref), step
+
+
+def test_injected_delays_and_guard():
+    need_gpu()
+    announce("delay injection")
+    n = (16, 16, 16)
+    o, g = pair(dict(n=n, length=BOX, nblk=(2, 2, 2), mode="at", algo="saa", L=4, seed=1))
+    rng = np.random.default_rng(0)
+    inj = rng.integers(-2, 9, size=(6, 8, 18)).astype(np.int8)
+    g.set_delays(4, inj)
+    for j in range(6):
+        step = 4 + j
+        ref = odl.delays("saa", step, 8, 4, 5, 1, override=inj[j].astype(np.int64))
+        k = g.get_delays(step)
+        if ref is None:
+            assert k is None
+        else:
+            assert np.array_equal(k.astype(np.int64), ref)
+    g.set_delays(0, np.zeros((0, 8, 18), dtype=np.int8))
+    assert np.array_equal(g.get_delays(7).astype(np.int64), o.delays(7))
+
+
+# ------------------------------------------------------------ step parity
+CASES = [
+    ("sa", "caa", 1), ("at", "caa", 4), ("at", "saa", 3), ("as", "caa", 4), ("as", "saa", 2),
+]
+
+
+@pytest.mark.parametrize("rk", ["rk4", "lserk4"])
+@pytest.mark.parametrize("mode, algo, L", CASES)
+def test_steps_fp64_match_oracle(rk, mode, algo, L):
+    need_gpu()
+    announce("steps f64", rk, mode, algo, L)
+    n = (24, 24, 16)
+    U0 = inputs.vortex_state(n, BOX, 3)
+    dt = inputs.cfl_dt(U0, n, BOX, 3, 1.4, 0.1)
+    o, g = pair(dict(n=n, length=BOX, nblk=(3, 2, 2), rk=rk, mode=mode, algo=algo, L=L, seed=5),
+                "f64", dt=dt)
+    set_both(o, g, U0)
+    nsteps = 12
+    g.step(nsteps)
+    o.step(nsteps)
+    G = to_np(g.get_state())
+    assert g.step_number() == nsteps
+    err = rel_max(G, o.U)
+    assert err < 1e-12, err
+
+
+@pytest.mark.parametrize("mode, algo, L", [("sa", "caa", 1), ("at", "caa", 4), ("at", "saa", 4)])
+def test_steps_fp32_against_fp64_oracle(mode, algo, L):
+    # FP32 state against the FP64 oracle of the same scheme and delays.
+    need_gpu()
+    announce("steps f32", mode, algo, L)
+    n = (32, 32, 16)
+    U0 = inputs.vortex_state(n, BOX, 3)
+    dt = inputs.cfl_dt(U0, n, BOX, 3, 1.4, 0.02)     # stable for SAA with L = 4
+    o, g = pair(dict(n=n, length=BOX, nblk=(2, 2, 2), mode=mode, algo=algo, L=L, seed=9),
+                "f32", dt=dt)
+    set_both(o, g, U0)
+    nsteps = 40
+    g.step(nsteps)
+    o.step(nsteps)
+    err = rel_l2(to_np(g.get_state()), o.U)
+    print("fp32 rel L2", mode, algo, L, err)
+    assert err < 1e-5, err
+
+
+def test_bitwise_reproducible_and_sa_decomposition():
+    # Same run twice -> identical bits; SA decomposed into blocks == one block.
+    need_gpu()
+    announce("bitwise")
+    n = (32, 32, 32)
+    U0 = inputs.vortex_state(n, BOX, 3)
+    dt = inputs.cfl_dt(U0, n, BOX, 3, 1.4, 0.2)
+    outs = []
+    for nblk in ((2, 2, 2), (2, 2, 2), (1, 1, 1), (4, 1, 2)):
+        _, g = pair(dict(n=n, length=BOX, nblk=nblk), "f32", dt=dt)
+        import torch
+        g.set_state(torch.from_numpy(U0))
+        g.step(6)
+        outs.append(to_np(g.get_state()))
+        g.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+    assert np.array_equal(outs[0], outs[3])
+
+
+# ------------------------------------------------------------ diagnostics
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_diagnostics_match_oracle(precision):
+    need_gpu()
+    announce("diagnostics", precision)
+    n = (32, 24, 16)
+    L3 = (2 * math.pi,) * 3
+    o, g = pair(dict(n=n, length=L3, nblk=(2, 2, 2)), precision)
+    U = inputs.tgv_state(n) + 0.01 * inputs.smooth_random_state(n, L3, seed=2)
+    if precision == "f32":
+        U = f32(U)
+    set_both(o, g, U)
+    d, ok = g.reduce()
+    assert ok
+    ref = diagnostics.all_diagnostics(U, o.cfg.h, 3)
+    assert np.abs(d - ref).max() < 1e-12 * np.abs(ref).max(), (d, ref)
+
+
+def test_reduce_reports_nonfinite():
+    need_gpu()
+    announce("nonfinite")
+    n = (16, 16, 16)
+    o, g = pair(dict(n=n, length=BOX, nblk=(1, 1, 1)), "f32")
+    U = inputs.vortex_state(n, BOX, 3)
+    U[0, 3, 4, 5] = np.nan
+    set_both(o, g, U)
+    _, ok = g.reduce()
+    assert not ok
+
+
+# -------------------------------------------------------- 2D vortex, FP64
+def test_vortex2d_64_sa_fp64_200_steps():
+    # 2D isentropic vortex, 64^2 on [0,10]^2, Mach 0.5, strength 5, SA, CD4,
+    # RK4, CFL 0.5, 200 steps, FP64 -- against the oracle and the exact
+    # translated vortex (whose periodic tail floors the error, ~1e-4 here).
+    need_gpu()
+    announce("vortex2d")
+    w = inputs.WORKLOADS["vortex2d_64"]
+    n, length = w["n"], w["length"]
+    U0 = inputs.vortex_state(n, length, 2)
+    dt = inputs.cfl_dt(U0, n, length, 2, 1.4, w["cfl"])
+    o, g = pair(dict(n=n, length=length, ndim=2), "f64", dt=dt)
+    set_both(o, g, U0)
+    g.step(w["steps"])
+    o.step(w["steps"])
+    G = to_np(g.get_state())
+    assert rel_max(G, o.U) < 1e-12
+    ex = inputs.vortex_state(n, length, 2, t=w["steps"] * dt)
+    assert rel_l2(G[0], ex[0]) < 2e-3

@@ -1,0 +1,85 @@
+"""Host-side checks of the HIP library (no GPU): it loads, exports every
+symbol include/atns.h declares, validates configurations before touching a
+device, and its host tables agree with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import at as oat, delays as odl
+from paper_2506_03027_amd import atns
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "atns.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(atns_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    L = atns.lib()
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(atns.EXPORTS)
+
+
+@pytest.mark.parametrize("rk, orc", [(atns.RK4, "rk4"), (atns.LSERK4, "lserk4")])
+@pytest.mark.parametrize("L", [1, 4, 5])
+def test_host_weight_table_matches_oracle(rk, orc, L):
+    W = atns.host_weights(rk, atns.AT, L)
+    ref = oat.halo_table(orc, "at", 5, L - 1)
+    scale = np.abs(ref).max()
+    assert np.abs(W - ref).max() < 1e-14 * scale
+    Was = atns.host_weights(rk, atns.AS, L)
+    assert np.array_equal(Was, oat.halo_table(orc, "as", 5, L - 1))
+
+
+@pytest.mark.parametrize("algo, oalgo", [(atns.CAA, "caa"), (atns.SAA, "saa")])
+def test_host_delays_match_oracle_bitwise(algo, oalgo):
+    for n in (0, 4, 5, 6, 7, 20, 1234):
+        for nb, L, seed in ((8, 4, 1), (64, 4, 99), (5, 5, 2 ** 63 + 17)):
+            k, sync = atns.host_delays(algo, n, nb, L, seed)
+            ref = odl.delays(oalgo, n, nb, L, 5, seed)
+            if ref is None:
+                assert sync and not k.any()
+            else:
+                assert not sync
+                assert np.array_equal(k.astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ndim=4),
+    dict(L=0),
+    dict(L=17),
+    dict(nblk=(20, 1, 1)),                   # blocks of 2 points < NS halo depth 4 ... Euler 2 ok
+    dict(physics=atns.NS, nblk=(16, 1, 1)),  # 2-point blocks < 4
+    dict(split=([10, 10, 10], [32], [32]), nblk=(3, 1, 1)),
+    dict(ndim=2),                            # nz != 1
+    dict(mode=7),
+    dict(precision=3),
+])
+def test_create_rejects_bad_config_without_device(bad):
+    kw = dict(n=(32, 32, 32), length=(1.0, 1.0, 1.0), ndim=3, nblk=(2, 2, 2))
+    kw.update(bad)
+    if kw.get("nblk") == (20, 1, 1):
+        kw["nblk"] = (32, 1, 1)              # 1-point blocks < 2
+    cfg, keep = atns.make_config(**kw)
+    import ctypes
+    ctx = ctypes.c_void_p()
+    st = atns.lib().atns_create(ctypes.byref(cfg), None, ctypes.byref(ctx))
+    assert st == -1
+    assert ctx.value is None
+    assert len(atns.lib().atns_last_error(None)) > 0
+
+
+def test_host_helpers_reject_bad_arguments():
+    import ctypes
+    out = np.zeros(100, dtype=np.float64)
+    assert atns.lib().atns_host_weights(atns.RK4, atns.AT, 0, out.ctypes.data) == -1
+    assert atns.lib().atns_host_weights(9, atns.AT, 4, out.ctypes.data) == -1
+    k = np.zeros(18, dtype=np.int8)
+    assert atns.lib().atns_host_delays(atns.SAA, -1, 1, 4, 0, k.ctypes.data, None) == -1
