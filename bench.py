@@ -112,9 +112,9 @@ def cpu_baseline(torch, w, budget_s=20.0):
     of the translating vortex so that every timed step is asynchronous.  The
     FP32 GPU path runs the same sample for the L2 error."""
     from oracle import solver
-    scale = 2 if w["n"][0] >= 128 else 1
-    n = tuple(max(16, x // scale) for x in w["n"])
-    nblk = tuple(max(1, b // scale) for b in w["nblk"])
+    blk = [w["n"][d] // w["nblk"][d] for d in range(3)]
+    n = tuple(w["n"][d] if w["n"][d] <= 64 else max(64, 2 * blk[d]) for d in range(3))
+    nblk = tuple(n[d] // blk[d] for d in range(3))
     s = dict(w, n=n, nblk=nblk)
     length = w["length"]
     stages = 4 if w["rk"] == "rk4" else 5
@@ -136,7 +136,7 @@ def cpu_baseline(torch, w, budget_s=20.0):
         o.set_state(hist[m], step=m)
     t0 = time.perf_counter()
     done = 0
-    while done < 1 or (time.perf_counter() - t0 < budget_s * 0.5 and done < 4):
+    while done < 1 or (time.perf_counter() - t0 < budget_s * 0.5 and done < 8):
         o.step(1)
         done += 1
     elapsed = time.perf_counter() - t0
