@@ -89,10 +89,14 @@ def time_steps(torch, g, steps):
     return e0.elapsed_time(e1)
 
 
+TUNE_CACHE = os.environ.get("ATNS_TUNE_CACHE", os.path.join("/tmp", "atns_tune.txt"))
+
+
 def gpu_run(torch, w, precision, mode, steps, warmup, U0, dt):
     g = make_solver(w, precision, mode)
     g.set_dt(dt)
     g.set_state(torch.from_numpy(U0))
+    tiles = g.autotune(reps=3, cache=TUNE_CACHE)   # tile shape of the stage kernels
     g.step(warmup)
     ms = time_steps(torch, g, steps)
     # per-launch durations of the fused stage kernel, from HIP events on the
@@ -103,7 +107,7 @@ def gpu_run(torch, w, precision, mode, steps, warmup, U0, dt):
     g.profile(False)
     diag, finite = g.reduce()
     g.close()
-    return ms, launches, kms, finite
+    return ms, launches, kms, finite, tiles
 
 
 def cpu_baseline(torch, w, budget_s=20.0):
@@ -181,7 +185,7 @@ def main():
     dt = inputs.cfl_dt(U0, w["n"], w["length"], w["ndim"], 1.4, w["cfl"])
     warmup = max(a.warmup, C_LEVELS + 1)   # the first C steps are synchronous
 
-    ms, launches, kms, finite = gpu_run(torch, w, atns.F32, None, a.steps, warmup, U0, dt)
+    ms, launches, kms, finite, tiles = gpu_run(torch, w, atns.F32, None, a.steps, warmup, U0, dt)
     value = npts * stages * a.steps / (ms * 1e-3)
     bpp, f = algorithmic_bytes_per_point_stage(w, stages, 4)
     avg_launch_ms = kms / max(1, launches)
@@ -202,7 +206,8 @@ def main():
         "config": {"workload": a.workload, "grid": list(w["n"]), "blocks": list(w["nblk"]),
                    "physics": w["physics"], "scheme": "CD4 + %s halos, %s" % (w["mode"].upper(),
                                                                              w["rk"].upper()),
-                   "algo": w.get("algo", "saa").upper(), "L": w["L"], "cfl": w["cfl"]},
+                   "algo": w.get("algo", "saa").upper(), "L": w["L"], "cfl": w["cfl"],
+                   "tiles": list(tiles)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "%s_stage_kernel" % ("ns" if w["physics"] == "ns" else "euler"),
@@ -211,7 +216,7 @@ def main():
         "finite": finite,
     }
     if not a.no_fp64:
-        ms64, l64, k64, fin64 = gpu_run(torch, w, atns.F64, "sa", a.steps, warmup, U0, dt)
+        ms64, l64, k64, fin64, _ = gpu_run(torch, w, atns.F64, "sa", a.steps, warmup, U0, dt)
         b64, _ = algorithmic_bytes_per_point_stage(dict(w, mode="sa"), stages, 8)
         out["fp64_sa"] = {"value": npts * stages * a.steps / (ms64 * 1e-3),
                           "ms_per_step": ms64 / a.steps,

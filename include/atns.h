@@ -169,6 +169,23 @@ atns_status atns_get_layout(const atns_ctx* ctx, int32_t* nblocks, int32_t* ring
 atns_status atns_profile_enable(atns_ctx* ctx, int32_t on);
 atns_status atns_profile_read(atns_ctx* ctx, int64_t* launches, double* total_ms);
 
+/* Tile shape of the stage kernels: a workgroup walks a TX x TY column of one
+ * block through TZ planes.  Supported (TX, TY): Euler (16,16) (32,8) (64,4)
+ * (16,8) (32,4); Navier-Stokes (16,16) (32,8) (16,8).  Tiles never straddle
+ * blocks; ragged edges are handled.  EINVAL for other shapes or tz < 1. */
+atns_status atns_set_tiles(atns_ctx* ctx, int32_t tx, int32_t ty, int32_t tz);
+atns_status atns_get_tiles(const atns_ctx* ctx, int32_t* tx, int32_t* ty, int32_t* tz);
+
+/* Autotuner of the tile shape.  Times every supported (TX, TY) with column
+ * lengths TZ in {4, 8, 16, 32} (Navier-Stokes: 8, 16, 32) on the current
+ * state -- reps launches of the stage kernel each, HIP events on the context
+ * stream, results into a scratch register so the state is untouched -- and
+ * keeps the fastest.  cache_path (or NULL) names a text file of
+ * "key tx ty tz" lines; a configuration found there is applied without
+ * timing, a newly tuned one is appended.  best_txyz (or NULL) receives the
+ * chosen shape.  Synchronizes; ESTATE before a state is set. */
+atns_status atns_autotune(atns_ctx* ctx, int32_t reps, const char* cache_path, int32_t* best_txyz);
+
 /* ---- host-only helpers (no device needed) -------------------------------
  * The FP64 per-stage halo weight table the kernels use: out[e][k][l] for
  * stages e < s (s = 4 for RK4, 5 for LSERK4), delays k < L and levels

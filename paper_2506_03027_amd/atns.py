@@ -27,7 +27,8 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "EN
 EXPORTS = ["atns_version", "atns_create", "atns_destroy", "atns_last_error", "atns_set_state",
            "atns_get_state", "atns_get_step", "atns_set_dt", "atns_set_delays", "atns_get_delays",
            "atns_rhs", "atns_rk_step", "atns_reduce", "atns_get_layout", "atns_profile_enable",
-           "atns_profile_read", "atns_host_weights", "atns_host_delays"]
+           "atns_profile_read", "atns_set_tiles", "atns_get_tiles", "atns_autotune",
+           "atns_host_weights", "atns_host_delays"]
 
 
 class AtnsError(RuntimeError):
@@ -72,6 +73,9 @@ def lib():
             "atns_get_layout": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
             "atns_profile_enable": ([vp, i32], i32),
             "atns_profile_read": ([vp, ctypes.POINTER(i64), ctypes.POINTER(dbl)], i32),
+            "atns_set_tiles": ([vp, i32, i32, i32], i32),
+            "atns_get_tiles": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+            "atns_autotune": ([vp, i32, ctypes.c_char_p, vp], i32),
             "atns_host_weights": ([i32, i32, i32, vp], i32),
             "atns_host_delays": ([i32, i64, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(i32)], i32),
         }
@@ -209,6 +213,20 @@ class Solver:
         n, ms = ctypes.c_int64(), ctypes.c_double()
         _check(lib().atns_profile_read(self.ctx, ctypes.byref(n), ctypes.byref(ms)), self.ctx)
         return n.value, ms.value
+
+    def set_tiles(self, tx, ty, tz):
+        _check(lib().atns_set_tiles(self.ctx, tx, ty, tz), self.ctx)
+
+    def get_tiles(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().atns_get_tiles(self.ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), self.ctx)
+        return a.value, b.value, c.value
+
+    def autotune(self, reps=5, cache=None):
+        best = np.zeros(3, dtype=np.int32)
+        path = cache.encode() if cache else None
+        _check(lib().atns_autotune(self.ctx, int(reps), path, best.ctypes.data), self.ctx)
+        return tuple(int(x) for x in best)
 
     def reduce(self):
         out = np.zeros(NDIAG, dtype=np.float64)

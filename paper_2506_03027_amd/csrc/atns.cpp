@@ -27,6 +27,8 @@ struct atns_ctx {
   int nb = 0;
   std::vector<BlockDev> blocks;
   std::vector<TileDev> tiles;
+  std::vector<HaloRegion> regions;
+  std::vector<HaloWork> work;
   size_t esz = 4;
   long long field = 0;
   // RK registers: RK4 uses X[0] = U, X[1] = Ya, X[2] = Yb, X[3] = acc.
@@ -44,6 +46,11 @@ struct atns_ctx {
   int64_t inject0 = 0;
   int inject_n = 0;
   double* d_W = nullptr;
+  void* hbuf = nullptr;              // stage halos: stages x slot_stride
+  HaloRegion* d_regions = nullptr;
+  HaloWork* d_work = nullptr;
+  int nwork = 0;
+  int tile[3] = {16, 16, 16};        // stage-kernel tile shape TX, TY, TZ
   double* d_partials = nullptr;
   double* d_diag = nullptr;
   int nparts = 1024;
@@ -174,6 +181,31 @@ void build_layout(atns_ctx* c) {
     }
   }
   c->slot_stride = off;
+  // reader-side halo offsets: region s of block b mirrors layer opposite(s)
+  // of its neighbour, so the per-stage halo buffer has the same total size
+  long long hoff = 0;
+  for (int b = 0; b < c->nb; ++b) {
+    BlockDev& B = c->blocks[b];
+    for (int s = 0; s < kNumSlots; ++s) {
+      B.hoff[s] = -1;
+      if (!slot_used(c, s)) continue;
+      int dir[3];
+      slot_dir(s, dir);
+      const int dep = s < 6 ? c->H : 2;
+      long long cnt = 1;
+      for (int d = 0; d < 3; ++d) cnt *= dir[d] ? dep : B.s[d];
+      B.hoff[s] = hoff;
+      HaloRegion r;
+      r.dst = hoff;
+      r.src = c->blocks[B.nbr[s]].lay[slot_opposite(s)];
+      r.npts = (int)cnt;
+      r.kidx = b * kNumSlots + s;
+      const int rid = (int)c->regions.size();
+      c->regions.push_back(r);
+      for (int st = 0; st < (int)cnt; st += kHaloChunk) c->work.push_back(HaloWork{rid, st});
+      hoff += 5 * cnt;
+    }
+  }
 }
 
 void build_tiles(atns_ctx* c, int TX, int TY, int TZ) {
@@ -205,13 +237,49 @@ void build_tiles(atns_ctx* c, int TX, int TY, int TZ) {
   }
 }
 
+bool shape_supported(int physics, int tx, int ty) {
+  if (physics == ATNS_NS) return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 16 && ty == 8);
+  return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 64 && ty == 4) || (tx == 16 && ty == 8) ||
+         (tx == 32 && ty == 4);
+}
+
+size_t count_tiles(const atns_ctx* c, int tx, int ty, int tz) {
+  size_t n = 0;
+  for (const BlockDev& B : c->blocks)
+    n += (size_t)((B.s[0] + tx - 1) / tx) * ((B.s[1] + ty - 1) / ty) * ((B.s[2] + tz - 1) / tz);
+  return n;
+}
+
+// Default shape before any tuning: 16 x 16 columns, and the longest column
+// (32, 16, 8 or 4 planes) that still gives about eight workgroups per CU.
+void default_tiles(atns_ctx* c) {
+  c->tile[0] = 16;
+  c->tile[1] = 16;
+  int tz = 4;
+  for (int cand : {32, 16, 8})
+    if (count_tiles(c, 16, 16, cand) >= 2048) {
+      tz = cand;
+      break;
+    }
+  c->tile[2] = c->cfg.ndim == 2 ? 1 : tz;
+}
+
+atns_status upload_tiles(atns_ctx* c) {
+  build_tiles(c, c->tile[0], c->tile[1], c->tile[2]);
+  if (c->d_tiles) (void)hipFree(c->d_tiles);
+  c->d_tiles = nullptr;
+  if (hipMalloc((void**)&c->d_tiles, c->tiles.size() * sizeof(TileDev)) != hipSuccess)
+    return fail(c, ATNS_ENOMEM, "tile table allocation failed");
+  HIP_TRY(c, hipMemcpy(c->d_tiles, c->tiles.data(), c->tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice));
+  return ATNS_OK;
+}
+
 template <typename T>
 StageParams<T> base_params(const atns_ctx* c) {
   StageParams<T> p{};
   p.ring = (T*)c->ring;
   p.blocks = c->d_blocks;
   p.tiles = c->d_tiles;
-  p.delays = c->d_delays;
   for (int d = 0; d < 3; ++d) {
     p.n[d] = c->n[d];
     p.inv12h[d] = 1.0 / (12.0 * c->h[d]);
@@ -253,8 +321,8 @@ hipError_t launch_stage(atns_ctx* c, const StageParams<T>& p, int kind) {
     if (r != hipSuccess) return r;
   }
   hipError_t r = (c->cfg.physics == ATNS_NS)
-                     ? launch_ns_stage<T>(p, (int)c->tiles.size(), kind, c->stream)
-                     : launch_euler_stage<T>(p, (int)c->tiles.size(), kind, c->stream);
+                     ? launch_ns_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], c->stream)
+                     : launch_euler_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], c->stream);
   if (r == hipSuccess && c->profiling) r = hipEventRecord(e1, c->stream);
   return r;
 }
@@ -269,21 +337,32 @@ atns_status draw_delays(atns_ctx* c, int64_t step, int8_t* dst) {
   return ATNS_OK;
 }
 
+// Delay draw and stage-halo assembly of the current step (asynchronous steps).
+template <typename T>
+atns_status prepare_halos(atns_ctx* c) {
+  atns_status st = draw_delays(c, c->step, c->d_delays);
+  if (st != ATNS_OK) return st;
+  HIP_TRY(c, launch_halo<T>((const T*)c->ring, (T*)c->hbuf, c->d_regions, c->d_work, (int)c->work.size(),
+                            c->d_delays, c->d_W, c->slot_stride, c->slot_stride, c->D,
+                            (int)(c->step % c->D), c->cfg.L, c->rk.stages, c->cfg.mode == ATNS_AS,
+                            c->stream));
+  return ATNS_OK;
+}
+
 template <typename T>
 atns_status do_steps(atns_ctx* c, int nsteps) {
   const RKScheme& rk = c->rk;
-  const int L = c->cfg.L;
   for (int it = 0; it < nsteps; ++it) {
     const bool async = is_async(c, c->step);
     if (async) {
-      atns_status st = draw_delays(c, c->step, c->d_delays);
+      atns_status st = prepare_halos<T>(c);
       if (st != ATNS_OK) return st;
     }
     StageParams<T> p = base_params<T>(c);
     p.halo = !async ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
     p.slot_now = c->D ? (int)(c->step % c->D) : 0;
     for (int e = 0; e < rk.stages; ++e) {
-      p.W = c->d_W ? c->d_W + (size_t)e * L * kC : nullptr;
+      p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)e * c->slot_stride : nullptr;
       p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
       int kind;
       if (!rk.low_storage) {
@@ -325,8 +404,8 @@ void release(atns_ctx* c) {
       (void)hipFree(x);
       x = nullptr;
     }
-  void* ptrs[] = {c->ring, c->d_blocks, c->d_tiles, c->d_delays, c->d_probe,
-                  c->d_inject, c->d_W, c->d_partials, c->d_diag};
+  void* ptrs[] = {c->ring, c->d_blocks, c->d_tiles, c->d_delays, c->d_probe, c->d_inject, c->d_W,
+                  c->d_partials, c->d_diag, c->hbuf, c->d_regions, c->d_work};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   c->ring = nullptr;
@@ -363,7 +442,8 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
   c->esz = cfg->precision == ATNS_F64 ? 8 : 4;
   c->field = (long long)c->n[0] * c->n[1] * c->n[2];
   build_layout(c);
-  build_tiles(c, 16, 16, 16);
+  default_tiles(c);
+  build_tiles(c, c->tile[0], c->tile[1], c->tile[2]);
   c->D = cfg->mode == ATNS_SA ? 0 : kC + cfg->L;
 
   auto fail_free = [&](atns_status s, const std::string& m) {
@@ -379,6 +459,15 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
   if (c->D) {
     if (hipMalloc(&c->ring, (size_t)c->slot_stride * c->D * c->esz) != hipSuccess)
       return fail_free(ATNS_ENOMEM, "ring allocation failed");
+    if (hipMalloc(&c->hbuf, (size_t)c->slot_stride * c->rk.stages * c->esz) != hipSuccess)
+      return fail_free(ATNS_ENOMEM, "halo buffer allocation failed");
+    if (hipMalloc((void**)&c->d_regions, c->regions.size() * sizeof(HaloRegion)) != hipSuccess ||
+        hipMalloc((void**)&c->d_work, c->work.size() * sizeof(HaloWork)) != hipSuccess ||
+        hipMemcpy(c->d_regions, c->regions.data(), c->regions.size() * sizeof(HaloRegion),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_work, c->work.data(), c->work.size() * sizeof(HaloWork), hipMemcpyHostToDevice) !=
+            hipSuccess)
+      return fail_free(ATNS_EHIP, "halo table upload failed");
     const std::vector<double> W = halo_weights(cfg->rk, cfg->mode == ATNS_AS ? ATNS_AS : ATNS_AT, cfg->L);
     if (hipMalloc((void**)&c->d_W, W.size() * sizeof(double)) != hipSuccess ||
         hipMemcpy(c->d_W, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
@@ -493,16 +582,16 @@ atns_status atns_rhs(atns_ctx* c, void* dev_R) {
   if (!c || !dev_R) return fail(c, ATNS_EINVAL, "null argument");
   if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
   const bool async = is_async(c, c->step);
-  if (async) {
-    atns_status st = draw_delays(c, c->step, c->d_delays);
-    if (st != ATNS_OK) return st;
-  }
   auto go = [&](auto tag) -> atns_status {
     using T = decltype(tag);
+    if (async) {
+      atns_status st = prepare_halos<T>(c);
+      if (st != ATNS_OK) return st;
+    }
     StageParams<T> p = base_params<T>(c);
     p.halo = !async ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
     p.slot_now = c->D ? (int)(c->step % c->D) : 0;
-    p.W = c->d_W;
+    p.hbuf = (const T*)c->hbuf;
     p.ring_write = 0;
     p.Y = (const T*)state_ptr(c);
     p.Yout = (T*)dev_R;
@@ -567,6 +656,139 @@ atns_status atns_profile_read(atns_ctx* c, int64_t* launches, double* total_ms) 
   *launches = (int64_t)(c->ev_used / 2);
   *total_ms = tot;
   c->ev_used = 0;
+  return ATNS_OK;
+}
+
+atns_status atns_set_tiles(atns_ctx* c, int32_t tx, int32_t ty, int32_t tz) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  if (!shape_supported(c->cfg.physics, tx, ty) || tz < 1 || tz > 32767)
+    return fail(c, ATNS_EINVAL, "unsupported tile shape");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->tile[0] = tx;
+  c->tile[1] = ty;
+  c->tile[2] = c->cfg.ndim == 2 ? 1 : tz;
+  return upload_tiles(c);
+}
+
+atns_status atns_get_tiles(const atns_ctx* c, int32_t* tx, int32_t* ty, int32_t* tz) {
+  if (!c || !tx || !ty || !tz) return fail(const_cast<atns_ctx*>(c), ATNS_EINVAL, "null argument");
+  *tx = c->tile[0];
+  *ty = c->tile[1];
+  *tz = c->tile[2];
+  return ATNS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+std::string tune_key(const atns_ctx* c) {
+  // blocks of one size class tune alike: key on the first block's shape,
+  // the block count, the physics, precision and dimension
+  char buf[256];
+  const BlockDev& B = c->blocks[0];
+  std::snprintf(buf, sizeof buf, "gfx950/phys%d/prec%d/ndim%d/blk%dx%dx%d/nb%d", c->cfg.physics,
+                c->cfg.precision, c->cfg.ndim, B.s[0], B.s[1], B.s[2], c->nb);
+  return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, int out[3]) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char k[256];
+  int a, b, d;
+  bool found = false;
+  while (std::fscanf(f, "%255s %d %d %d", k, &a, &b, &d) == 4)
+    if (key == k) {
+      out[0] = a;
+      out[1] = b;
+      out[2] = d;
+      found = true;
+    }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const int v[3]) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d\n", key.c_str(), v[0], v[1], v[2]);
+  std::fclose(f);
+}
+
+template <typename T>
+atns_status time_shape(atns_ctx* c, int reps, float* ms_out) {
+  StageParams<T> p = base_params<T>(c);
+  p.halo = kHaloSync;
+  p.slot_now = c->D ? (int)(c->step % c->D) : 0;
+  p.ring_write = 0;
+  p.Y = (const T*)state_ptr(c);
+  p.Yout = (T*)(c->rk.low_storage ? c->X[1 - c->cur] : c->X[1]);   // scratch register
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  HIP_TRY(c, launch_stage<T>(c, p, kRhsOnly));   // warm
+  HIP_TRY(c, hipEventRecord(e0, c->stream));
+  for (int r = 0; r < reps; ++r) HIP_TRY(c, launch_stage<T>(c, p, kRhsOnly));
+  HIP_TRY(c, hipEventRecord(e1, c->stream));
+  HIP_TRY(c, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_out = ms / reps;
+  return ATNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+atns_status atns_autotune(atns_ctx* c, int32_t reps, const char* cache_path, int32_t* best) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+  if (reps < 1) return fail(c, ATNS_EINVAL, "reps must be positive");
+  const std::string key = tune_key(c);
+  int pick[3];
+  if (!cache_lookup(cache_path, key, pick)) {
+    static const int euler_xy[][2] = {{16, 16}, {32, 8}, {64, 4}, {16, 8}, {32, 4}};
+    static const int ns_xy[][2] = {{16, 16}, {32, 8}, {16, 8}};
+    const bool ns = c->cfg.physics == ATNS_NS;
+    const int nxy = ns ? 3 : 5;
+    const int tzs[] = {4, 8, 16, 32};
+    float best_ms = 1e30f;
+    pick[0] = c->tile[0];
+    pick[1] = c->tile[1];
+    pick[2] = c->tile[2];
+    for (int i = 0; i < nxy; ++i)
+      for (int tz : tzs) {
+        if (c->cfg.ndim == 2 && tz != 4) continue;
+        if (ns && tz < 8) continue;   // 8 extra planes per column: short ones waste work
+        const int tx = ns ? ns_xy[i][0] : euler_xy[i][0];
+        const int ty = ns ? ns_xy[i][1] : euler_xy[i][1];
+        atns_status st = atns_set_tiles(c, tx, ty, tz);
+        if (st != ATNS_OK) return st;
+        float ms = 0.f;
+        st = c->esz == 4 ? time_shape<float>(c, reps, &ms) : time_shape<double>(c, reps, &ms);
+        if (st != ATNS_OK) return st;
+        if (ms < best_ms) {
+          best_ms = ms;
+          pick[0] = tx;
+          pick[1] = ty;
+          pick[2] = c->tile[2];
+        }
+      }
+    cache_store(cache_path, key, pick);
+  }
+  atns_status st = atns_set_tiles(c, pick[0], pick[1], pick[2]);
+  if (st != ATNS_OK) return st;
+  if (best) {
+    best[0] = pick[0];
+    best[1] = pick[1];
+    best[2] = pick[2];
+  }
   return ATNS_OK;
 }
 

@@ -9,19 +9,34 @@ namespace atns {
 
 constexpr int kLevels = 5;  // AT4: C = 5
 
+// Workgroup barrier that orders LDS only: finish this wave's LDS operations,
+// then meet at s_barrier.  Unlike __syncthreads() it does not wait for
+// outstanding global loads, so loads issued for the next plane stay in
+// flight across the barrier (the compiler still waits before their use).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 __device__ __forceinline__ int wrap(int g, int n) {
   g += (g < 0) ? n : 0;
   g -= (g >= n) ? n : 0;
   return g;
 }
 
+// Copy a block descriptor into LDS (cooperatively, 32-bit words) and wait.
+__device__ __forceinline__ void stage_block(const BlockDev* __restrict__ src, BlockDev* dst) {
+  constexpr int nw = (int)(sizeof(BlockDev) / 4);
+  const int* s = reinterpret_cast<const int*>(src);
+  int* d = reinterpret_cast<int*>(dst);
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) d[i] = s[i];
+  __syncthreads();
+}
+
 // Conserved variables at block-local point (lx, ly, lz) of block B as seen by
 // that block in the current stage:
 //  * owned points, and every point under synchronous halos: the stage field
 //    Y at the periodic global position;
-//  * halo points (outside the block): for stale halos (AS) the ring level
-//    n-k; for AT the FP64 combination sum_l W[k][l] ring[n-k-l], rounded to T.
-// k is the delay the block sees from the neighbour owning the point.
+//  * halo points (outside the block): the stage's halo value, assembled once
+//    per step by halo_kernel (AT weights or the stale level) into a buffer
+//    laid out like the neighbour's ring layer.
 template <typename T>
 __device__ __forceinline__ void fetch(const StageParams<T>& p, const BlockDev* __restrict__ B,
                                       int blk, int lx, int ly, int lz, T u[5]) {
@@ -38,8 +53,6 @@ __device__ __forceinline__ void fetch(const StageParams<T>& p, const BlockDev* _
     return;
   }
   const int s = slot_index(sx, sy, sz);
-  const BlockDev* Bn = p.blocks + B->nbr[s];
-  const long long base = Bn->lay[slot_opposite(s)];
   const int dep = ((sx != 0) + (sy != 0) + (sz != 0) == 1) ? p.H : 2;
   const int ix = sx < 0 ? lx + dep : (sx > 0 ? lx - B->s[0] : lx);
   const int iy = sy < 0 ? ly + dep : (sy > 0 ? ly - B->s[1] : ly);
@@ -49,28 +62,9 @@ __device__ __forceinline__ void fetch(const StageParams<T>& p, const BlockDev* _
   const int ez = sz ? dep : B->s[2];
   const long long li = ((long long)iz * ey + iy) * ex + ix;
   const long long vs = (long long)ex * ey * ez;
-  const int k = p.delays[blk * kNumSlots + s];
-  if (p.halo == kHaloStale) {
-    int sl = p.slot_now - k;
-    sl += (sl < 0) ? p.D : 0;
-    const T* r = p.ring + (long long)sl * p.slot_stride + base + li;
+  const T* r = p.hbuf + B->hoff[s] + li;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) u[v] = r[v * vs];
-    return;
-  }
-  double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const double* w = p.W + k * kLevels;
-#pragma unroll
-  for (int l = 0; l < kLevels; ++l) {
-    int sl = p.slot_now - k - l;
-    sl += (sl < 0) ? p.D : 0;
-    const T* r = p.ring + (long long)sl * p.slot_stride + base + li;
-    const double wl = w[l];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) a[v] = fma(wl, (double)r[v * vs], a[v]);
-  }
-#pragma unroll
-  for (int v = 0; v < 5; ++v) u[v] = (T)a[v];
+  for (int v = 0; v < 5; ++v) u[v] = r[v * vs];
 }
 
 // Write the values of owned point (lx, ly, lz) into every boundary layer of
@@ -108,6 +102,53 @@ __device__ __forceinline__ void ring_store(const StageParams<T>& p, const BlockD
     const long long vs = (long long)ext[0] * ext[1] * ext[2];
 #pragma unroll
     for (int v = 0; v < 5; ++v) slot[off + li + v * vs] = u[v];
+  }
+}
+
+// Operands the RK epilogue reads at a point besides the stage input: the
+// accumulator / Q register and, for the middle RK4 stages, U^n.  Loaded one
+// plane ahead so their latency hides behind the stencil work.
+template <typename T, int KIND>
+__device__ __forceinline__ void epilogue_load(const StageParams<T>& p, long long g, T accv[5], T u0v[5]) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const long long i = v * p.field + g;
+    if (KIND == kRK4Mid || KIND == kRK4Last || KIND == kLSMid) accv[v] = p.acc[i];
+    if (KIND == kRK4Mid) u0v[v] = p.U0[i];
+  }
+}
+
+// RK epilogue with preloaded operands (see epilogue_load).
+template <typename T, int KIND>
+__device__ __forceinline__ void epilogue_pre(const StageParams<T>& p, long long g, const T Y[5], const T R[5],
+                                             const T accv[5], const T u0v[5], T out[5]) {
+  const T dt = (T)p.dt, cA = (T)p.cA, cB = (T)p.cB;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const long long i = v * p.field + g;
+    const T r = R[v];
+    if (KIND == kRhsOnly) {
+      out[v] = r;
+    } else if (KIND == kRK4First) {
+      const T dr = dt * r;
+      p.acc[i] = Y[v] + cA * dr;
+      out[v] = Y[v] + cB * dr;
+    } else if (KIND == kRK4Mid) {
+      const T dr = dt * r;
+      p.acc[i] = accv[v] + cA * dr;
+      out[v] = u0v[v] + cB * dr;
+    } else if (KIND == kRK4Last) {
+      out[v] = accv[v] + cA * (dt * r);
+    } else if (KIND == kLSFirst) {
+      const T q = dt * r;
+      p.acc[i] = q;
+      out[v] = Y[v] + cB * q;
+    } else {  // kLSMid
+      const T q = cA * accv[v] + dt * r;
+      p.acc[i] = q;
+      out[v] = Y[v] + cB * q;
+    }
+    p.Yout[i] = out[v];
   }
 }
 

@@ -43,7 +43,12 @@ template <typename T, int TX, int TY, int KIND>
 __global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T> p) {
   const TileDev t = p.tiles[blockIdx.x];
   if (t.nx == 0) return;
-  const BlockDev* __restrict__ B = p.blocks + t.blk;
+  // The block descriptor lives in LDS for the whole kernel: re-reading it from
+  // global memory inside the plane loop would make every such load wait for
+  // all outstanding (prefetch) loads.
+  __shared__ BlockDev sB;
+  stage_block(p.blocks + t.blk, &sB);
+  const BlockDev* __restrict__ B = &sB;
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
   const bool act = (tx < t.nx) && (ty < t.ny);
@@ -72,13 +77,22 @@ __global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T
   }
 
   T q[5][5];
+  T nq[5], na[5];   // prefetched: own column at z+2 and the apron point at z
   if (act && three) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) fetch(p, B, t.blk, lx, ly, t.z0 - 2 + j, q[j + 1]);
+    fetch(p, B, t.blk, lx, ly, t.z0 + 2, nq);
   }
+  if (arole) fetch(p, B, t.blk, t.x0 + ax, t.y0 + ay, t.z0, na);
 
   T* ring_slot = nullptr;
   if (p.ring_write) ring_slot = p.ring + (long long)((p.slot_now + 1) % p.D) * p.slot_stride;
+
+  // global index of the thread's column at plane z0, and the stride per plane
+  const long long g0 = ((long long)(B->o[2] + t.z0) * p.n[1] + (B->o[1] + ly)) * p.n[0] + (B->o[0] + lx);
+  const long long gplane = (long long)p.n[0] * p.n[1];
+  T accv[5], u0v[5];
+  if (act) epilogue_load<T, KIND>(p, g0, accv, u0v);
 
   for (int iz = 0; iz < t.nz; ++iz) {
     const int lz = t.z0 + iz;
@@ -89,7 +103,10 @@ __global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T
         for (int j = 0; j < 4; ++j)
 #pragma unroll
           for (int v = 0; v < 5; ++v) q[j][v] = q[j + 1][v];
-        fetch(p, B, t.blk, lx, ly, lz + 2, q[4]);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[4][v] = nq[v];
+        // next plane's column value: in flight while this plane is computed
+        if (iz + 1 < t.nz) fetch(p, B, t.blk, lx, ly, lz + 3, nq);
       } else {
         fetch(p, B, t.blk, lx, ly, lz, q[2]);
       }
@@ -103,7 +120,9 @@ __global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T
     }
     if (arole) {
       T u[5], f[5];
-      fetch(p, B, t.blk, t.x0 + ax, t.y0 + ay, lz, u);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) u[v] = na[v];
+      if (iz + 1 < t.nz) fetch(p, B, t.blk, t.x0 + ax, t.y0 + ay, lz + 1, na);
       if (arole == 1) {
         euler_flux(u, 0, gm1, f);
 #pragma unroll
@@ -114,7 +133,7 @@ __global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T
         for (int v = 0; v < 5; ++v) sG[buf][v][ay + 2][ax] = f[v];
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (act) {
       T R[5];
 #pragma unroll
@@ -134,18 +153,17 @@ __global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T
 #pragma unroll
         for (int v = 0; v < 5; ++v) R[v] -= (T(8) * (h3[v] - h1[v]) - (h4[v] - h0[v])) * ihz;
       }
-      const int gx = B->o[0] + lx, gy = B->o[1] + ly, gz = B->o[2] + lz;
-      const long long g = ((long long)gz * p.n[1] + gy) * p.n[0] + gx;
+      const long long g = g0 + iz * gplane;
       T out[5];
-      epilogue<T, KIND>(p, g, q[2], R, out);
+      epilogue_pre<T, KIND>(p, g, q[2], R, accv, u0v, out);
+      if (iz + 1 < t.nz) epilogue_load<T, KIND>(p, g + gplane, accv, u0v);
       if (ring_slot) ring_store(p, B, lx, ly, lz, out, ring_slot);
     }
   }
 }
 
-template <typename T>
-hipError_t launch_euler_stage(const StageParams<T>& p, int ntiles, int kind, hipStream_t s) {
-  constexpr int TX = 16, TY = 16;
+template <typename T, int TX, int TY>
+hipError_t launch_euler_shape(const StageParams<T>& p, int ntiles, int kind, hipStream_t s) {
   dim3 grid(ntiles), block(TX * TY);
   switch (kind) {
     case kRhsOnly: euler_stage_kernel<T, TX, TY, kRhsOnly><<<grid, block, 0, s>>>(p); break;
@@ -158,7 +176,18 @@ hipError_t launch_euler_stage(const StageParams<T>& p, int ntiles, int kind, hip
   return hipGetLastError();
 }
 
-template hipError_t launch_euler_stage<float>(const StageParams<float>&, int, int, hipStream_t);
-template hipError_t launch_euler_stage<double>(const StageParams<double>&, int, int, hipStream_t);
+// Tile shapes (TX x TY) the Euler kernel is built for.
+template <typename T>
+hipError_t launch_euler_stage(const StageParams<T>& p, int ntiles, int kind, int tx, int ty, hipStream_t s) {
+  if (tx == 16 && ty == 16) return launch_euler_shape<T, 16, 16>(p, ntiles, kind, s);
+  if (tx == 32 && ty == 8) return launch_euler_shape<T, 32, 8>(p, ntiles, kind, s);
+  if (tx == 64 && ty == 4) return launch_euler_shape<T, 64, 4>(p, ntiles, kind, s);
+  if (tx == 16 && ty == 8) return launch_euler_shape<T, 16, 8>(p, ntiles, kind, s);
+  if (tx == 32 && ty == 4) return launch_euler_shape<T, 32, 4>(p, ntiles, kind, s);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_euler_stage<float>(const StageParams<float>&, int, int, int, int, hipStream_t);
+template hipError_t launch_euler_stage<double>(const StageParams<double>&, int, int, int, int, hipStream_t);
 
 }  // namespace atns

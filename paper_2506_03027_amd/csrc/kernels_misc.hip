@@ -39,6 +39,76 @@ hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nbl
   return hipGetLastError();
 }
 
+// Stage halos of one step.  For every halo point of every block and every
+// variable: read the C delayed levels U^{n-k-l} of the neighbour's boundary
+// layer from the ring, and write the s stage values
+//   Uhat^(e) = sum_l W[e][k][l] U^{n-k-l}          (FP64 arithmetic)
+// (AT: buffer extrapolation and RK-consistent updates, Eqs. 7-15; AS: the
+// stale level itself).  One thread per point, consecutive threads on
+// consecutive points of a region, so reads and writes are contiguous runs.
+template <typename T, int S, bool STALE>
+__global__ void __launch_bounds__(kHaloChunk)
+    halo_kernel(const T* __restrict__ ring, T* __restrict__ halo, const HaloRegion* __restrict__ regions,
+                const HaloWork* __restrict__ work, const int8_t* __restrict__ delays,
+                const double* __restrict__ W, long long slot_stride, long long halo_stride, int D,
+                int slot_now, int L) {
+  const HaloWork wk = work[blockIdx.x];
+  const HaloRegion rg = regions[wk.region];
+  const int i = wk.start + threadIdx.x;
+  if (i >= rg.npts) return;
+  const int k = delays[rg.kidx];
+  int sl[kLevels];
+#pragma unroll
+  for (int l = 0; l < kLevels; ++l) {
+    int q = slot_now - k - l;
+    sl[l] = q + ((q < 0) ? D : 0);
+  }
+  for (int v = 0; v < 5; ++v) {
+    const long long so = rg.src + (long long)v * rg.npts + i;
+    const long long dof = rg.dst + (long long)v * rg.npts + i;
+    if (STALE) {
+      const T x = ring[(long long)sl[0] * slot_stride + so];
+#pragma unroll
+      for (int e = 0; e < S; ++e) halo[e * halo_stride + dof] = x;
+      continue;
+    }
+    double lev[kLevels];
+#pragma unroll
+    for (int l = 0; l < kLevels; ++l) lev[l] = (double)ring[(long long)sl[l] * slot_stride + so];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+      const double* w = W + ((long long)e * L + k) * kLevels;
+      double a = 0.0;
+#pragma unroll
+      for (int l = 0; l < kLevels; ++l) a = fma(w[l], lev[l], a);
+      halo[e * halo_stride + dof] = (T)a;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_halo(const T* ring, T* halo, const HaloRegion* regions, const HaloWork* work, int nwork,
+                       const int8_t* delays, const double* W, long long slot_stride, long long halo_stride,
+                       int D, int slot_now, int L, int stages, bool stale, hipStream_t s) {
+  dim3 grid(nwork), block(kHaloChunk);
+#define ATNS_HALO(SS, ST)                                                                               \
+  halo_kernel<T, SS, ST><<<grid, block, 0, s>>>(ring, halo, regions, work, delays, W, slot_stride, \
+                                                 halo_stride, D, slot_now, L)
+  if (stages == 4) {
+    if (stale) ATNS_HALO(4, true); else ATNS_HALO(4, false);
+  } else {
+    if (stale) ATNS_HALO(5, true); else ATNS_HALO(5, false);
+  }
+#undef ATNS_HALO
+  return hipGetLastError();
+}
+template hipError_t launch_halo<float>(const float*, float*, const HaloRegion*, const HaloWork*, int,
+                                       const int8_t*, const double*, long long, long long, int, int, int,
+                                       int, bool, hipStream_t);
+template hipError_t launch_halo<double>(const double*, double*, const HaloRegion*, const HaloWork*, int,
+                                        const int8_t*, const double*, long long, long long, int, int, int,
+                                        int, bool, hipStream_t);
+
 // Copy the boundary layers of every block of field U into ring slot `slot`.
 template <typename T>
 __global__ void ring_fill_kernel(const StageParams<T> p, const T* U, int slot) {

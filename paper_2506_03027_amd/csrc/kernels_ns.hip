@@ -31,9 +31,15 @@ namespace atns {
 template <typename T, int TX, int TY, int KIND, int NDIM>
 __global__ void __launch_bounds__((TX + 8) * (TY + 8)) ns_stage_kernel(const StageParams<T> p) {
   constexpr int EX = TX + 8, EY = TY + 8;
+  constexpr bool three = (NDIM == 3);
   const TileDev t = p.tiles[blockIdx.x];
   if (t.nx == 0) return;
-  const BlockDev* __restrict__ B = p.blocks + t.blk;
+  // The block descriptor lives in LDS for the whole kernel: re-reading it from
+  // global memory inside the plane loop would make every such load wait for
+  // all outstanding (prefetch) loads.
+  __shared__ BlockDev sB;
+  stage_block(p.blocks + t.blk, &sB);
+  const BlockDev* __restrict__ B = &sB;
   const int tid = threadIdx.x;
   const int x = tid % EX - 4, y = tid / EX - 4;   // tile-local, -4 .. T+3
   const int nx = t.nx, ny = t.ny;
@@ -47,7 +53,6 @@ __global__ void __launch_bounds__((TX + 8) * (TY + 8)) ns_stage_kernel(const Sta
                      (dx >= 1 && dx <= 2 && dy >= 1 && dy <= 2);
   const bool grad_pt = core || crossx || crossy;
   const int lx = t.x0 + x, ly = t.y0 + y;
-  constexpr bool three = (NDIM == 3);
 
   const T gm1 = (T)(p.gamma - 1.0);
   const T gM2 = (T)p.mach2_gamma;
@@ -56,39 +61,67 @@ __global__ void __launch_bounds__((TX + 8) * (TY + 8)) ns_stage_kernel(const Sta
   const T ihx = (T)p.inv12h[0], ihy = (T)p.inv12h[1], ihz = (T)p.inv12h[2];
   const T two3 = (T)(2.0 / 3.0);
 
-  __shared__ T sP[4][EY][EX];          // u, v, w, T of plane m
-  __shared__ T sFX[5][TY][TX + 4];     // F - Fv_x/Re on the x-cross of plane m
-  __shared__ T sFY[5][TY + 4][TX];     // G - Fv_y/Re on the y-cross of plane m
+  __shared__ T sP[2][4][EY][EX];        // u, v, w, T of plane m (double-buffered)
+  __shared__ T sFX[2][5][TY][TX + 4];   // F - Fv_x/Re on the x-cross of plane m
+  __shared__ T sFY[2][5][TY + 4][TX];   // G - Fv_y/Re on the y-cross of plane m
+  __shared__ T sAcc[5][5][TY][TX];      // RHS accumulators, plane q at q mod 5
 
   // queues: q*[j] holds plane f-4+j; r*[j] holds plane f-2+j
   T qu[5], qv[5], qw[5], qT[5];
   T rr[3], rp[3], re[3];
-  T acc[5][5];
 #pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    qu[j] = qv[j] = qw[j] = qT[j] = T(0);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) acc[j][v] = T(0);
-  }
+  for (int j = 0; j < 5; ++j) qu[j] = qv[j] = qw[j] = qT[j] = T(0);
 #pragma unroll
   for (int j = 0; j < 3; ++j) rr[j] = rp[j] = re[j] = T(0);
+  if (core) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sAcc[j][v][y][x] = T(0);
+  }
 
   T* ring_slot = nullptr;
   if (p.ring_write) ring_slot = p.ring + (long long)((p.slot_now + 1) % p.D) * p.slot_stride;
 
   const int z0 = t.z0, nz = t.nz;
   const int f_begin = three ? z0 - 4 : 0;
-  const int f_end = three ? z0 + nz + 4 : 1;   // exclusive
-  for (int f = f_begin; f < f_end; ++f) {
-    const int m = three ? f - 2 : f;   // plane whose gradients are formed now
-    // ---------------------------------------------------- 1. fetch plane f
+  // 3D: planes z0-4 .. z0+nz+3 enter; the last tile plane is finished when
+  // plane z0+nz+3 has entered.  2D: one plane, and a second pass for the
+  // x/y divergence, which runs one pass behind the gradients.
+  const int f_end = three ? z0 + nz + 4 : 2;   // exclusive
+  // which planes this thread's point is needed at: the tile and the cross
+  // apron to 2 planes beyond the tile, the tile column to 4 planes beyond,
+  // the outer apron only at tile planes
+  auto need_plane = [&](int f) {
     const int rel = f - z0;
     const bool tileplane = rel >= 0 && rel < nz;
     const bool near = (rel >= -2 && rel < 0) || (rel >= nz && rel < nz + 2);
     const bool far = (rel >= -4 && rel < -2) || (rel >= nz + 2 && rel < nz + 4);
-    const bool need = core ? (tileplane || near || far)
-                           : ((crossx || crossy) ? (tileplane || near) : (outer && tileplane));
-    if (three) {
+    return core ? (tileplane || near || far) : ((crossx || crossy) ? (tileplane || near) : (outer && tileplane));
+  };
+  auto slot5 = [](int q) { return ((q % 5) + 5) % 5; };
+  T nxt[5] = {T(1), T(0), T(0), T(0), T(1)};
+  if (need_plane(f_begin)) fetch(p, B, t.blk, lx, ly, f_begin, nxt);
+  // epilogue operands of the next plane to finish (the tile's first plane)
+  const long long g0 = core ? ((long long)(B->o[2] + z0) * p.n[1] + (B->o[1] + ly)) * p.n[0] + (B->o[0] + lx) : 0;
+  const long long gplane = (long long)p.n[0] * p.n[1];
+  T Yv[5], accv[5], u0v[5];
+  if (core) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + g0];
+    epilogue_load<T, KIND>(p, g0, accv, u0v);
+  }
+
+  for (int f = f_begin; f < f_end; ++f) {
+    const int it = f - f_begin;
+    const int buf = it & 1;
+    const int m = three ? f - 2 : f;   // plane whose gradients are formed now
+    const int mrel = m - z0;
+    const bool m_tile = mrel >= 0 && mrel < nz;
+    const bool m_grad = three ? (mrel >= -2 && mrel < nz + 2) : (mrel == 0);
+    // ---------------------------------------------------- A. plane f in
+    const bool need = (three || f == 0) && need_plane(f);
+    if constexpr (three) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         qu[j] = qu[j + 1];
@@ -106,36 +139,31 @@ __global__ void __launch_bounds__((TX + 8) * (TY + 8)) ns_stage_kernel(const Sta
     constexpr int qi = three ? 4 : 2;   // queue slot of the fetched plane
     constexpr int ri = three ? 2 : 0;
     if (need) {
-      T u[5];
-      fetch(p, B, t.blk, lx, ly, f, u);
-      const T ir = T(1) / u[0];
-      const T vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
-      const T pr = gm1 * (u[4] - T(0.5) * (u[1] * vx + u[2] * vy + u[3] * vz));
+      // plane f was prefetched during the previous iteration
+      const T ir = T(1) / nxt[0];
+      const T vx = nxt[1] * ir, vy = nxt[2] * ir, vz = nxt[3] * ir;
+      const T pr = gm1 * (nxt[4] - T(0.5) * (nxt[1] * vx + nxt[2] * vy + nxt[3] * vz));
       qu[qi] = vx;
       qv[qi] = vy;
       qw[qi] = vz;
       qT[qi] = gM2 * pr * ir;
-      rr[ri] = u[0];
+      rr[ri] = nxt[0];
       rp[ri] = pr;
-      re[ri] = u[4];
+      re[ri] = nxt[4];
     }
-    // ------------------------------------------ 2. plane m into shared memory
-    const int mrel = m - z0;
-    const bool m_tile = mrel >= 0 && mrel < nz;
-    const bool m_grad = three ? (mrel >= -2 && mrel < nz + 2) : true;
-    {
-      const bool has_m = core ? (mrel >= -4 && mrel < nz + 4)
-                              : ((crossx || crossy) ? (mrel >= -2 && mrel < nz + 2) : (outer && m_tile));
-      if (has_m && m_grad) {
-        sP[0][y + 4][x + 4] = qu[2];
-        sP[1][y + 4][x + 4] = qv[2];
-        sP[2][y + 4][x + 4] = qw[2];
-        sP[3][y + 4][x + 4] = qT[2];
+    // issue the loads of plane f + 1; they complete behind this plane's work
+    if (three && f + 1 < f_end && need_plane(f + 1)) fetch(p, B, t.blk, lx, ly, f + 1, nxt);
+    if (m_grad) {
+      const bool has_m = core || ((crossx || crossy) && (mrel >= -2 && mrel < nz + 2)) || (outer && m_tile);
+      if (has_m) {
+        sP[buf][0][y + 4][x + 4] = qu[2];
+        sP[buf][1][y + 4][x + 4] = qv[2];
+        sP[buf][2][y + 4][x + 4] = qw[2];
+        sP[buf][3][y + 4][x + 4] = qT[2];
       }
     }
-    __syncthreads();
-    // ------------------------------------------- 3. gradients and fluxes
-    T zf[5];
+    lds_barrier();
+    // ------------------------------------- B. gradients and fluxes of plane m
     if (m_grad && (core || (m_tile && grad_pt))) {
       const int sx = x + 4, sy = y + 4;
       T g[3][3], gT[3];   // g[i][j] = d u_i / d x_j
@@ -148,8 +176,10 @@ __global__ void __launch_bounds__((TX + 8) * (TY + 8)) ns_stage_kernel(const Sta
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const T ddx = (T(8) * (sP[c][sy][sx + 1] - sP[c][sy][sx - 1]) - (sP[c][sy][sx + 2] - sP[c][sy][sx - 2])) * ihx;
-        const T ddy = (T(8) * (sP[c][sy + 1][sx] - sP[c][sy - 1][sx]) - (sP[c][sy + 2][sx] - sP[c][sy - 2][sx])) * ihy;
+        const T ddx = (T(8) * (sP[buf][c][sy][sx + 1] - sP[buf][c][sy][sx - 1]) -
+                       (sP[buf][c][sy][sx + 2] - sP[buf][c][sy][sx - 2])) * ihx;
+        const T ddy = (T(8) * (sP[buf][c][sy + 1][sx] - sP[buf][c][sy - 1][sx]) -
+                       (sP[buf][c][sy + 2][sx] - sP[buf][c][sy - 2][sx])) * ihy;
         if (c < 3) {
           g[c][0] = ddx;
           g[c][1] = ddy;
@@ -181,63 +211,73 @@ __global__ void __launch_bounds__((TX + 8) * (TY + 8)) ns_stage_kernel(const Sta
         if (core || crossx) {
           flux(0, fl);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) sFX[v][y][x + 2] = fl[v];
+          for (int v = 0; v < 5; ++v) sFX[buf][v][y][x + 2] = fl[v];
         }
         if (core || crossy) {
           flux(1, fl);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) sFY[v][y + 2][x] = fl[v];
+          for (int v = 0; v < 5; ++v) sFY[buf][v][y + 2][x] = fl[v];
         }
       }
-      if (core && three) flux(2, zf);
-    }
-    if (core && three && m_grad) {
-      // z-divergence contributions of plane m to planes m-2 .. m+2
+      if constexpr (three) {
+        if (core) {
+          // z-divergence contributions of plane m to planes m-2 .. m+2
+          T zf[5];
+          flux(2, zf);
+          // only planes of the tile accumulate (the slots are recycled)
+          const bool t0 = mrel - 2 >= 0 && mrel - 2 < nz, t1 = mrel - 1 >= 0 && mrel - 1 < nz;
+          const bool t3 = mrel + 1 >= 0 && mrel + 1 < nz, t4 = mrel + 2 >= 0 && mrel + 2 < nz;
+          const int a0 = slot5(m - 2), a1 = slot5(m - 1), a3 = slot5(m + 1), a4 = slot5(m + 2);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const T z = zf[v] * ihz;
-        acc[0][v] += z;
-        acc[1][v] -= T(8) * z;
-        acc[3][v] += T(8) * z;
-        acc[4][v] -= z;
+          for (int v = 0; v < 5; ++v) {
+            const T z = zf[v] * ihz;
+            if (t0) sAcc[a0][v][y][x] += z;
+            if (t1) sAcc[a1][v][y][x] -= T(8) * z;
+            if (t3) sAcc[a3][v][y][x] += T(8) * z;
+            if (t4) sAcc[a4][v][y][x] -= z;
+          }
+        }
       }
     }
-    __syncthreads();
-    // -------------------------------------------- 4. x and y divergence
-    if (core && m_tile) {
-      constexpr int ai = three ? 2 : 0;
+    // ------------------------- C. x and y divergence of plane m - 1 (3D) / m (2D)
+    const int dm = m - 1;
+    const int dbuf = buf ^ 1;
+    if (core && (dm - z0) >= 0 && (dm - z0) < nz) {
+      const int a = slot5(dm);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        const T ddx = (T(8) * (sFX[v][y][x + 3] - sFX[v][y][x + 1]) - (sFX[v][y][x + 4] - sFX[v][y][x])) * ihx;
-        const T ddy = (T(8) * (sFY[v][y + 3][x] - sFY[v][y + 1][x]) - (sFY[v][y + 4][x] - sFY[v][y][x])) * ihy;
-        acc[ai][v] -= ddx + ddy;
+        const T ddx = (T(8) * (sFX[dbuf][v][y][x + 3] - sFX[dbuf][v][y][x + 1]) -
+                       (sFX[dbuf][v][y][x + 4] - sFX[dbuf][v][y][x])) * ihx;
+        const T ddy = (T(8) * (sFY[dbuf][v][y + 3][x] - sFY[dbuf][v][y + 1][x]) -
+                       (sFY[dbuf][v][y + 4][x] - sFY[dbuf][v][y][x])) * ihy;
+        sAcc[a][v][y][x] -= ddx + ddy;
       }
     }
-    // --------------------------------------------- 5. finish plane m - 2
-    const int pz = three ? m - 2 : m;
+    // ------------------------------------------------- D. finish plane pz
+    const int pz = three ? m - 2 : m - 1;
     if (core && pz >= z0 && pz < z0 + nz) {
-      const int gx = B->o[0] + lx, gy = B->o[1] + ly, gz = B->o[2] + pz;
-      const long long gi = ((long long)gz * p.n[1] + gy) * p.n[0] + gx;
-      T Y[5], out[5];
+      const int a = slot5(pz);
+      T R[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Y[v] = p.Y[v * p.field + gi];
-      epilogue<T, KIND>(p, gi, Y, acc[0], out);
+      for (int v = 0; v < 5; ++v) {
+        R[v] = sAcc[a][v][y][x];
+        sAcc[a][v][y][x] = T(0);   // the slot is reused for plane pz + 5
+      }
+      const long long gi = g0 + (pz - z0) * gplane;
+      T out[5];
+      epilogue_pre<T, KIND>(p, gi, Yv, R, accv, u0v, out);
+      if (pz + 1 < z0 + nz) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + gi + gplane];
+        epilogue_load<T, KIND>(p, gi + gplane, accv, u0v);
+      }
       if (ring_slot) ring_store(p, B, lx, ly, pz, out, ring_slot);
-    }
-    if (three) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int v = 0; v < 5; ++v) acc[j][v] = acc[j + 1][v];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) acc[4][v] = T(0);
     }
   }
 }
 
-template <typename T, int KIND>
+template <typename T, int KIND, int TX, int TY>
 hipError_t launch_ns_kind(const StageParams<T>& p, int ntiles, hipStream_t s) {
-  constexpr int TX = 16, TY = 16;
   dim3 grid(ntiles), block((TX + 8) * (TY + 8));
   if (p.ndim == 3)
     ns_stage_kernel<T, TX, TY, KIND, 3><<<grid, block, 0, s>>>(p);
@@ -246,19 +286,28 @@ hipError_t launch_ns_kind(const StageParams<T>& p, int ntiles, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_ns_stage(const StageParams<T>& p, int ntiles, int kind, hipStream_t s) {
+template <typename T, int TX, int TY>
+hipError_t launch_ns_shape(const StageParams<T>& p, int ntiles, int kind, hipStream_t s) {
   switch (kind) {
-    case kRhsOnly: return launch_ns_kind<T, kRhsOnly>(p, ntiles, s);
-    case kRK4First: return launch_ns_kind<T, kRK4First>(p, ntiles, s);
-    case kRK4Mid: return launch_ns_kind<T, kRK4Mid>(p, ntiles, s);
-    case kRK4Last: return launch_ns_kind<T, kRK4Last>(p, ntiles, s);
-    case kLSFirst: return launch_ns_kind<T, kLSFirst>(p, ntiles, s);
-    default: return launch_ns_kind<T, kLSMid>(p, ntiles, s);
+    case kRhsOnly: return launch_ns_kind<T, kRhsOnly, TX, TY>(p, ntiles, s);
+    case kRK4First: return launch_ns_kind<T, kRK4First, TX, TY>(p, ntiles, s);
+    case kRK4Mid: return launch_ns_kind<T, kRK4Mid, TX, TY>(p, ntiles, s);
+    case kRK4Last: return launch_ns_kind<T, kRK4Last, TX, TY>(p, ntiles, s);
+    case kLSFirst: return launch_ns_kind<T, kLSFirst, TX, TY>(p, ntiles, s);
+    default: return launch_ns_kind<T, kLSMid, TX, TY>(p, ntiles, s);
   }
 }
 
-template hipError_t launch_ns_stage<float>(const StageParams<float>&, int, int, hipStream_t);
-template hipError_t launch_ns_stage<double>(const StageParams<double>&, int, int, hipStream_t);
+// Tile shapes (TX x TY) the Navier-Stokes kernel is built for.
+template <typename T>
+hipError_t launch_ns_stage(const StageParams<T>& p, int ntiles, int kind, int tx, int ty, hipStream_t s) {
+  if (tx == 16 && ty == 16) return launch_ns_shape<T, 16, 16>(p, ntiles, kind, s);
+  if (tx == 32 && ty == 8) return launch_ns_shape<T, 32, 8>(p, ntiles, kind, s);
+  if (tx == 16 && ty == 8) return launch_ns_shape<T, 16, 8>(p, ntiles, kind, s);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_ns_stage<float>(const StageParams<float>&, int, int, int, int, hipStream_t);
+template hipError_t launch_ns_stage<double>(const StageParams<double>&, int, int, int, int, hipStream_t);
 
 }  // namespace atns

@@ -50,10 +50,28 @@ __host__ __device__ inline int slot_opposite(int s) {
 }
 
 struct BlockDev {
-  int o[3];                 // origin (global index of local (0,0,0))
-  int s[3];                 // size
-  int nbr[kNumSlots];       // neighbour block in each slot direction
-  long long lay[kNumSlots]; // offset of this block's layer for slot s (-1: unused)
+  int o[3];                  // origin (global index of local (0,0,0))
+  int s[3];                  // size
+  int nbr[kNumSlots];        // neighbour block in each slot direction
+  long long lay[kNumSlots];  // offset of this block's layer for slot s (-1: unused)
+  long long hoff[kNumSlots]; // offset of this block's halo region s in a
+                             // stage-halo buffer (-1: unused)
+};
+
+// One reader-side halo region: block b's halo in slot direction s, which is
+// the layer opposite(s) of neighbour nbr[b][s] (same extents and order).
+struct HaloRegion {
+  long long dst;   // offset in a stage-halo buffer
+  long long src;   // offset of the neighbour's layer in a ring slot
+  int npts;        // points per variable
+  int kidx;        // index of the delay: b * kNumSlots + s
+};
+
+// A chunk of up to kHaloChunk consecutive points of one region.
+constexpr int kHaloChunk = 256;
+struct HaloWork {
+  int region;
+  int start;
 };
 
 struct TileDev {
@@ -81,10 +99,9 @@ struct StageParams {
   T* Yout;             // next stage input / final state
   T* acc;              // RK4 accumulator / LSERK Q register
   T* ring;             // ring base
+  const T* hbuf;       // this stage's halo values (reader-side layout)
   const BlockDev* blocks;
   const TileDev* tiles;
-  const int8_t* delays;  // [nblocks][18] of this step
-  const double* W;       // this stage's weights [L][C]
   int n[3];              // global sizes
   long long field;       // nx*ny*nz, the variable stride
   long long slot_stride; // elements per ring slot
