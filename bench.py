@@ -110,6 +110,50 @@ def gpu_run(torch, w, precision, mode, steps, warmup, U0, dt):
     return ms, launches, kms, finite, tiles
 
 
+PROBE_BYTES = 1 << 30
+
+
+def hbm_probe(torch, reps=10):
+    """Achievable HBM bandwidth from the library's streaming copy of 1 GiB
+    (read + write counted)."""
+    src = torch.empty(PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    atns.hbm_probe(src, dst, PROBE_BYTES)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        atns.hbm_probe(src, dst, PROBE_BYTES)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_per_launch": 2 * PROBE_BYTES, "ms": ms, "GBps": 2 * PROBE_BYTES / (ms * 1e-3) / 1e9}
+
+
+def kernel_source_hash():
+    """Hash of the kernel sources: stored counter results apply only to it."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2506_03027_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload):
+    """Per-launch HBM traffic of the stage kernel from the committed counter
+    summary, if it was taken with the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def cpu_baseline(torch, w, budget_s=20.0):
     """The FP64 oracle on a bounded sample of the workload: the same block
     shape and halo scheme on a smaller grid, started from a delayed history
@@ -209,12 +253,16 @@ def main():
                    "algo": w.get("algo", "saa").upper(), "L": w["L"], "cfl": w["cfl"],
                    "tiles": list(tiles)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(a.workload),
                      "kernel": "%s_stage_kernel" % ("ns" if w["physics"] == "ns" else "euler"),
                      "bytes_per_point_stage": bpp, "halo_points_per_point": f,
                      "avg_launch_ms": avg_launch_ms, "launches": launches},
         "finite": finite,
     }
+    probe = hbm_probe(torch)
+    out["hbm_probe"] = probe
+    out["roofline"]["frac_of_probe"] = achieved / probe["GBps"]
+    out["kernel_hash"] = kernel_source_hash()
     if not a.no_fp64:
         ms64, l64, k64, fin64, _ = gpu_run(torch, w, atns.F64, "sa", a.steps, warmup, U0, dt)
         b64, _ = algorithmic_bytes_per_point_stage(dict(w, mode="sa"), stages, 8)

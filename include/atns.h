@@ -186,6 +186,49 @@ atns_status atns_get_tiles(const atns_ctx* ctx, int32_t* tx, int32_t* ty, int32_
  * chosen shape.  Synchronizes; ESTATE before a state is set. */
 atns_status atns_autotune(atns_ctx* ctx, int32_t reps, const char* cache_path, int32_t* best_txyz);
 
+/* ---- learned halo correction (an addition to the paper's method) --------
+ * A 64-64-64-16 MLP (ReLU, BF16 operands on the matrix cores, FP32
+ * accumulation) predicts, for each face halo point, the error of the AT
+ * buffer extrapolation (Eq. 15) from the delayed levels the extrapolation
+ * reads: features (U^{n-k-l}_v(p) - U^{n-k}_v(x)) / s_v for the 4 newest
+ * levels l, the 5 variables v and the point x with its two neighbours p
+ * along the face normal (60 values), then k/(L-1), then 3 zeros.  The
+ * correction delta_v = r_v out_v is added to every stage halo value of the
+ * point, unless |out_1..5|_2 > tau, when the AT value is kept (fallback).
+ * Parameters: float[9360] = W1[64][64] b1[64] W2[64][64] b2[64] W3[16][64]
+ * b3[16], row-major [out][in].  Training samples come from the context's
+ * ring (an AT run, or an SA run created with L > 1, which keeps a history):
+ * a random face halo point and delay k, target (U^n - Uhat_AT^(0)) / r_v.
+ * X arrays are float[n][64], Y arrays float[n][8] (first 5 used). */
+atns_status atns_mlp_set_params(atns_ctx* ctx, const float* host_params);
+atns_status atns_mlp_get_params(atns_ctx* ctx, float* host_params);
+/* Per-variable feature scales s_v and target scales r_v (positive). */
+atns_status atns_mlp_set_scales(atns_ctx* ctx, const float* feat_scale5, const float* targ_scale5);
+/* Outputs float[n][16] of the network for inputs dev_X (device). */
+atns_status atns_mlp_forward(atns_ctx* ctx, const float* dev_X, int32_t n, float* dev_out);
+/* Gradient (float[9360], device) and loss (mean over samples and the 5 used
+ * outputs of the squared error) for one batch; deterministic. */
+atns_status atns_mlp_grad(atns_ctx* ctx, const float* dev_X, const float* dev_Y, int32_t n, float* dev_grad,
+                          double* host_loss);
+/* n training samples (features, targets) from the current history with a
+ * SplitMix64 stream seeded by `seed`.  ESTATE without a long enough ring. */
+atns_status atns_mlp_sample(atns_ctx* ctx, int32_t n, uint64_t seed, float* dev_X, float* dev_Y);
+/* `iters` Adam steps (beta 0.9/0.999, eps 1e-8) on fresh batches of `batch`
+ * (>= 64) samples from the current history; host_losses (or NULL) receives
+ * each batch's loss before its update.  Synchronizes. */
+atns_status atns_mlp_train(atns_ctx* ctx, int32_t iters, int32_t batch, double lr, uint64_t seed,
+                           double* host_losses);
+/* Use the correction in every asynchronous step (mode ATNS_AT only). */
+atns_status atns_mlp_enable(atns_ctx* ctx, int32_t on, double tau);
+/* Corrected and fallback face-halo points since the last call (resets). */
+atns_status atns_mlp_stats(atns_ctx* ctx, int64_t* applied, int64_t* fallback);
+
+/* HBM probe: enqueue a plain streaming copy of `bytes` (a positive multiple
+ * of 16) from dev_src to dev_dst on `stream` (hipStream_t or NULL).  Times
+ * the achievable bandwidth and calibrates byte counters.  Buffers are the
+ * caller's; nothing is allocated.  Asynchronous. */
+atns_status atns_hbm_probe(const void* dev_src, void* dev_dst, int64_t bytes, void* stream);
+
 /* ---- host-only helpers (no device needed) -------------------------------
  * The FP64 per-stage halo weight table the kernels use: out[e][k][l] for
  * stages e < s (s = 4 for RK4, 5 for LSERK4), delays k < L and levels

@@ -147,6 +147,8 @@ class Oracle:
         self.U = None
         self.overrides = {}
         self.halo = "closed"
+        self.mlp = None        # dict(theta, s, r, tau) for the learned halo correction
+        self.mlp_counts = [0, 0]
         if cfg.mode in (atmod.AT, atmod.AS):
             self.W = atmod.halo_table(cfg.rk, cfg.mode, cfg.C, cfg.L - 1)
         # float coefficients for the literal Eq. (8) recursion
@@ -194,6 +196,18 @@ class Oracle:
                     w = self.W[e, kk, l]
                     if w != 0.0:
                         vals = vals + w * self.history[self.n - kk - l][gidx]
+                if self.mlp is not None and cfg.mode == atmod.AT and v < 6:
+                    key = ("mlp", b, v)
+                    if key not in bufs:
+                        from . import mlp as mlpmod
+                        m = self.mlp
+                        bufs[key] = mlpmod.correction_for_region(
+                            m["theta"], m["s"], m["r"], m["tau"], self.history, self.n, kk, cfg.L,
+                            self.blocks, b, v, cfg.H)
+                        ok = bufs[key][1]
+                        self.mlp_counts[0] += int(ok.sum())
+                        self.mlp_counts[1] += int((~ok).sum())
+                    vals = vals + bufs[key][0]
             zr = rng[2] + hz
             yr = rng[1] + H
             xr = rng[0] + H

@@ -28,7 +28,10 @@ EXPORTS = ["atns_version", "atns_create", "atns_destroy", "atns_last_error", "at
            "atns_get_state", "atns_get_step", "atns_set_dt", "atns_set_delays", "atns_get_delays",
            "atns_rhs", "atns_rk_step", "atns_reduce", "atns_get_layout", "atns_profile_enable",
            "atns_profile_read", "atns_set_tiles", "atns_get_tiles", "atns_autotune",
-           "atns_host_weights", "atns_host_delays"]
+           "atns_mlp_set_params", "atns_mlp_get_params", "atns_mlp_set_scales", "atns_mlp_forward",
+           "atns_mlp_grad", "atns_mlp_sample", "atns_mlp_train", "atns_mlp_enable", "atns_mlp_stats",
+           "atns_hbm_probe", "atns_host_weights", "atns_host_delays"]
+MLP_PARAMS = 9360
 
 
 class AtnsError(RuntimeError):
@@ -76,6 +79,16 @@ def lib():
             "atns_set_tiles": ([vp, i32, i32, i32], i32),
             "atns_get_tiles": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
             "atns_autotune": ([vp, i32, ctypes.c_char_p, vp], i32),
+            "atns_hbm_probe": ([vp, vp, i64, vp], i32),
+            "atns_mlp_set_params": ([vp, vp], i32),
+            "atns_mlp_get_params": ([vp, vp], i32),
+            "atns_mlp_set_scales": ([vp, vp, vp], i32),
+            "atns_mlp_forward": ([vp, vp, i32, vp], i32),
+            "atns_mlp_grad": ([vp, vp, vp, i32, vp, ctypes.POINTER(dbl)], i32),
+            "atns_mlp_sample": ([vp, i32, ctypes.c_uint64, vp, vp], i32),
+            "atns_mlp_train": ([vp, i32, i32, dbl, ctypes.c_uint64, vp], i32),
+            "atns_mlp_enable": ([vp, i32, dbl], i32),
+            "atns_mlp_stats": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
             "atns_host_weights": ([i32, i32, i32, vp], i32),
             "atns_host_delays": ([i32, i64, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(i32)], i32),
         }
@@ -91,6 +104,12 @@ def _check(status, ctx=None):
     if status != 0:
         msg = lib().atns_last_error(ctx).decode()
         raise AtnsError(status, msg)
+
+
+def hbm_probe(src, dst, nbytes, stream=None):
+    """Enqueue the library's streaming copy of nbytes from tensor src to dst."""
+    _check(lib().atns_hbm_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                int(nbytes), stream))
 
 
 def host_weights(rk, mode, L):
@@ -227,6 +246,65 @@ class Solver:
         path = cache.encode() if cache else None
         _check(lib().atns_autotune(self.ctx, int(reps), path, best.ctypes.data), self.ctx)
         return tuple(int(x) for x in best)
+
+    # ---------------------------------------------------- learned halo
+    def mlp_set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.size != MLP_PARAMS:
+            raise ValueError("expected %d parameters" % MLP_PARAMS)
+        _check(lib().atns_mlp_set_params(self.ctx, th.ctypes.data), self.ctx)
+
+    def mlp_get_params(self):
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(lib().atns_mlp_get_params(self.ctx, out.ctypes.data), self.ctx)
+        return out
+
+    def mlp_set_scales(self, feat_scale, targ_scale):
+        fs = np.ascontiguousarray(feat_scale, dtype=np.float32)
+        ts = np.ascontiguousarray(targ_scale, dtype=np.float32)
+        _check(lib().atns_mlp_set_scales(self.ctx, fs.ctypes.data, ts.ctypes.data), self.ctx)
+
+    def mlp_forward(self, X):
+        X = X.to(device="cuda", dtype=self.torch.float32).contiguous()
+        out = self.torch.empty((X.shape[0], 16), dtype=self.torch.float32, device="cuda")
+        self.torch.cuda.synchronize()
+        _check(lib().atns_mlp_forward(self.ctx, ctypes.c_void_p(X.data_ptr()), X.shape[0],
+                                      ctypes.c_void_p(out.data_ptr())), self.ctx)
+        self.torch.cuda.synchronize()
+        return out
+
+    def mlp_grad(self, X, Y):
+        X = X.to(device="cuda", dtype=self.torch.float32).contiguous()
+        Y = Y.to(device="cuda", dtype=self.torch.float32).contiguous()
+        g = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device="cuda")
+        loss = ctypes.c_double()
+        self.torch.cuda.synchronize()
+        _check(lib().atns_mlp_grad(self.ctx, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                   X.shape[0], ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss)), self.ctx)
+        self.torch.cuda.synchronize()
+        return g, loss.value
+
+    def mlp_sample(self, n, seed):
+        X = self.torch.empty((n, 64), dtype=self.torch.float32, device="cuda")
+        Y = self.torch.empty((n, 8), dtype=self.torch.float32, device="cuda")
+        _check(lib().atns_mlp_sample(self.ctx, int(n), ctypes.c_uint64(seed), ctypes.c_void_p(X.data_ptr()),
+                                     ctypes.c_void_p(Y.data_ptr())), self.ctx)
+        self.torch.cuda.synchronize()
+        return X, Y
+
+    def mlp_train(self, iters, batch, lr, seed):
+        losses = np.zeros(iters, dtype=np.float64)
+        _check(lib().atns_mlp_train(self.ctx, int(iters), int(batch), float(lr), ctypes.c_uint64(seed),
+                                    losses.ctypes.data), self.ctx)
+        return losses
+
+    def mlp_enable(self, on, tau=1e30):
+        _check(lib().atns_mlp_enable(self.ctx, 1 if on else 0, float(tau)), self.ctx)
+
+    def mlp_stats(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().atns_mlp_stats(self.ctx, ctypes.byref(a), ctypes.byref(b)), self.ctx)
+        return a.value, b.value
 
     def reduce(self):
         out = np.zeros(NDIAG, dtype=np.float64)

@@ -12,6 +12,7 @@
 #include "coeffs.hpp"
 #include "launch.hpp"
 #include "layout.hpp"
+#include "mlp.hpp"
 
 using namespace atns;
 
@@ -51,6 +52,31 @@ struct atns_ctx {
   HaloWork* d_work = nullptr;
   int nwork = 0;
   int tile[3] = {16, 16, 16};        // stage-kernel tile shape TX, TY, TZ
+  // learned halo correction
+  std::vector<FaceInfo> faceinfo;    // per halo region (faces meaningful)
+  std::vector<int> face_regions;     // ids of face regions
+  std::vector<HaloWork> face_chunks; // 16-point chunks of face regions
+  FaceInfo* d_faceinfo = nullptr;
+  int* d_face_regions = nullptr;
+  HaloWork* d_face_chunks = nullptr;
+  double* d_W0at = nullptr;          // AT stage-0 weights [L][C] (sampler target)
+  MlpNet net{nullptr, nullptr, nullptr, nullptr};
+  float* d_adam_m = nullptr;
+  float* d_adam_v = nullptr;
+  int adam_t = 0;
+  float* d_grad = nullptr;
+  float* d_part = nullptr;           // per-workgroup partial gradients
+  float* d_loss_part = nullptr;
+  float* d_loss = nullptr;
+  float* d_X = nullptr;              // training batch
+  float* d_Y = nullptr;
+  int batch_cap = 0;
+  unsigned long long* d_counters = nullptr;
+  float mlp_s[5] = {1, 1, 1, 1, 1};
+  float mlp_r[5] = {1, 1, 1, 1, 1};
+  double mlp_tau = 1e30;
+  bool mlp_on = false;
+  bool mlp_ready = false;
   double* d_partials = nullptr;
   double* d_diag = nullptr;
   int nparts = 1024;
@@ -203,6 +229,14 @@ void build_layout(atns_ctx* c) {
       const int rid = (int)c->regions.size();
       c->regions.push_back(r);
       for (int st = 0; st < (int)cnt; st += kHaloChunk) c->work.push_back(HaloWork{rid, st});
+      FaceInfo fi;
+      fi.axis = dir[0] ? 0 : (dir[1] ? 1 : 2);
+      for (int d = 0; d < 3; ++d) fi.ext[d] = dir[d] ? dep : B.s[d];
+      c->faceinfo.push_back(fi);
+      if (s < 6) {
+        c->face_regions.push_back(rid);
+        for (int st = 0; st < (int)cnt; st += kMlpChunk) c->face_chunks.push_back(HaloWork{rid, st});
+      }
       hoff += 5 * cnt;
     }
   }
@@ -337,6 +371,23 @@ atns_status draw_delays(atns_ctx* c, int64_t step, int8_t* dst) {
   return ATNS_OK;
 }
 
+template <typename T>
+MlpFeatArgs<T> feat_args(const atns_ctx* c) {
+  MlpFeatArgs<T> fa{};
+  fa.ring = (const T*)c->ring;
+  fa.slot_stride = c->slot_stride;
+  fa.D = c->D;
+  fa.slot_now = c->D ? (int)(c->step % c->D) : 0;
+  fa.L = c->cfg.L;
+  for (int v = 0; v < 5; ++v) {
+    fa.inv_s[v] = 1.f / c->mlp_s[v];
+    fa.inv_r[v] = 1.f / c->mlp_r[v];
+    fa.r[v] = c->mlp_r[v];
+  }
+  fa.tau2 = (float)std::min(c->mlp_tau * c->mlp_tau, 1e30);
+  return fa;
+}
+
 // Delay draw and stage-halo assembly of the current step (asynchronous steps).
 template <typename T>
 atns_status prepare_halos(atns_ctx* c) {
@@ -346,6 +397,12 @@ atns_status prepare_halos(atns_ctx* c) {
                             c->d_delays, c->d_W, c->slot_stride, c->slot_stride, c->D,
                             (int)(c->step % c->D), c->cfg.L, c->rk.stages, c->cfg.mode == ATNS_AS,
                             c->stream));
+  if (c->mlp_on && c->cfg.mode == ATNS_AT) {
+    MlpFeatArgs<T> fa = feat_args<T>(c);
+    HIP_TRY(c, mlp_halo<T>(fa, c->net, c->d_regions, c->d_faceinfo, c->d_face_chunks,
+                           (long long)c->face_chunks.size(), c->d_delays, (T*)c->hbuf, c->slot_stride,
+                           c->rk.stages, c->d_counters, c->stream));
+  }
   return ATNS_OK;
 }
 
@@ -405,7 +462,10 @@ void release(atns_ctx* c) {
       x = nullptr;
     }
   void* ptrs[] = {c->ring, c->d_blocks, c->d_tiles, c->d_delays, c->d_probe, c->d_inject, c->d_W,
-                  c->d_partials, c->d_diag, c->hbuf, c->d_regions, c->d_work};
+                  c->d_partials, c->d_diag, c->hbuf, c->d_regions, c->d_work, c->d_faceinfo,
+                  c->d_face_regions, c->d_face_chunks, c->d_W0at, c->net.params, c->net.w1, c->net.w2,
+                  c->net.w3, c->d_adam_m, c->d_adam_v, c->d_grad, c->d_part, c->d_loss_part, c->d_loss,
+                  c->d_X, c->d_Y, c->d_counters};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   c->ring = nullptr;
@@ -444,7 +504,9 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
   build_layout(c);
   default_tiles(c);
   build_tiles(c, c->tile[0], c->tile[1], c->tile[2]);
-  c->D = cfg->mode == ATNS_SA ? 0 : kC + cfg->L;
+  // SA keeps a delayed-level ring only when L > 1 (history for the learned
+  // halo's training samples); the asynchronous modes always do.
+  c->D = (cfg->mode == ATNS_SA && cfg->L <= 1) ? 0 : kC + cfg->L;
 
   auto fail_free = [&](atns_status s, const std::string& m) {
     release(c);
@@ -459,8 +521,26 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
   if (c->D) {
     if (hipMalloc(&c->ring, (size_t)c->slot_stride * c->D * c->esz) != hipSuccess)
       return fail_free(ATNS_ENOMEM, "ring allocation failed");
-    if (hipMalloc(&c->hbuf, (size_t)c->slot_stride * c->rk.stages * c->esz) != hipSuccess)
+    if (cfg->mode != ATNS_SA &&
+        hipMalloc(&c->hbuf, (size_t)c->slot_stride * c->rk.stages * c->esz) != hipSuccess)
       return fail_free(ATNS_ENOMEM, "halo buffer allocation failed");
+    {
+      const std::vector<double> W0 = halo_weights(cfg->rk, ATNS_AT, cfg->L);   // stage 0 = first L*C entries
+      if (hipMalloc((void**)&c->d_W0at, (size_t)cfg->L * kC * sizeof(double)) != hipSuccess ||
+          hipMemcpy(c->d_W0at, W0.data(), (size_t)cfg->L * kC * sizeof(double), hipMemcpyHostToDevice) !=
+              hipSuccess)
+        return fail_free(ATNS_EHIP, "weight table upload failed");
+      if (hipMalloc((void**)&c->d_faceinfo, c->faceinfo.size() * sizeof(FaceInfo)) != hipSuccess ||
+          hipMemcpy(c->d_faceinfo, c->faceinfo.data(), c->faceinfo.size() * sizeof(FaceInfo),
+                    hipMemcpyHostToDevice) != hipSuccess ||
+          hipMalloc((void**)&c->d_face_regions, c->face_regions.size() * sizeof(int)) != hipSuccess ||
+          hipMemcpy(c->d_face_regions, c->face_regions.data(), c->face_regions.size() * sizeof(int),
+                    hipMemcpyHostToDevice) != hipSuccess ||
+          hipMalloc((void**)&c->d_face_chunks, c->face_chunks.size() * sizeof(HaloWork)) != hipSuccess ||
+          hipMemcpy(c->d_face_chunks, c->face_chunks.data(), c->face_chunks.size() * sizeof(HaloWork),
+                    hipMemcpyHostToDevice) != hipSuccess)
+        return fail_free(ATNS_EHIP, "face table upload failed");
+    }
     if (hipMalloc((void**)&c->d_regions, c->regions.size() * sizeof(HaloRegion)) != hipSuccess ||
         hipMalloc((void**)&c->d_work, c->work.size() * sizeof(HaloWork)) != hipSuccess ||
         hipMemcpy(c->d_regions, c->regions.data(), c->regions.size() * sizeof(HaloRegion),
@@ -789,6 +869,189 @@ atns_status atns_autotune(atns_ctx* c, int32_t reps, const char* cache_path, int
     best[1] = pick[1];
     best[2] = pick[2];
   }
+  return ATNS_OK;
+}
+
+namespace {
+
+atns_status mlp_alloc(atns_ctx* c) {
+  if (c->net.params) return ATNS_OK;
+  const size_t pb = kMlpParams * sizeof(float);
+  if (hipMalloc((void**)&c->net.params, pb) != hipSuccess ||
+      hipMalloc((void**)&c->net.w1, kMlpH * kMlpIn * 2) != hipSuccess ||
+      hipMalloc((void**)&c->net.w2, kMlpH * kMlpH * 2) != hipSuccess ||
+      hipMalloc((void**)&c->net.w3, kMlpOut * kMlpH * 2) != hipSuccess ||
+      hipMalloc((void**)&c->d_adam_m, pb) != hipSuccess || hipMalloc((void**)&c->d_adam_v, pb) != hipSuccess ||
+      hipMalloc((void**)&c->d_grad, pb) != hipSuccess || hipMalloc((void**)&c->d_loss, sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&c->d_counters, 2 * sizeof(unsigned long long)) != hipSuccess)
+    return fail(c, ATNS_ENOMEM, "MLP allocation failed");
+  HIP_TRY(c, hipMemsetAsync(c->d_adam_m, 0, pb, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_adam_v, 0, pb, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_counters, 0, 2 * sizeof(unsigned long long), c->stream));
+  return ATNS_OK;
+}
+
+atns_status mlp_batch(atns_ctx* c, int n) {
+  const int nparts = (n + 63) / 64;
+  if (n <= c->batch_cap) return ATNS_OK;
+  for (float** p : {&c->d_part, &c->d_loss_part, &c->d_X, &c->d_Y})
+    if (*p) {
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+  if (hipMalloc((void**)&c->d_part, (size_t)nparts * kMlpParams * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&c->d_loss_part, (size_t)nparts * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&c->d_X, (size_t)n * kMlpIn * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&c->d_Y, (size_t)n * 8 * sizeof(float)) != hipSuccess)
+    return fail(c, ATNS_ENOMEM, "MLP batch allocation failed");
+  c->batch_cap = n;
+  return ATNS_OK;
+}
+
+atns_status mlp_need(atns_ctx* c) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  if (!c->mlp_ready) return fail(c, ATNS_ESTATE, "MLP parameters not set");
+  return ATNS_OK;
+}
+
+atns_status sample_into(atns_ctx* c, int n, uint64_t seed, float* X, float* Y) {
+  if (!c->ring) return fail(c, ATNS_ESTATE, "no delayed-level history (SA with L = 1)");
+  if (c->face_regions.empty()) return fail(c, ATNS_ESTATE, "no face halos");
+  if (c->step < kC + c->cfg.L - 1) return fail(c, ATNS_ESTATE, "history shorter than C + L - 1 levels");
+  if (c->esz == 4) {
+    MlpFeatArgs<float> fa = feat_args<float>(c);
+    HIP_TRY(c, mlp_sample<float>(fa, c->d_regions, c->d_faceinfo, c->d_face_regions, (int)c->face_regions.size(),
+                                 c->d_W0at, seed, n, X, Y, c->stream));
+  } else {
+    MlpFeatArgs<double> fa = feat_args<double>(c);
+    HIP_TRY(c, mlp_sample<double>(fa, c->d_regions, c->d_faceinfo, c->d_face_regions,
+                                  (int)c->face_regions.size(), c->d_W0at, seed, n, X, Y, c->stream));
+  }
+  return ATNS_OK;
+}
+
+}  // namespace
+
+atns_status atns_mlp_set_params(atns_ctx* c, const float* host_params) {
+  if (!c || !host_params) return fail(c, ATNS_EINVAL, "null argument");
+  atns_status st = mlp_alloc(c);
+  if (st != ATNS_OK) return st;
+  HIP_TRY(c, hipMemcpyAsync(c->net.params, host_params, kMlpParams * sizeof(float), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, mlp_pack(c->net, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_adam_m, 0, kMlpParams * sizeof(float), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_adam_v, 0, kMlpParams * sizeof(float), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->adam_t = 0;
+  c->mlp_ready = true;
+  return ATNS_OK;
+}
+
+atns_status atns_mlp_get_params(atns_ctx* c, float* host_params) {
+  atns_status st = mlp_need(c);
+  if (st != ATNS_OK) return st;
+  if (!host_params) return fail(c, ATNS_EINVAL, "null argument");
+  HIP_TRY(c, hipMemcpyAsync(host_params, c->net.params, kMlpParams * sizeof(float), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return ATNS_OK;
+}
+
+atns_status atns_mlp_set_scales(atns_ctx* c, const float* feat_scale, const float* targ_scale) {
+  if (!c || !feat_scale || !targ_scale) return fail(c, ATNS_EINVAL, "null argument");
+  for (int v = 0; v < 5; ++v)
+    if (!(feat_scale[v] > 0) || !(targ_scale[v] > 0) || !std::isfinite(feat_scale[v]) ||
+        !std::isfinite(targ_scale[v]))
+      return fail(c, ATNS_EINVAL, "scales must be positive and finite");
+  for (int v = 0; v < 5; ++v) {
+    c->mlp_s[v] = feat_scale[v];
+    c->mlp_r[v] = targ_scale[v];
+  }
+  return ATNS_OK;
+}
+
+atns_status atns_mlp_forward(atns_ctx* c, const float* dev_X, int32_t n, float* dev_out) {
+  atns_status st = mlp_need(c);
+  if (st != ATNS_OK) return st;
+  if (!dev_X || !dev_out || n < 1) return fail(c, ATNS_EINVAL, "bad forward arguments");
+  HIP_TRY(c, mlp_forward(c->net, dev_X, n, dev_out, c->stream));
+  return ATNS_OK;
+}
+
+atns_status atns_mlp_grad(atns_ctx* c, const float* dev_X, const float* dev_Y, int32_t n, float* dev_grad,
+                          double* host_loss) {
+  atns_status st = mlp_need(c);
+  if (st != ATNS_OK) return st;
+  if (!dev_X || !dev_Y || !dev_grad || n < 1) return fail(c, ATNS_EINVAL, "bad gradient arguments");
+  st = mlp_batch(c, n);
+  if (st != ATNS_OK) return st;
+  HIP_TRY(c, mlp_grad(c->net, dev_X, dev_Y, n, c->d_part, c->d_loss_part, dev_grad, c->d_loss, c->stream));
+  if (host_loss) {
+    float l = 0.f;
+    HIP_TRY(c, hipMemcpyAsync(&l, c->d_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *host_loss = l;
+  }
+  return ATNS_OK;
+}
+
+atns_status atns_mlp_sample(atns_ctx* c, int32_t n, uint64_t seed, float* dev_X, float* dev_Y) {
+  if (!c || !dev_X || !dev_Y || n < 1) return fail(c, ATNS_EINVAL, "bad sample arguments");
+  return sample_into(c, n, seed, dev_X, dev_Y);
+}
+
+atns_status atns_mlp_train(atns_ctx* c, int32_t iters, int32_t batch, double lr, uint64_t seed, double* losses) {
+  atns_status st = mlp_need(c);
+  if (st != ATNS_OK) return st;
+  if (iters < 1 || batch < 64 || !(lr > 0)) return fail(c, ATNS_EINVAL, "bad training arguments");
+  st = mlp_batch(c, batch);
+  if (st != ATNS_OK) return st;
+  std::vector<float> lv(iters);
+  for (int i = 0; i < iters; ++i) {
+    st = sample_into(c, batch, seed + (uint64_t)i * 0x632BE59BD9B4E019ull, c->d_X, c->d_Y);
+    if (st != ATNS_OK) return st;
+    HIP_TRY(c, mlp_grad(c->net, c->d_X, c->d_Y, batch, c->d_part, c->d_loss_part, c->d_grad, c->d_loss,
+                        c->stream));
+    if (losses) HIP_TRY(c, hipMemcpyAsync(&lv[i], c->d_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    c->adam_t += 1;
+    HIP_TRY(c, mlp_adam(c->net, c->d_adam_m, c->d_adam_v, c->d_grad, (float)lr, c->adam_t, c->stream));
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (losses)
+    for (int i = 0; i < iters; ++i) losses[i] = lv[i];
+  return ATNS_OK;
+}
+
+atns_status atns_mlp_enable(atns_ctx* c, int32_t on, double tau) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  if (on && !c->mlp_ready) return fail(c, ATNS_ESTATE, "MLP parameters not set");
+  if (on && c->cfg.mode != ATNS_AT) return fail(c, ATNS_EINVAL, "the learned halo needs mode ATNS_AT");
+  if (!(tau >= 0)) return fail(c, ATNS_EINVAL, "tau must be non-negative");
+  c->mlp_on = on != 0;
+  c->mlp_tau = tau;
+  return ATNS_OK;
+}
+
+atns_status atns_mlp_stats(atns_ctx* c, int64_t* applied, int64_t* fallback) {
+  if (!c || !applied || !fallback) return fail(c, ATNS_EINVAL, "null argument");
+  if (!c->d_counters) {
+    *applied = *fallback = 0;
+    return ATNS_OK;
+  }
+  unsigned long long h[2] = {0, 0};
+  HIP_TRY(c, hipMemcpyAsync(h, c->d_counters, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->d_counters, 0, sizeof h, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *applied = (int64_t)h[0];
+  *fallback = (int64_t)h[1];
+  return ATNS_OK;
+}
+
+atns_status atns_hbm_probe(const void* dev_src, void* dev_dst, int64_t bytes, void* stream) {
+  if (!dev_src || !dev_dst || bytes < 16 || bytes % 16 != 0)
+    return fail(nullptr, ATNS_EINVAL, "probe needs device buffers and a positive multiple of 16 bytes");
+  const hipError_t e = launch_copy_probe(dev_src, dev_dst, bytes, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(nullptr, ATNS_EHIP, std::string("copy probe: ") + hipGetErrorString(e));
   return ATNS_OK;
 }
 

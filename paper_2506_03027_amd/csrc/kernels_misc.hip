@@ -138,6 +138,21 @@ hipError_t launch_ring_fill(const StageParams<T>& p, const T* U, int slot, int n
 template hipError_t launch_ring_fill<float>(const StageParams<float>&, const float*, int, int, hipStream_t);
 template hipError_t launch_ring_fill<double>(const StageParams<double>&, const double*, int, int, hipStream_t);
 
+// ------------------------------------------------------------------ HBM probe
+// Plain streaming copy, 16 bytes per lane per iteration: the achievable HBM
+// bandwidth of the device, and the reference a byte-counter run is scaled by.
+__global__ void __launch_bounds__(256) copy_probe_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                         long long n16) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n16; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy_probe(const void* src, void* dst, long long bytes, hipStream_t s) {
+  const long long n16 = bytes / 16;
+  copy_probe_kernel<<<4096, 256, 0, s>>>((const float4*)src, (float4*)dst, n16);
+  return hipGetLastError();
+}
+
 // ----------------------------------------------------------------- diagnostics
 // Per-workgroup FP64 partial sums of: the five conserved variables, rho|u|^2
 // and rho|w|^2 with w = curl u by CD4 on the periodic global field.

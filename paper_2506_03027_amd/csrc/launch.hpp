@@ -15,6 +15,7 @@ template <typename T>
 hipError_t launch_halo(const T* ring, T* halo, const HaloRegion* regions, const HaloWork* work, int nwork,
                        const int8_t* delays, const double* W, long long slot_stride, long long halo_stride,
                        int D, int slot_now, int L, int stages, bool stale, hipStream_t s);
+hipError_t launch_copy_probe(const void* src, void* dst, long long bytes, hipStream_t s);
 hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
                          unsigned long long seed, int algo, hipStream_t s);
 template <typename T>
