@@ -161,6 +161,16 @@ atns_status atns_reduce(atns_ctx* ctx, double* host_out);
 /* Number of blocks, and the ring depth D (levels kept), of a context. */
 atns_status atns_get_layout(const atns_ctx* ctx, int32_t* nblocks, int32_t* ring_depth);
 
+/* Graph-captured steps (on by default).  Each asynchronous step (step >= C)
+ * is one hipGraph launch: delay draw, halo assembly (and the learned-halo
+ * correction when enabled), the s stage kernels and an increment of a device
+ * step counter the kernels read, so one captured graph serves every step.
+ * Synchronous steps, steps with injected delays and profiled steps run
+ * eagerly.  The graph is re-captured after changes of dt, tile shape or the
+ * learned-halo settings.  on = 0 runs every step eagerly.  Results are the
+ * same bits either way. */
+atns_status atns_set_graphs(atns_ctx* ctx, int32_t on);
+
 /* Per-kernel timing of the fused stage kernels.  While enabled (on != 0),
  * every stage-kernel launch of atns_rk_step is bracketed by a pair of HIP
  * events recorded on the context stream.  atns_profile_read synchronizes,
@@ -170,8 +180,8 @@ atns_status atns_profile_enable(atns_ctx* ctx, int32_t on);
 atns_status atns_profile_read(atns_ctx* ctx, int64_t* launches, double* total_ms);
 
 /* Tile shape of the stage kernels: a workgroup walks a TX x TY column of one
- * block through TZ planes.  Supported (TX, TY): Euler (16,16) (32,8) (64,4)
- * (16,8) (32,4); Navier-Stokes (16,16) (32,8) (16,8).  Tiles never straddle
+ * block through TZ planes.  Supported (TX, TY), both physics: (16,16) (32,8)
+ * (16,8).  Tiles never straddle
  * blocks; ragged edges are handled.  EINVAL for other shapes or tz < 1. */
 atns_status atns_set_tiles(atns_ctx* ctx, int32_t tx, int32_t ty, int32_t tz);
 atns_status atns_get_tiles(const atns_ctx* ctx, int32_t* tx, int32_t* ty, int32_t* tz);
@@ -243,6 +253,41 @@ atns_status atns_host_weights(int32_t rk, int32_t mode, int32_t L, double* out);
  * (n*nblocks + b)*ATNS_NSLOTS + v of stream `seed`, modulo L. */
 atns_status atns_host_delays(int32_t algo, int64_t n, int32_t nblocks, int32_t L,
                              uint64_t seed, int8_t* out, int32_t* synchronous);
+
+/* ---- batches --------------------------------------------------------------
+ * Many independent instances (members) -- different grids, block splits,
+ * physics and delay bounds -- advanced together.  Members are ordinary
+ * contexts (reach them with atns_batch_member to set state and dt, read
+ * state and diagnostics) that must be three-dimensional, use classical RK4
+ * and one precision, and
+ * are stepped in lockstep by atns_batch_step.  After the first C
+ * (synchronous) steps, which run member by member, every step is one
+ * hipGraph launch in which a persistent, grid-stride stage kernel per physics
+ * walks the combined tile list of all members of that physics; the Euler and
+ * Navier-Stokes members form two independent branches of the graph.  Each
+ * physics uses one tile shape for all its members (atns_batch_set_tiles, or
+ * atns_batch_autotune, which times every shape on the batch itself --
+ * advancing it by reps + 1 steps per shape -- and keeps the fastest; best
+ * receives int[6] = Euler (tx, ty, tz), Navier-Stokes (tx, ty, tz)).
+ * Member results are bit-identical to stepping each member alone.
+ * Ownership: the batch owns its member contexts; never pass a member to
+ * atns_destroy (atns_batch_destroy releases them).  Member calls that change
+ * dt, tiles or learned-halo settings are picked up by the next batch step
+ * (the batch graph is re-captured).  atns_batch_step enqueues on internal
+ * streams ordered after earlier work on the stream given at creation, and
+ * later work on that stream is ordered after it.  Errors: ATNS_EINVAL for
+ * bad arguments or members that are not 3-D classical RK4 of one precision,
+ * ATNS_ESTATE if members are at different steps or lack state or dt (and,
+ * for atns_batch_autotune, before the members are past step C), ATNS_EHIP
+ * for HIP failures; atns_batch_last_error(NULL) explains a failed create. */
+typedef struct atns_batch atns_batch;
+atns_status atns_batch_create(const atns_config* cfgs, int32_t n, void* stream, atns_batch** out);
+atns_status atns_batch_destroy(atns_batch* batch);
+const char* atns_batch_last_error(const atns_batch* batch);
+atns_status atns_batch_member(atns_batch* batch, int32_t i, atns_ctx** ctx);
+atns_status atns_batch_set_tiles(atns_batch* batch, int32_t physics, int32_t tx, int32_t ty, int32_t tz);
+atns_status atns_batch_autotune(atns_batch* batch, int32_t reps, int32_t* best);
+atns_status atns_batch_step(atns_batch* batch, int32_t nsteps);
 
 #ifdef __cplusplus
 }

@@ -26,11 +26,13 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "EN
 
 EXPORTS = ["atns_version", "atns_create", "atns_destroy", "atns_last_error", "atns_set_state",
            "atns_get_state", "atns_get_step", "atns_set_dt", "atns_set_delays", "atns_get_delays",
-           "atns_rhs", "atns_rk_step", "atns_reduce", "atns_get_layout", "atns_profile_enable",
+           "atns_rhs", "atns_rk_step", "atns_reduce", "atns_get_layout", "atns_set_graphs", "atns_profile_enable",
            "atns_profile_read", "atns_set_tiles", "atns_get_tiles", "atns_autotune",
            "atns_mlp_set_params", "atns_mlp_get_params", "atns_mlp_set_scales", "atns_mlp_forward",
            "atns_mlp_grad", "atns_mlp_sample", "atns_mlp_train", "atns_mlp_enable", "atns_mlp_stats",
-           "atns_hbm_probe", "atns_host_weights", "atns_host_delays"]
+           "atns_hbm_probe", "atns_host_weights", "atns_host_delays", "atns_batch_create",
+           "atns_batch_destroy", "atns_batch_last_error", "atns_batch_member", "atns_batch_set_tiles",
+           "atns_batch_autotune", "atns_batch_step"]
 MLP_PARAMS = 9360
 
 
@@ -74,6 +76,7 @@ def lib():
             "atns_rk_step": ([vp, i32], i32),
             "atns_reduce": ([vp, vp], i32),
             "atns_get_layout": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+            "atns_set_graphs": ([vp, i32], i32),
             "atns_profile_enable": ([vp, i32], i32),
             "atns_profile_read": ([vp, ctypes.POINTER(i64), ctypes.POINTER(dbl)], i32),
             "atns_set_tiles": ([vp, i32, i32, i32], i32),
@@ -91,6 +94,13 @@ def lib():
             "atns_mlp_stats": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
             "atns_host_weights": ([i32, i32, i32, vp], i32),
             "atns_host_delays": ([i32, i64, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(i32)], i32),
+            "atns_batch_create": ([ctypes.POINTER(Config), i32, vp, ctypes.POINTER(vp)], i32),
+            "atns_batch_destroy": ([vp], i32),
+            "atns_batch_last_error": ([vp], ctypes.c_char_p),
+            "atns_batch_member": ([vp, i32, ctypes.POINTER(vp)], i32),
+            "atns_batch_set_tiles": ([vp, i32, i32, i32, i32], i32),
+            "atns_batch_autotune": ([vp, i32, vp], i32),
+            "atns_batch_step": ([vp, i32], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -149,17 +159,21 @@ def make_config(n, length, ndim=3, nblk=(1, 1, 1), physics=EULER, gamma=1.4, mac
 class Solver:
     """One context of the library; state tensors live on the current device."""
 
-    def __init__(self, stream=None, **kw):
+    def __init__(self, stream=None, _ctx=None, _owner=None, **kw):
         import torch
         self.torch = torch
         self.kw = dict(kw)
-        self.cfg, keep = make_config(**kw)
         self.n = tuple(kw["n"])
         self.dtype = torch.float64 if kw.get("precision", F32) == F64 else torch.float32
-        ctx = ctypes.c_void_p()
-        st = lib().atns_create(ctypes.byref(self.cfg), stream, ctypes.byref(ctx))
-        if st != 0:
-            raise AtnsError(st, lib().atns_last_error(None).decode())
+        self._owner = _owner     # a Batch owns its members' contexts
+        if _ctx is None:
+            self.cfg, keep = make_config(**kw)
+            ctx = ctypes.c_void_p()
+            st = lib().atns_create(ctypes.byref(self.cfg), stream, ctypes.byref(ctx))
+            if st != 0:
+                raise AtnsError(st, lib().atns_last_error(None).decode())
+        else:
+            ctx = _ctx
         self.ctx = ctx
         nb, D = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().atns_get_layout(ctx, ctypes.byref(nb), ctypes.byref(D)), ctx)
@@ -167,7 +181,8 @@ class Solver:
 
     def close(self):
         if getattr(self, "ctx", None):
-            lib().atns_destroy(self.ctx)
+            if self._owner is None:
+                lib().atns_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):
@@ -223,6 +238,9 @@ class Solver:
 
     def step(self, nsteps=1):
         _check(lib().atns_rk_step(self.ctx, int(nsteps)), self.ctx)
+
+    def set_graphs(self, on):
+        _check(lib().atns_set_graphs(self.ctx, 1 if on else 0), self.ctx)
 
     def profile(self, on):
         _check(lib().atns_profile_enable(self.ctx, 1 if on else 0), self.ctx)
@@ -312,3 +330,59 @@ class Solver:
         if st not in (0, -5):
             _check(st, self.ctx)
         return out, st == 0
+
+
+class Batch:
+    """Many instances stepped together (classical RK4, one precision).
+
+    ``configs`` is a list of keyword dicts as taken by ``Solver``; the members
+    are ``Solver`` objects over contexts the batch owns (``members``)."""
+
+    def __init__(self, configs, stream=None):
+        import torch
+        self.torch = torch
+        made = [make_config(**kw) for kw in configs]
+        arr = (Config * len(made))(*[m[0] for m in made])
+        self._keep = [m[1] for m in made]
+        h = ctypes.c_void_p()
+        st = lib().atns_batch_create(arr, len(made), stream, ctypes.byref(h))
+        if st != 0:
+            raise AtnsError(st, lib().atns_batch_last_error(None).decode())
+        self.h = h
+        self.members = []
+        for i, kw in enumerate(configs):
+            c = ctypes.c_void_p()
+            self._check(lib().atns_batch_member(h, i, ctypes.byref(c)))
+            self.members.append(Solver(_ctx=c, _owner=self, **kw))
+
+    def _check(self, st):
+        if st != 0:
+            raise AtnsError(st, lib().atns_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            for m in self.members:
+                m.ctx = None
+            lib().atns_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, nsteps=1):
+        self.torch.cuda.synchronize()
+        self._check(lib().atns_batch_step(self.h, int(nsteps)))
+
+    def set_tiles(self, physics, tx, ty, tz):
+        self._check(lib().atns_batch_set_tiles(self.h, int(physics), tx, ty, tz))
+
+    def autotune(self, reps=3):
+        """Times every tile shape on the batch (advancing it) and keeps the
+        fastest; returns ((Euler tx, ty, tz), (Navier-Stokes tx, ty, tz))."""
+        best = np.zeros(6, dtype=np.int32)
+        self.torch.cuda.synchronize()
+        self._check(lib().atns_batch_autotune(self.h, int(reps), best.ctypes.data))
+        return tuple(int(x) for x in best[:3]), tuple(int(x) for x in best[3:])

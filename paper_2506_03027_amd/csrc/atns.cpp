@@ -77,6 +77,14 @@ struct atns_ctx {
   double mlp_tau = 1e30;
   bool mlp_on = false;
   bool mlp_ready = false;
+  // graph-captured asynchronous steps
+  long long* d_nstep = nullptr;      // device copy of the step number
+  hipStream_t gstream = nullptr;     // capture/launch stream when `stream` is the null stream
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};   // per LSERK register parity
+  bool use_graph = true;
+  bool nstep_synced = false;
+  uint64_t graph_gen = 0;   // bumped whenever captured step parameters go stale
+  hipEvent_t order_ev = nullptr;
   double* d_partials = nullptr;
   double* d_diag = nullptr;
   int nparts = 1024;
@@ -271,10 +279,14 @@ void build_tiles(atns_ctx* c, int TX, int TY, int TZ) {
   }
 }
 
-bool shape_supported(int physics, int tx, int ty) {
-  if (physics == ATNS_NS) return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 16 && ty == 8);
-  return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 64 && ty == 4) || (tx == 16 && ty == 8) ||
-         (tx == 32 && ty == 4);
+// (TX, TY) column shapes the stage kernels are instantiated for (both physics).
+constexpr int kNumShapes = 3;
+constexpr int kShapes[kNumShapes][2] = {{16, 16}, {32, 8}, {16, 8}};
+
+bool shape_supported(int /*physics*/, int tx, int ty) {
+  for (const auto& s : kShapes)
+    if (s[0] == tx && s[1] == ty) return true;
+  return false;
 }
 
 size_t count_tiles(const atns_ctx* c, int tx, int ty, int tz) {
@@ -298,7 +310,10 @@ void default_tiles(atns_ctx* c) {
   c->tile[2] = c->cfg.ndim == 2 ? 1 : tz;
 }
 
+void drop_graphs(atns_ctx* c);
+
 atns_status upload_tiles(atns_ctx* c) {
+  drop_graphs(c);
   build_tiles(c, c->tile[0], c->tile[1], c->tile[2]);
   if (c->d_tiles) (void)hipFree(c->d_tiles);
   c->d_tiles = nullptr;
@@ -406,11 +421,150 @@ atns_status prepare_halos(atns_ctx* c) {
   return ATNS_OK;
 }
 
+hipStream_t work_stream(const atns_ctx* c) { return c->stream ? c->stream : c->gstream; }
+
+// Executable graphs are destroyed only once every launch of them has
+// finished: a queued launch still reads the kernel arguments the graph owns.
+void drop_graphs(atns_ctx* c) {
+  c->graph_gen += 1;
+  bool any = false;
+  for (hipGraphExec_t g : c->gexec) any = any || g != nullptr;
+  if (!any) return;
+  (void)hipStreamSynchronize(work_stream(c));
+  for (hipGraphExec_t& g : c->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
+// Stage parameters of stage e of an asynchronous step whose step number is
+// read on the device (graph-captured steps).
 template <typename T>
-atns_status do_steps(atns_ctx* c, int nsteps) {
+StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind) {
+  const RKScheme& rk = c->rk;
+  StageParams<T> p = base_params<T>(c);
+  p.nstep = c->d_nstep;
+  p.async_halo = c->cfg.mode == ATNS_SA ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
+  p.halo = kHaloSync;
+  p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)e * c->slot_stride : nullptr;
+  p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
+  if (!rk.low_storage) {
+    T* U = (T*)c->X[0];
+    T* Ya = (T*)c->X[1];
+    T* Yb = (T*)c->X[2];
+    p.U0 = U;
+    p.acc = (T*)c->X[3];
+    const T* ins[4] = {U, Ya, Yb, Ya};
+    T* outs[4] = {Ya, Yb, Ya, U};
+    p.Y = ins[e];
+    p.Yout = outs[e];
+    *kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
+    p.cA = rk.b[e];
+    p.cB = e < 3 ? rk.a[e + 1][e] : 0.0;
+  } else {
+    const int cur = (c->cur + e) & 1;
+    p.Y = (const T*)c->X[cur];
+    p.Yout = (T*)c->X[1 - cur];
+    p.acc = (T*)c->X[3];
+    *kind = e == 0 ? kLSFirst : kLSMid;
+    p.cA = rk.A[e];
+    p.cB = rk.B[e];
+  }
+  return p;
+}
+
+// Enqueue the halo work of one asynchronous step with the device step counter.
+template <typename T>
+atns_status enqueue_graph_halos(atns_ctx* c, hipStream_t s) {
+  if (c->cfg.mode == ATNS_SA) return ATNS_OK;
+  HIP_TRY(c, launch_delays(c->d_delays, nullptr, 0, c->nb, c->cfg.L, c->cfg.seed, c->cfg.algo, s, c->d_nstep));
+  HIP_TRY(c, launch_halo<T>((const T*)c->ring, (T*)c->hbuf, c->d_regions, c->d_work, (int)c->work.size(),
+                            c->d_delays, c->d_W, c->slot_stride, c->slot_stride, c->D, 0, c->cfg.L,
+                            c->rk.stages, c->cfg.mode == ATNS_AS, s, c->d_nstep));
+  if (c->mlp_on && c->cfg.mode == ATNS_AT) {
+    MlpFeatArgs<T> fa = feat_args<T>(c);
+    fa.nstep = c->d_nstep;
+    HIP_TRY(c, mlp_halo<T>(fa, c->net, c->d_regions, c->d_faceinfo, c->d_face_chunks,
+                           (long long)c->face_chunks.size(), c->d_delays, (T*)c->hbuf, c->slot_stride,
+                           c->rk.stages, c->d_counters, s));
+  }
+  return ATNS_OK;
+}
+
+// One captured step: halos, s stage kernels, counter increment.
+template <typename T>
+atns_status capture_step(atns_ctx* c, hipGraphExec_t* out) {
+  hipStream_t s = work_stream(c);
+  hipGraph_t graph = nullptr;
+  HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  atns_status st = enqueue_graph_halos<T>(c, s);
+  for (int e = 0; st == ATNS_OK && e < c->rk.stages; ++e) {
+    int kind = 0;
+    const StageParams<T> p = graph_stage_params<T>(c, e, &kind);
+    const hipError_t r =
+        (c->cfg.physics == ATNS_NS)
+            ? launch_ns_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], s)
+            : launch_euler_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], s);
+    if (r != hipSuccess) st = fail(c, ATNS_EHIP, std::string("stage launch in capture: ") + hipGetErrorString(r));
+  }
+  if (st == ATNS_OK) {
+    const hipError_t r = launch_step_inc1(c->d_nstep, s);
+    if (r != hipSuccess) st = fail(c, ATNS_EHIP, std::string("counter launch in capture: ") + hipGetErrorString(r));
+  }
+  const hipError_t ec = hipStreamEndCapture(s, &graph);
+  if (st != ATNS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ec != hipSuccess) return fail(c, ATNS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+  const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return fail(c, ATNS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  return ATNS_OK;
+}
+
+// Work enqueued on `from` so far precedes later work on `to`.
+atns_status order_streams(atns_ctx* c, hipStream_t from, hipStream_t to) {
+  if (from == to) return ATNS_OK;
+  HIP_TRY(c, hipEventRecord(c->order_ev, from));
+  HIP_TRY(c, hipStreamWaitEvent(to, c->order_ev, 0));
+  return ATNS_OK;
+}
+
+template <typename T>
+atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
   const RKScheme& rk = c->rk;
   for (int it = 0; it < nsteps; ++it) {
     const bool async = is_async(c, c->step);
+    const bool graphable = async && c->use_graph && !c->profiling && c->inject_n == 0;
+    hipStream_t s = work_stream(c);
+    if (graphable) {
+      const int par = rk.low_storage ? c->cur : 0;
+      if (!c->gexec[par]) {
+        atns_status st = capture_step<T>(c, &c->gexec[par]);
+        if (st != ATNS_OK) return st;
+      }
+      if (!*on_graph) {
+        atns_status st = order_streams(c, c->stream, s);
+        if (st != ATNS_OK) return st;
+        *on_graph = true;
+      }
+      if (!c->nstep_synced) {
+        HIP_TRY(c, launch_step_set(c->d_nstep, c->step, s));
+        c->nstep_synced = true;
+      }
+      HIP_TRY(c, hipGraphLaunch(c->gexec[par], s));
+      if (rk.low_storage && (rk.stages & 1)) c->cur = 1 - c->cur;
+      c->step += 1;
+      continue;
+    }
+    if (*on_graph) {
+      atns_status st = order_streams(c, s, c->stream);
+      if (st != ATNS_OK) return st;
+      *on_graph = false;
+    }
+    c->nstep_synced = false;
     if (async) {
       atns_status st = prepare_halos<T>(c);
       if (st != ATNS_OK) return st;
@@ -451,9 +605,27 @@ atns_status do_steps(atns_ctx* c, int nsteps) {
   return ATNS_OK;
 }
 
+template <typename T>
+atns_status do_steps(atns_ctx* c, int nsteps) {
+  bool on_graph = false;
+  atns_status st = do_steps_impl<T>(c, nsteps, &on_graph);
+  if (on_graph) {
+    const atns_status s2 = order_streams(c, work_stream(c), c->stream);
+    if (st == ATNS_OK) st = s2;
+  }
+  return st;
+}
+
 void* state_ptr(const atns_ctx* c) { return c->rk.low_storage ? c->X[c->cur] : c->X[0]; }
 
 void release(atns_ctx* c) {
+  drop_graphs(c);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
+  c->gstream = nullptr;
+  if (c->order_ev) (void)hipEventDestroy(c->order_ev);
+  c->order_ev = nullptr;
+  if (c->d_nstep) (void)hipFree(c->d_nstep);
+  c->d_nstep = nullptr;
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   c->ev_pool.clear();
   for (void*& x : c->X)
@@ -515,6 +687,12 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
     return s;
   };
   if (hipGetDevice(&c->device) != hipSuccess) return fail_free(ATNS_EHIP, "no HIP device");
+  if (hipMalloc((void**)&c->d_nstep, sizeof(long long)) != hipSuccess)
+    return fail_free(ATNS_ENOMEM, "counter allocation failed");
+  if (!c->stream && hipStreamCreate(&c->gstream) != hipSuccess)
+    return fail_free(ATNS_EHIP, "stream creation failed");
+  if (hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming) != hipSuccess)
+    return fail_free(ATNS_EHIP, "event creation failed");
   const size_t fbytes = (size_t)c->field * 5 * c->esz;
   for (int i = 0; i < 4; ++i)
     if (hipMalloc(&c->X[i], fbytes) != hipSuccess) return fail_free(ATNS_ENOMEM, "state allocation failed");
@@ -585,6 +763,7 @@ atns_status atns_set_state(atns_ctx* c, const void* dev_U, int64_t step) {
   HIP_TRY(c, hipMemcpyAsync(dst, dev_U, (size_t)c->field * 5 * c->esz, hipMemcpyDeviceToDevice, c->stream));
   c->step = step;
   c->state_set = true;
+  c->nstep_synced = false;
   if (c->ring) {
     const int slot = (int)(step % c->D);
     if (c->esz == 4) {
@@ -620,6 +799,7 @@ atns_status atns_get_step(const atns_ctx* c, int64_t* step) {
 atns_status atns_set_dt(atns_ctx* c, double dt) {
   if (!c) return fail(c, ATNS_EINVAL, "null context");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(c, ATNS_EINVAL, "dt must be positive and finite");
+  if (dt != c->dt) drop_graphs(c);
   c->dt = dt;
   return ATNS_OK;
 }
@@ -713,6 +893,14 @@ atns_status atns_get_layout(const atns_ctx* c, int32_t* nblocks, int32_t* ring_d
   if (!c) return fail(nullptr, ATNS_EINVAL, "null context");
   if (nblocks) *nblocks = c->nb;
   if (ring_depth) *ring_depth = c->D;
+  return ATNS_OK;
+}
+
+atns_status atns_set_graphs(atns_ctx* c, int32_t on) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  HIP_TRY(c, hipDeviceSynchronize());
+  c->use_graph = on != 0;
+  if (!c->use_graph) drop_graphs(c);
   return ATNS_OK;
 }
 
@@ -832,22 +1020,21 @@ atns_status atns_autotune(atns_ctx* c, int32_t reps, const char* cache_path, int
   if (reps < 1) return fail(c, ATNS_EINVAL, "reps must be positive");
   const std::string key = tune_key(c);
   int pick[3];
-  if (!cache_lookup(cache_path, key, pick)) {
-    static const int euler_xy[][2] = {{16, 16}, {32, 8}, {64, 4}, {16, 8}, {32, 4}};
-    static const int ns_xy[][2] = {{16, 16}, {32, 8}, {16, 8}};
+  // entries naming a shape this build does not provide are ignored
+  const bool cached = cache_lookup(cache_path, key, pick) && shape_supported(c->cfg.physics, pick[0], pick[1]) &&
+                      pick[2] >= 1 && pick[2] <= 32767;
+  if (!cached) {
     const bool ns = c->cfg.physics == ATNS_NS;
-    const int nxy = ns ? 3 : 5;
     const int tzs[] = {4, 8, 16, 32};
     float best_ms = 1e30f;
     pick[0] = c->tile[0];
     pick[1] = c->tile[1];
     pick[2] = c->tile[2];
-    for (int i = 0; i < nxy; ++i)
+    for (int i = 0; i < kNumShapes; ++i)
       for (int tz : tzs) {
         if (c->cfg.ndim == 2 && tz != 4) continue;
         if (ns && tz < 8) continue;   // 8 extra planes per column: short ones waste work
-        const int tx = ns ? ns_xy[i][0] : euler_xy[i][0];
-        const int ty = ns ? ns_xy[i][1] : euler_xy[i][1];
+        const int tx = kShapes[i][0], ty = kShapes[i][1];
         atns_status st = atns_set_tiles(c, tx, ty, tz);
         if (st != ATNS_OK) return st;
         float ms = 0.f;
@@ -967,6 +1154,7 @@ atns_status atns_mlp_set_scales(atns_ctx* c, const float* feat_scale, const floa
     c->mlp_s[v] = feat_scale[v];
     c->mlp_r[v] = targ_scale[v];
   }
+  drop_graphs(c);
   return ATNS_OK;
 }
 
@@ -1029,6 +1217,7 @@ atns_status atns_mlp_enable(atns_ctx* c, int32_t on, double tau) {
   if (!(tau >= 0)) return fail(c, ATNS_EINVAL, "tau must be non-negative");
   c->mlp_on = on != 0;
   c->mlp_tau = tau;
+  drop_graphs(c);
   return ATNS_OK;
 }
 
@@ -1069,6 +1258,343 @@ atns_status atns_host_delays(int32_t algo, int64_t n, int32_t nblocks, int32_t L
     return fail(nullptr, ATNS_EINVAL, "bad delay request");
   const bool async = step_delays(algo, n, nblocks, L, seed, nullptr, out);
   if (synchronous) *synchronous = async ? 0 : 1;
+  return ATNS_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Batches: many independent instances advanced together.
+// ============================================================================
+struct atns_batch {
+  std::vector<atns_ctx*> m;
+  hipStream_t user = nullptr;
+  hipStream_t s[2] = {nullptr, nullptr};   // Euler chain, Navier-Stokes chain
+  hipEvent_t fork = nullptr, join = nullptr, order = nullptr;
+  int shape[2][3] = {{16, 16, 8}, {16, 16, 32}};
+  std::vector<BatchTile> tl[2];
+  BatchTile* d_tl[2] = {nullptr, nullptr};
+  int grid[2] = {0, 0};
+  void* d_ps = nullptr;                    // StageParams<T>[stages][n]
+  long long** d_cnt = nullptr;             // member step counters
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint64_t> gen;   // member graph_gen at capture
+  int esz = 4;
+  int stages = 4;
+  std::string err;
+};
+
+namespace {
+
+atns_status bfail(atns_batch* b, atns_status s, const std::string& msg) {
+  if (b) b->err = msg;
+  g_err = msg;
+  return s;
+}
+
+#define BHIP(b, expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return bfail(b, ATNS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void batch_drop_graph(atns_batch* b) {
+  if (!b->gexec) return;
+  (void)hipStreamSynchronize(b->s[0]);   // see drop_graphs
+  (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+}
+
+// Combined tile list of the members of one physics, XCD-ordered.
+atns_status batch_tiles(atns_batch* b, int ph) {
+  batch_drop_graph(b);
+  std::vector<BatchTile> nat;
+  for (int i = 0; i < (int)b->m.size(); ++i) {
+    atns_ctx* c = b->m[i];
+    if ((c->cfg.physics == ATNS_NS) != (ph == 1)) continue;
+    c->tile[0] = b->shape[ph][0];
+    c->tile[1] = b->shape[ph][1];
+    c->tile[2] = b->shape[ph][2];
+    atns_status st = upload_tiles(c);   // the member's own list stays consistent
+    if (st != ATNS_OK) return bfail(b, st, c->err);
+    for (const TileDev& t : c->tiles)
+      if (t.nx > 0) nat.push_back(BatchTile{i, t});
+  }
+  const size_t chunk = (nat.size() + 7) / 8;
+  b->tl[ph].assign(chunk * 8, BatchTile{0, TileDev{0, 0, 0, 0, 0, 0, 0}});
+  for (size_t j = 0; j < nat.size(); ++j) b->tl[ph][(j % chunk) * 8 + j / chunk] = nat[j];
+  if (b->d_tl[ph]) (void)hipFree(b->d_tl[ph]);
+  b->d_tl[ph] = nullptr;
+  if (!b->tl[ph].empty()) {
+    if (hipMalloc((void**)&b->d_tl[ph], b->tl[ph].size() * sizeof(BatchTile)) != hipSuccess)
+      return bfail(b, ATNS_ENOMEM, "batch tile allocation failed");
+    BHIP(b, hipMemcpy(b->d_tl[ph], b->tl[ph].data(), b->tl[ph].size() * sizeof(BatchTile), hipMemcpyHostToDevice));
+  }
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->m[0]->device);
+  const int per_cu = ph == 0 ? 4 : 2;   // resident workgroups per CU of the two kernels
+  b->grid[ph] = (int)std::min<size_t>(b->tl[ph].size(), (size_t)cus * per_cu);
+  return ATNS_OK;
+}
+
+template <typename T>
+atns_status batch_params(atns_batch* b) {
+  const int n = (int)b->m.size();
+  std::vector<StageParams<T>> ps((size_t)b->stages * n);
+  for (int e = 0; e < b->stages; ++e)
+    for (int i = 0; i < n; ++i) {
+      int kind = 0;
+      ps[(size_t)e * n + i] = graph_stage_params<T>(b->m[i], e, &kind);
+    }
+  if (!b->d_ps && hipMalloc(&b->d_ps, ps.size() * sizeof(StageParams<T>)) != hipSuccess)
+    return bfail(b, ATNS_ENOMEM, "batch parameter allocation failed");
+  BHIP(b, hipMemcpy(b->d_ps, ps.data(), ps.size() * sizeof(StageParams<T>), hipMemcpyHostToDevice));
+  return ATNS_OK;
+}
+
+template <typename T>
+atns_status batch_capture(atns_batch* b) {
+  atns_status st = batch_params<T>(b);
+  if (st != ATNS_OK) return st;
+  const int n = (int)b->m.size();
+  hipGraph_t graph = nullptr;
+  BHIP(b, hipStreamBeginCapture(b->s[0], hipStreamCaptureModeThreadLocal));
+  auto body = [&]() -> atns_status {
+    BHIP(b, hipEventRecord(b->fork, b->s[0]));
+    BHIP(b, hipStreamWaitEvent(b->s[1], b->fork, 0));
+    for (int ph = 0; ph < 2; ++ph) {
+      hipStream_t s = b->s[ph];
+      for (int i = 0; i < n; ++i) {
+        atns_ctx* c = b->m[i];
+        if ((c->cfg.physics == ATNS_NS) != (ph == 1)) continue;
+        atns_status r = enqueue_graph_halos<T>(c, s);
+        if (r != ATNS_OK) return bfail(b, r, c->err);
+      }
+      if (b->tl[ph].empty()) continue;
+      for (int e = 0; e < b->stages; ++e) {
+        const StageParams<T>* pe = (const StageParams<T>*)b->d_ps + (size_t)e * n;
+        const int kind = e == 0 ? kRK4First : (e == b->stages - 1 ? kRK4Last : kRK4Mid);
+        const hipError_t r =
+            ph == 0 ? launch_euler_batch<T>(pe, b->d_tl[0], (int)b->tl[0].size(), b->grid[0], kind, b->shape[0][0],
+                                           b->shape[0][1], s)
+                    : launch_ns_batch<T>(pe, b->d_tl[1], (int)b->tl[1].size(), b->grid[1], kind, b->shape[1][0],
+                                        b->shape[1][1], s);
+        if (r != hipSuccess) return bfail(b, ATNS_EHIP, std::string("batch stage launch: ") + hipGetErrorString(r));
+      }
+    }
+    BHIP(b, hipEventRecord(b->join, b->s[1]));
+    BHIP(b, hipStreamWaitEvent(b->s[0], b->join, 0));
+    BHIP(b, launch_step_inc(b->d_cnt, n, b->s[0]));
+    return ATNS_OK;
+  };
+  st = body();
+  const hipError_t ec = hipStreamEndCapture(b->s[0], &graph);
+  if (st != ATNS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (ec != hipSuccess) return bfail(b, ATNS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+  const hipError_t ei = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return bfail(b, ATNS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  b->gen.clear();
+  for (atns_ctx* c : b->m) b->gen.push_back(c->graph_gen);
+  return ATNS_OK;
+}
+
+// Orders everything enqueued so far on stream `from` before later work on `to`.
+atns_status batch_order(atns_batch* b, hipStream_t from, hipStream_t to) {
+  BHIP(b, hipEventRecord(b->order, from));
+  BHIP(b, hipStreamWaitEvent(to, b->order, 0));
+  return ATNS_OK;
+}
+
+template <typename T>
+atns_status batch_steps(atns_batch* b, int nsteps) {
+  bool on_graph = false;   // the last work of this call went to the graph stream
+  atns_status st = ATNS_OK;
+  for (int it = 0; it < nsteps && st == ATNS_OK; ++it) {
+    const int64_t step = b->m[0]->step;
+    bool eager = step < kC;
+    for (atns_ctx* c : b->m) {
+      if (c->step != step) return bfail(b, ATNS_ESTATE, "members are not at the same step");
+      if (!c->state_set || !(c->dt > 0)) return bfail(b, ATNS_ESTATE, "member state or dt not set");
+      if (c->inject_n > 0 || c->profiling) eager = true;
+    }
+    if (eager) {
+      if (on_graph && (st = batch_order(b, b->s[0], b->user)) != ATNS_OK) break;
+      on_graph = false;
+      for (atns_ctx* c : b->m) {
+        st = atns_rk_step(c, 1);
+        if (st != ATNS_OK) return bfail(b, st, c->err);
+      }
+      continue;
+    }
+    // A member whose dt, tiles or learned-halo settings changed since the
+    // capture invalidates the batch graph too.
+    for (size_t i = 0; b->gexec && i < b->m.size(); ++i)
+      if (b->m[i]->graph_gen != b->gen[i]) batch_drop_graph(b);
+    if (!b->gexec && (st = batch_capture<T>(b)) != ATNS_OK) break;
+    if (!on_graph) {
+      // Member work (state uploads, eager steps) precedes the graph; the
+      // device step counters are written from the host's step numbers.
+      if ((st = batch_order(b, b->user, b->s[0])) != ATNS_OK) break;
+      for (atns_ctx* c : b->m) BHIP(b, launch_step_set(c->d_nstep, c->step, b->s[0]));
+      on_graph = true;
+    }
+    BHIP(b, hipGraphLaunch(b->gexec, b->s[0]));
+    for (atns_ctx* c : b->m) {
+      c->step += 1;
+      c->nstep_synced = false;
+    }
+  }
+  if (on_graph) {
+    const atns_status s2 = batch_order(b, b->s[0], b->user);
+    if (st == ATNS_OK) st = s2;
+  }
+  return st;
+}
+
+void batch_release(atns_batch* b) {
+  batch_drop_graph(b);
+  for (atns_ctx* c : b->m) atns_destroy(c);
+  b->m.clear();
+  for (BatchTile*& t : b->d_tl)
+    if (t) {
+      (void)hipFree(t);
+      t = nullptr;
+    }
+  if (b->d_ps) (void)hipFree(b->d_ps);
+  if (b->d_cnt) (void)hipFree(b->d_cnt);
+  for (hipStream_t& s : b->s)
+    if (s) (void)hipStreamDestroy(s);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
+  if (b->order) (void)hipEventDestroy(b->order);
+}
+
+}  // namespace
+
+extern "C" {
+
+atns_status atns_batch_create(const atns_config* cfgs, int32_t n, void* stream, atns_batch** out) {
+  if (!out || !cfgs || n < 1) return bfail(nullptr, ATNS_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (cfgs[i].rk != ATNS_RK4) return bfail(nullptr, ATNS_EINVAL, "batch members use classical RK4");
+    if (cfgs[i].precision != cfgs[0].precision) return bfail(nullptr, ATNS_EINVAL, "batch members share precision");
+    if (cfgs[i].ndim != 3) return bfail(nullptr, ATNS_EINVAL, "batch members are three-dimensional");
+  }
+  auto* b = new atns_batch();
+  b->user = (hipStream_t)stream;
+  b->esz = cfgs[0].precision == ATNS_F64 ? 8 : 4;
+  for (int i = 0; i < n; ++i) {
+    atns_ctx* c = nullptr;
+    atns_status st = atns_create(&cfgs[i], stream, &c);
+    if (st != ATNS_OK) {
+      batch_release(b);
+      delete b;
+      return st;
+    }
+    b->m.push_back(c);
+  }
+  auto bad = [&](atns_status s, const char* m) {
+    batch_release(b);
+    delete b;
+    return bfail(nullptr, s, m);
+  };
+  if (hipStreamCreate(&b->s[0]) != hipSuccess || hipStreamCreate(&b->s[1]) != hipSuccess ||
+      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->order, hipEventDisableTiming) != hipSuccess)
+    return bad(ATNS_EHIP, "batch stream creation failed");
+  std::vector<long long*> cnt;
+  for (atns_ctx* c : b->m) cnt.push_back(c->d_nstep);
+  if (hipMalloc((void**)&b->d_cnt, cnt.size() * sizeof(long long*)) != hipSuccess ||
+      hipMemcpy(b->d_cnt, cnt.data(), cnt.size() * sizeof(long long*), hipMemcpyHostToDevice) != hipSuccess)
+    return bad(ATNS_EHIP, "batch counter table failed");
+  for (int ph = 0; ph < 2; ++ph)
+    if (batch_tiles(b, ph) != ATNS_OK) return bad(ATNS_EHIP, "batch tile table failed");
+  *out = b;
+  return ATNS_OK;
+}
+
+atns_status atns_batch_destroy(atns_batch* b) {
+  if (!b) return ATNS_OK;
+  (void)hipDeviceSynchronize();
+  batch_release(b);
+  delete b;
+  return ATNS_OK;
+}
+
+const char* atns_batch_last_error(const atns_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
+
+atns_status atns_batch_member(atns_batch* b, int32_t i, atns_ctx** ctx) {
+  if (!b || !ctx || i < 0 || i >= (int)b->m.size()) return bfail(b, ATNS_EINVAL, "bad member index");
+  *ctx = b->m[i];
+  return ATNS_OK;
+}
+
+atns_status atns_batch_set_tiles(atns_batch* b, int32_t physics, int32_t tx, int32_t ty, int32_t tz) {
+  if (!b || (physics != ATNS_EULER && physics != ATNS_NS)) return bfail(b, ATNS_EINVAL, "bad physics");
+  if (!shape_supported(physics, tx, ty) || tz < 1) return bfail(b, ATNS_EINVAL, "unsupported tile shape");
+  BHIP(b, hipDeviceSynchronize());
+  const int ph = physics == ATNS_NS ? 1 : 0;
+  b->shape[ph][0] = tx;
+  b->shape[ph][1] = ty;
+  b->shape[ph][2] = tz;
+  return batch_tiles(b, ph);
+}
+
+atns_status atns_batch_step(atns_batch* b, int32_t nsteps) {
+  if (!b || nsteps < 0) return bfail(b, ATNS_EINVAL, "bad arguments");
+  return b->esz == 4 ? batch_steps<float>(b, nsteps) : batch_steps<double>(b, nsteps);
+}
+
+atns_status atns_batch_autotune(atns_batch* b, int32_t reps, int32_t* best) {
+  if (!b || reps < 1) return bfail(b, ATNS_EINVAL, "bad arguments");
+  for (atns_ctx* c : b->m)
+    if (c->step < kC || c->inject_n > 0 || c->profiling)
+      return bfail(b, ATNS_ESTATE, "autotune times graph steps: step the batch past its synchronous start first");
+  for (int ph = 0; ph < 2; ++ph) {
+    bool any = false;
+    for (atns_ctx* c : b->m) any = any || ((c->cfg.physics == ATNS_NS) == (ph == 1));
+    if (!any) continue;
+    float best_ms = 1e30f;
+    int pick[3] = {b->shape[ph][0], b->shape[ph][1], b->shape[ph][2]};
+    for (int i = 0; i < kNumShapes; ++i)
+      for (int tz : {4, 8, 16, 32}) {
+        if (ph == 1 && tz < 8) continue;
+        const int tx = kShapes[i][0], ty = kShapes[i][1];
+        atns_status st = atns_batch_set_tiles(b, ph ? ATNS_NS : ATNS_EULER, tx, ty, tz);
+        if (st != ATNS_OK) return st;
+        st = atns_batch_step(b, 1);   // capture (and a warm step)
+        if (st != ATNS_OK) return st;
+        hipEvent_t e0, e1;
+        BHIP(b, hipEventCreate(&e0));
+        BHIP(b, hipEventCreate(&e1));
+        BHIP(b, hipEventRecord(e0, b->s[0]));
+        st = atns_batch_step(b, reps);
+        if (st != ATNS_OK) return st;
+        BHIP(b, hipEventRecord(e1, b->s[0]));
+        BHIP(b, hipEventSynchronize(e1));
+        float ms = 0.f;
+        BHIP(b, hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (ms < best_ms) {
+          best_ms = ms;
+          pick[0] = tx;
+          pick[1] = ty;
+          pick[2] = tz;
+        }
+      }
+    atns_status st = atns_batch_set_tiles(b, ph ? ATNS_NS : ATNS_EULER, pick[0], pick[1], pick[2]);
+    if (st != ATNS_OK) return st;
+  }
+  if (best)
+    for (int ph = 0; ph < 2; ++ph)
+      for (int d = 0; d < 3; ++d) best[ph * 3 + d] = b->shape[ph][d];
   return ATNS_OK;
 }
 

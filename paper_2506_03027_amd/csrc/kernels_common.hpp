@@ -21,9 +21,33 @@ __device__ __forceinline__ int wrap(int g, int n) {
   return g;
 }
 
+// Stage parameters with the step-dependent fields resolved from the device
+// step counter when present.
+template <typename T>
+__device__ __forceinline__ StageParams<T> resolve_step(const StageParams<T>& p) {
+  StageParams<T> q = p;
+  if (p.nstep) {
+    const long long n = *p.nstep;
+    q.slot_now = p.D ? (int)(n % p.D) : 0;
+    q.halo = (n >= kLevels) ? p.async_halo : kHaloSync;
+  }
+  return q;
+}
+
 // Copy a block descriptor into LDS (cooperatively, 32-bit words) and wait.
 __device__ __forceinline__ void stage_block(const BlockDev* __restrict__ src, BlockDev* dst) {
   constexpr int nw = (int)(sizeof(BlockDev) / 4);
+  const int* s = reinterpret_cast<const int*>(src);
+  int* d = reinterpret_cast<int*>(dst);
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) d[i] = s[i];
+  __syncthreads();
+}
+
+// Copy any 4-byte-multiple struct into LDS (cooperatively) and wait.
+template <typename S>
+__device__ __forceinline__ void stage_struct(const S* __restrict__ src, S* dst) {
+  static_assert(sizeof(S) % 4 == 0, "struct size");
+  constexpr int nw = (int)(sizeof(S) / 4);
   const int* s = reinterpret_cast<const int*>(src);
   int* d = reinterpret_cast<int*>(dst);
   for (int i = threadIdx.x; i < nw; i += blockDim.x) d[i] = s[i];

@@ -18,30 +18,36 @@
 
 namespace atns {
 
+// The fluxes of a point are computed by its own thread or, at a tile edge, by
+// an apron thread of the neighbouring tile.  The fused multiply-adds are
+// written out and no other contraction is allowed here, so both call sites
+// give the same bits and results do not depend on the tile shape.
 template <typename T>
 __device__ __forceinline__ void euler_prims(const T u[5], T gm1, T& iv_rho, T& p) {
+#pragma clang fp contract(off)
   iv_rho = T(1) / u[0];
-  const T ke = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * iv_rho;
-  p = gm1 * (u[4] - ke);
+  const T m2 = fma(u[1], u[1], fma(u[2], u[2], u[3] * u[3]));
+  p = gm1 * fma(T(-0.5) * m2, iv_rho, u[4]);
 }
 
 // Inviscid flux along direction d (0, 1, 2) of conserved state u.
 template <typename T>
 __device__ __forceinline__ void euler_flux(const T u[5], int d, T gm1, T f[5]) {
+#pragma clang fp contract(off)
   T ir, p;
   euler_prims(u, gm1, ir, p);
   const T vel = u[1 + d] * ir;
   f[0] = u[1 + d];
-  f[1] = u[1] * vel;
-  f[2] = u[2] * vel;
-  f[3] = u[3] * vel;
-  f[1 + d] += p;
+  f[1] = d == 0 ? fma(u[1], vel, p) : u[1] * vel;
+  f[2] = d == 1 ? fma(u[2], vel, p) : u[2] * vel;
+  f[3] = d == 2 ? fma(u[3], vel, p) : u[3] * vel;
   f[4] = (u[4] + p) * vel;
 }
 
 template <typename T, int TX, int TY, int KIND>
-__global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T> p) {
-  const TileDev t = p.tiles[blockIdx.x];
+__device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDev t) {
+  // every apron point (4 per tile row and column) has a thread of its own
+  static_assert(4 * (TX + TY) <= TX * TY, "tile shape too narrow for its apron");
   if (t.nx == 0) return;
   // The block descriptor lives in LDS for the whole kernel: re-reading it from
   // global memory inside the plane loop would make every such load wait for
@@ -162,6 +168,54 @@ __global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T
   }
 }
 
+template <typename T, int TX, int TY, int KIND>
+__global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T> p) {
+  const StageParams<T> q = resolve_step(p);
+  euler_tile<T, TX, TY, KIND>(q, p.tiles[blockIdx.x]);
+}
+
+// Persistent form for a batch: every workgroup walks the combined tile list
+// of all members (grid stride); the member's parameters are staged in LDS.
+template <typename T, int TX, int TY, int KIND>
+__global__ void __launch_bounds__(TX* TY)
+    euler_batch_kernel(const StageParams<T>* __restrict__ ps, const BatchTile* __restrict__ tl, int ntiles) {
+  __shared__ StageParams<T> sp;
+  for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
+    const BatchTile bt = tl[i];
+    __syncthreads();
+    stage_struct(ps + bt.inst, &sp);
+    if (threadIdx.x == 0 && sp.nstep) sp = resolve_step(sp);
+    __syncthreads();
+    euler_tile<T, TX, TY, KIND>(sp, bt.t);
+  }
+}
+
+template <typename T, int TX, int TY>
+hipError_t launch_euler_batch_shape(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind,
+                                    hipStream_t s) {
+  dim3 g(grid), b(TX * TY);
+  switch (kind) {
+    case kRK4First: euler_batch_kernel<T, TX, TY, kRK4First><<<g, b, 0, s>>>(ps, tl, ntiles); break;
+    case kRK4Mid: euler_batch_kernel<T, TX, TY, kRK4Mid><<<g, b, 0, s>>>(ps, tl, ntiles); break;
+    case kRK4Last: euler_batch_kernel<T, TX, TY, kRK4Last><<<g, b, 0, s>>>(ps, tl, ntiles); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_euler_batch(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind, int tx,
+                              int ty, hipStream_t s) {
+  if (tx == 16 && ty == 16) return launch_euler_batch_shape<T, 16, 16>(ps, tl, ntiles, grid, kind, s);
+  if (tx == 32 && ty == 8) return launch_euler_batch_shape<T, 32, 8>(ps, tl, ntiles, grid, kind, s);
+  if (tx == 16 && ty == 8) return launch_euler_batch_shape<T, 16, 8>(ps, tl, ntiles, grid, kind, s);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_euler_batch<float>(const StageParams<float>*, const BatchTile*, int, int, int, int, int,
+                                              hipStream_t);
+template hipError_t launch_euler_batch<double>(const StageParams<double>*, const BatchTile*, int, int, int, int, int,
+                                               hipStream_t);
+
 template <typename T, int TX, int TY>
 hipError_t launch_euler_shape(const StageParams<T>& p, int ntiles, int kind, hipStream_t s) {
   dim3 grid(ntiles), block(TX * TY);
@@ -181,9 +235,7 @@ template <typename T>
 hipError_t launch_euler_stage(const StageParams<T>& p, int ntiles, int kind, int tx, int ty, hipStream_t s) {
   if (tx == 16 && ty == 16) return launch_euler_shape<T, 16, 16>(p, ntiles, kind, s);
   if (tx == 32 && ty == 8) return launch_euler_shape<T, 32, 8>(p, ntiles, kind, s);
-  if (tx == 64 && ty == 4) return launch_euler_shape<T, 64, 4>(p, ntiles, kind, s);
   if (tx == 16 && ty == 8) return launch_euler_shape<T, 16, 8>(p, ntiles, kind, s);
-  if (tx == 32 && ty == 4) return launch_euler_shape<T, 32, 4>(p, ntiles, kind, s);
   return hipErrorInvalidValue;
 }
 

@@ -16,9 +16,10 @@ __device__ __forceinline__ unsigned long long sm64(unsigned long long seed, unsi
 // Delays of step n (n >= C) for every (block, slot): CAA (n - C) mod L,
 // SAA SplitMix64 draw mod L, or the injected value; then the Alg. 3 guard.
 __global__ void delays_kernel(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
-                              unsigned long long seed, int algo) {
+                              unsigned long long seed, int algo, const long long* nstep) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nblocks * kNumSlots) return;
+  if (nstep) n = *nstep;
   long long k;
   if (inject) {
     k = inject[i];
@@ -33,9 +34,29 @@ __global__ void delays_kernel(int8_t* out, const int8_t* inject, long long n, in
 }
 
 hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
-                         unsigned long long seed, int algo, hipStream_t s) {
+                         unsigned long long seed, int algo, hipStream_t s, const long long* nstep) {
   const int cnt = nblocks * kNumSlots;
-  delays_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(out, inject, n, nblocks, L, seed, algo);
+  delays_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(out, inject, n, nblocks, L, seed, algo, nstep);
+  return hipGetLastError();
+}
+
+// Device step counters of graph-captured steps.
+__global__ void step_set_kernel(long long* nstep, long long value) { *nstep = value; }
+__global__ void step_inc_kernel(long long* const* counters, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) *counters[i] += 1;
+}
+__global__ void step_inc1_kernel(long long* nstep) { *nstep += 1; }
+hipError_t launch_step_inc1(long long* nstep, hipStream_t s) {
+  step_inc1_kernel<<<1, 1, 0, s>>>(nstep);
+  return hipGetLastError();
+}
+hipError_t launch_step_set(long long* nstep, long long value, hipStream_t s) {
+  step_set_kernel<<<1, 1, 0, s>>>(nstep, value);
+  return hipGetLastError();
+}
+hipError_t launch_step_inc(long long* const* counters, int n, hipStream_t s) {
+  step_inc_kernel<<<(n + 63) / 64, 64, 0, s>>>(counters, n);
   return hipGetLastError();
 }
 
@@ -51,7 +72,8 @@ __global__ void __launch_bounds__(kHaloChunk)
     halo_kernel(const T* __restrict__ ring, T* __restrict__ halo, const HaloRegion* __restrict__ regions,
                 const HaloWork* __restrict__ work, const int8_t* __restrict__ delays,
                 const double* __restrict__ W, long long slot_stride, long long halo_stride, int D,
-                int slot_now, int L) {
+                int slot_now, int L, const long long* nstep) {
+  if (nstep) slot_now = (int)(*nstep % D);
   const HaloWork wk = work[blockIdx.x];
   const HaloRegion rg = regions[wk.region];
   const int i = wk.start + threadIdx.x;
@@ -89,11 +111,12 @@ __global__ void __launch_bounds__(kHaloChunk)
 template <typename T>
 hipError_t launch_halo(const T* ring, T* halo, const HaloRegion* regions, const HaloWork* work, int nwork,
                        const int8_t* delays, const double* W, long long slot_stride, long long halo_stride,
-                       int D, int slot_now, int L, int stages, bool stale, hipStream_t s) {
+                       int D, int slot_now, int L, int stages, bool stale, hipStream_t s,
+                       const long long* nstep) {
   dim3 grid(nwork), block(kHaloChunk);
 #define ATNS_HALO(SS, ST)                                                                               \
   halo_kernel<T, SS, ST><<<grid, block, 0, s>>>(ring, halo, regions, work, delays, W, slot_stride, \
-                                                 halo_stride, D, slot_now, L)
+                                                 halo_stride, D, slot_now, L, nstep)
   if (stages == 4) {
     if (stale) ATNS_HALO(4, true); else ATNS_HALO(4, false);
   } else {
@@ -104,10 +127,10 @@ hipError_t launch_halo(const T* ring, T* halo, const HaloRegion* regions, const 
 }
 template hipError_t launch_halo<float>(const float*, float*, const HaloRegion*, const HaloWork*, int,
                                        const int8_t*, const double*, long long, long long, int, int, int,
-                                       int, bool, hipStream_t);
+                                       int, bool, hipStream_t, const long long*);
 template hipError_t launch_halo<double>(const double*, double*, const HaloRegion*, const HaloWork*, int,
                                         const int8_t*, const double*, long long, long long, int, int, int,
-                                        int, bool, hipStream_t);
+                                        int, bool, hipStream_t, const long long*);
 
 // Copy the boundary layers of every block of field U into ring slot `slot`.
 template <typename T>

@@ -29,10 +29,9 @@
 namespace atns {
 
 template <typename T, int TX, int TY, int KIND, int NDIM>
-__global__ void __launch_bounds__((TX + 8) * (TY + 8)) ns_stage_kernel(const StageParams<T> p) {
+__device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t) {
   constexpr int EX = TX + 8, EY = TY + 8;
   constexpr bool three = (NDIM == 3);
-  const TileDev t = p.tiles[blockIdx.x];
   if (t.nx == 0) return;
   // The block descriptor lives in LDS for the whole kernel: re-reading it from
   // global memory inside the plane loop would make every such load wait for
@@ -275,6 +274,53 @@ __global__ void __launch_bounds__((TX + 8) * (TY + 8)) ns_stage_kernel(const Sta
     }
   }
 }
+
+template <typename T, int TX, int TY, int KIND, int NDIM>
+__global__ void __launch_bounds__((TX + 8) * (TY + 8)) ns_stage_kernel(const StageParams<T> p) {
+  const StageParams<T> q = resolve_step(p);
+  ns_tile<T, TX, TY, KIND, NDIM>(q, p.tiles[blockIdx.x]);
+}
+
+// Persistent form for a batch (see the Euler kernel).
+template <typename T, int TX, int TY, int KIND>
+__global__ void __launch_bounds__((TX + 8) * (TY + 8))
+    ns_batch_kernel(const StageParams<T>* __restrict__ ps, const BatchTile* __restrict__ tl, int ntiles) {
+  __shared__ StageParams<T> sp;
+  for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
+    const BatchTile bt = tl[i];
+    __syncthreads();
+    stage_struct(ps + bt.inst, &sp);
+    if (threadIdx.x == 0 && sp.nstep) sp = resolve_step(sp);
+    __syncthreads();
+    ns_tile<T, TX, TY, KIND, 3>(sp, bt.t);
+  }
+}
+
+template <typename T, int TX, int TY>
+hipError_t launch_ns_batch_shape(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind,
+                                 hipStream_t s) {
+  dim3 g(grid), b((TX + 8) * (TY + 8));
+  switch (kind) {
+    case kRK4First: ns_batch_kernel<T, TX, TY, kRK4First><<<g, b, 0, s>>>(ps, tl, ntiles); break;
+    case kRK4Mid: ns_batch_kernel<T, TX, TY, kRK4Mid><<<g, b, 0, s>>>(ps, tl, ntiles); break;
+    case kRK4Last: ns_batch_kernel<T, TX, TY, kRK4Last><<<g, b, 0, s>>>(ps, tl, ntiles); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ns_batch(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind, int tx,
+                           int ty, hipStream_t s) {
+  if (tx == 16 && ty == 16) return launch_ns_batch_shape<T, 16, 16>(ps, tl, ntiles, grid, kind, s);
+  if (tx == 32 && ty == 8) return launch_ns_batch_shape<T, 32, 8>(ps, tl, ntiles, grid, kind, s);
+  if (tx == 16 && ty == 8) return launch_ns_batch_shape<T, 16, 8>(ps, tl, ntiles, grid, kind, s);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_ns_batch<float>(const StageParams<float>*, const BatchTile*, int, int, int, int, int,
+                                           hipStream_t);
+template hipError_t launch_ns_batch<double>(const StageParams<double>*, const BatchTile*, int, int, int, int, int,
+                                            hipStream_t);
 
 template <typename T, int KIND, int TX, int TY>
 hipError_t launch_ns_kind(const StageParams<T>& p, int ntiles, hipStream_t s) {

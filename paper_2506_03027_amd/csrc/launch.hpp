@@ -12,12 +12,23 @@ template <typename T>
 hipError_t launch_ns_stage(const StageParams<T>& p, int ntiles, int kind, int tx, int ty, hipStream_t s);
 
 template <typename T>
+hipError_t launch_euler_batch(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind, int tx,
+                              int ty, hipStream_t s);
+template <typename T>
+hipError_t launch_ns_batch(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind, int tx,
+                           int ty, hipStream_t s);
+hipError_t launch_step_set(long long* nstep, long long value, hipStream_t s);
+hipError_t launch_step_inc(long long* const* counters, int n, hipStream_t s);
+hipError_t launch_step_inc1(long long* nstep, hipStream_t s);
+
+template <typename T>
 hipError_t launch_halo(const T* ring, T* halo, const HaloRegion* regions, const HaloWork* work, int nwork,
                        const int8_t* delays, const double* W, long long slot_stride, long long halo_stride,
-                       int D, int slot_now, int L, int stages, bool stale, hipStream_t s);
+                       int D, int slot_now, int L, int stages, bool stale, hipStream_t s,
+                       const long long* nstep = nullptr);
 hipError_t launch_copy_probe(const void* src, void* dst, long long bytes, hipStream_t s);
 hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
-                         unsigned long long seed, int algo, hipStream_t s);
+                         unsigned long long seed, int algo, hipStream_t s, const long long* nstep = nullptr);
 template <typename T>
 hipError_t launch_ring_fill(const StageParams<T>& p, const T* U, int slot, int nblocks, hipStream_t s);
 template <typename T>

@@ -80,6 +80,12 @@ struct TileDev {
   short nx, ny, nz;         // tile extent (nx == 0: padding tile, no work)
 };
 
+// A tile of one member of a batch.
+struct BatchTile {
+  int inst;      // member index
+  TileDev t;
+};
+
 // Stage epilogue kinds.
 enum StageKind {
   kRhsOnly = 0,   // Yout = R
@@ -108,6 +114,10 @@ struct StageParams {
   int D;                 // ring depth
   int slot_now;          // n % D
   int halo;              // HaloMode for this stage
+  // When nstep is set (graph-captured steps), n is read from this device
+  // counter: slot_now = n % D and halo = (n >= C) ? async_halo : kHaloSync.
+  const long long* nstep;
+  int async_halo;
   int L;
   int H;                 // halo depth (faces)
   int ndim;

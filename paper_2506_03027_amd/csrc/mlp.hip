@@ -156,14 +156,15 @@ __device__ __forceinline__ void face_features(const MlpFeatArgs<T>& a, const Hal
     idx[j] = (cc[2] * fi.ext[1] + cc[1]) * fi.ext[0] + cc[0];
   }
   float centre[5];
-  int sl0 = a.slot_now - k;
+  const int snow = a.nstep ? (int)(*a.nstep % a.D) : a.slot_now;
+  int sl0 = snow - k;
   sl0 += (sl0 < 0) ? a.D : 0;
   const T* base0 = a.ring + (long long)sl0 * a.slot_stride + rg.src;
 #pragma unroll
   for (int v = 0; v < 5; ++v) centre[v] = (float)base0[(long long)v * rg.npts + idx[1]];
   int f = 0;
   for (int l = 0; l < 4; ++l) {
-    int sl = a.slot_now - k - l;
+    int sl = snow - k - l;
     sl += (sl < 0) ? a.D : 0;
     const T* base = a.ring + (long long)sl * a.slot_stride + rg.src;
 #pragma unroll

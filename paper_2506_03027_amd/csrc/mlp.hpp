@@ -38,6 +38,7 @@ struct MlpFeatArgs {
   long long slot_stride;
   int D;
   int slot_now;
+  const long long* nstep;   // when set, slot_now = *nstep % D
   int L;
   float inv_s[5];   // 1 / feature scale per variable
   float inv_r[5];   // 1 / target scale per variable

@@ -11,17 +11,26 @@ from paper_2506_03027_amd import atns, inputs
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = {"euler": [(16, 16), (32, 8), (64, 4), (16, 8), (32, 4)],
+SHAPES = {"euler": [(16, 16), (32, 8), (16, 8)],
           "ns": [(16, 16), (32, 8), (16, 8)]}
 
 
+GRIDS = {
+    # narrow, ragged blocks: partial tiles everywhere
+    "ragged": dict(n=(40, 36, 24), length=(6.0, 5.0, 4.0), nblk=(3, 2, 2),
+                   split=([20, 12, 8], [20, 16], [13, 11])),
+    # one wide block: full tiles of every shape (and a partial z column)
+    "wide": dict(n=(64, 48, 20), length=(8.0, 6.0, 2.5), nblk=(1, 1, 1), split=None),
+}
+
+
+@pytest.mark.parametrize("grid", ["ragged", "wide"])
 @pytest.mark.parametrize("physics", ["euler", "ns"])
-def test_all_tile_shapes_bitwise_equal(physics):
+def test_all_tile_shapes_bitwise_equal(physics, grid):
     torch = need_gpu()
-    announce("tiles", physics)
-    n = (40, 36, 24)
-    box = (6.0, 5.0, 4.0)
-    split = ([20, 12, 8], [20, 16], [13, 11])
+    announce("tiles", physics, grid)
+    gd = GRIDS[grid]
+    n, box = gd["n"], gd["length"]
     U0 = inputs.smooth_random_state(n, box, seed=2)
     dt = inputs.cfl_dt(U0, n, box, 3, 1.4, 0.03)
     ref = None
@@ -29,7 +38,7 @@ def test_all_tile_shapes_bitwise_equal(physics):
         for tz in (4, 7, 16):
             if physics == "ns" and tz < 8 and (tx, ty) != (16, 16):
                 continue
-            _, g = pair(dict(n=n, length=box, nblk=(3, 2, 2), split=split, physics=physics,
+            _, g = pair(dict(n=n, length=box, nblk=gd["nblk"], split=gd["split"], physics=physics,
                              mode="at", algo="saa", L=3, seed=5, re=200.0, mach=0.3), "f32", dt=dt)
             g.set_tiles(tx, ty, tz)
             assert g.get_tiles() == (tx, ty, tz)
@@ -37,6 +46,7 @@ def test_all_tile_shapes_bitwise_equal(physics):
             g.step(8)
             out = to_np(g.get_state())
             g.close()
+            assert np.isfinite(out).all(), (tx, ty, tz)
             if ref is None:
                 ref = out
             else:
@@ -48,6 +58,8 @@ def test_bad_tile_shape_rejected():
     _, g = pair(dict(n=(16, 16, 16), length=(1.0, 1.0, 1.0), nblk=(1, 1, 1)), "f32")
     with pytest.raises(atns.AtnsError):
         g.set_tiles(8, 8, 4)
+    with pytest.raises(atns.AtnsError):
+        g.set_tiles(64, 4, 4)
     with pytest.raises(atns.AtnsError):
         g.set_tiles(16, 16, 0)
 

@@ -83,3 +83,19 @@ def test_host_helpers_reject_bad_arguments():
     assert atns.lib().atns_host_weights(9, atns.AT, 4, out.ctypes.data) == -1
     k = np.zeros(18, dtype=np.int8)
     assert atns.lib().atns_host_delays(atns.SAA, -1, 1, 4, 0, k.ctypes.data, None) == -1
+
+
+def test_batch_create_rejects_bad_members_without_device():
+    import ctypes
+    good = dict(n=(32, 32, 32), length=(1.0, 1.0, 1.0), ndim=3, nblk=(2, 2, 2))
+    for members in ([dict(good, rk=atns.LSERK4)],
+                    [good, dict(good, precision=atns.F64)],
+                    [dict(good, L=0)]):
+        made = [atns.make_config(**kw) for kw in members]
+        arr = (atns.Config * len(made))(*[m[0] for m in made])
+        h = ctypes.c_void_p()
+        assert atns.lib().atns_batch_create(arr, len(made), None, ctypes.byref(h)) == -1
+        assert h.value is None
+        assert len(atns.lib().atns_batch_last_error(None)) > 0
+    arr = (atns.Config * 1)(atns.make_config(**good)[0])
+    assert atns.lib().atns_batch_create(arr, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
