@@ -31,8 +31,9 @@
  *   array with x fastest: element (v, k, j, i) at ((v*nz + k)*ny + j)*nx + i.
  *   The element type is float (ATNS_F32) or double (ATNS_F64).
  * - Work is enqueued on the stream given to atns_create() (NULL = the null
- *   stream).  Only atns_reduce(), atns_get_state(on_host=1) and
- *   atns_get_delays() synchronize with the host.
+ *   stream).  Only atns_reduce(), atns_get_state(on_host=1),
+ *   atns_get_delays(), atns_checkpoint() and atns_restore() synchronize
+ *   with the host.
  * - Steps are numbered n = 0, 1, ...; step n advances U^n to U^{n+1}.
  *
  * Neighbour slots (index into delay arrays):
@@ -120,6 +121,40 @@ atns_status atns_set_state(atns_ctx* ctx, const void* dev_U, int64_t step);
 /* Copy the current state into dst (device pointer if on_host == 0, host
  * pointer otherwise; host copies synchronize). */
 atns_status atns_get_state(const atns_ctx* ctx, void* dst, int32_t on_host);
+
+/* Analytic initial field, evaluated in FP64 on the device and rounded to the
+ * context precision, set as U^step exactly as atns_set_state would (ring
+ * slot included).  Coordinates x_i = i len/n (periodic, no duplicated end).
+ *  ATNS_CASE_VORTEX: the isentropic vortex used for the inviscid tests
+ *    (Sec. 5.1 tests the method on a vortex; this is the textbook translating
+ *    isentropic vortex): rho_inf = p_inf = T_inf = 1, p = rho T, freestream
+ *    of speed mach*sqrt(gamma) along (1,1)/sqrt2 (2-D) or (1,1,1)/sqrt3
+ *    (3-D, vortex axis z); perturbation du = -(beta/2pi)(y-yc) e^((1-r^2)/2),
+ *    dv = (beta/2pi)(x-xc) e^((1-r^2)/2), T = 1 - (gamma-1) beta^2 e^(1-r^2)
+ *    / (8 gamma pi^2), rho = T^(1/(gamma-1)), r the minimum-image distance to
+ *    the centre carried by the freestream for time t.  params (np <= 5, in
+ *    this order, defaults in brackets): t [0], beta [5], mach [0.5],
+ *    xc [5], yc [5].
+ *  ATNS_CASE_TGV: the Taylor-Green vortex of Sec. 5.2 (Eq. 16) with
+ *    rho0 = U0 = L0 = 1, v = -cos x sin y cos z (the divergence-free sign),
+ *    uniform T0 = 1 so rho = gamma M^2 p, M = cfg.mach; 3-D only; np = 0.
+ * EINVAL for unknown cases or bad parameter lists. */
+enum { ATNS_CASE_VORTEX = 0, ATNS_CASE_TGV = 1 };
+atns_status atns_init_case(atns_ctx* ctx, int32_t case_id, const double* params, int32_t np, int64_t step);
+
+/* Checkpoint and restart.  atns_checkpoint with host_blob == NULL stores the
+ * record size in *bytes; otherwise it writes the restart record into the
+ * host buffer host_blob of *bytes bytes (EINVAL if smaller than the record,
+ * ESTATE before any state is set), sets *bytes to the record size and
+ * synchronizes.  The record holds the state, the delayed-level ring, the
+ * step number, dt and a fingerprint of the configuration (grid, blocks,
+ * physics, scheme, delays, seed, precision).  atns_restore accepts only a
+ * record of an identically configured context (EINVAL otherwise, nothing
+ * changed) and leaves the context as the checkpointed one was, so stepping
+ * on gives the same bits.  Learned-halo parameters and settings are not
+ * part of the record (atns_mlp_get_params / atns_mlp_set_params). */
+atns_status atns_checkpoint(atns_ctx* ctx, void* host_blob, size_t* bytes);
+atns_status atns_restore(atns_ctx* ctx, const void* host_blob, size_t bytes);
 
 /* Current step number n. */
 atns_status atns_get_step(const atns_ctx* ctx, int64_t* step);

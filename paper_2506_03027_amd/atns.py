@@ -18,6 +18,7 @@ RK4, LSERK4 = 0, 1
 SA, AS, AT = 0, 1, 2
 CAA, SAA = 0, 1
 F32, F64 = 0, 1
+CASE_VORTEX, CASE_TGV = 0, 1
 NSLOTS = 18
 NDIAG = 7
 C_LEVELS = 5
@@ -32,7 +33,7 @@ EXPORTS = ["atns_version", "atns_create", "atns_destroy", "atns_last_error", "at
            "atns_mlp_grad", "atns_mlp_sample", "atns_mlp_train", "atns_mlp_enable", "atns_mlp_stats",
            "atns_hbm_probe", "atns_host_weights", "atns_host_delays", "atns_batch_create",
            "atns_batch_destroy", "atns_batch_last_error", "atns_batch_member", "atns_batch_set_tiles",
-           "atns_batch_autotune", "atns_batch_step"]
+           "atns_batch_autotune", "atns_batch_step", "atns_init_case", "atns_checkpoint", "atns_restore"]
 MLP_PARAMS = 9360
 
 
@@ -101,6 +102,9 @@ def lib():
             "atns_batch_set_tiles": ([vp, i32, i32, i32, i32], i32),
             "atns_batch_autotune": ([vp, i32, vp], i32),
             "atns_batch_step": ([vp, i32], i32),
+            "atns_init_case": ([vp, i32, vp, i32, i64], i32),
+            "atns_checkpoint": ([vp, vp, ctypes.POINTER(ctypes.c_size_t)], i32),
+            "atns_restore": ([vp, vp, ctypes.c_size_t], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -208,6 +212,27 @@ class Solver:
         _check(lib().atns_get_state(self.ctx, ctypes.c_void_p(out.data_ptr()), 0), self.ctx)
         self.torch.cuda.synchronize()
         return out
+
+    def init_case(self, case, params=(), step=0):
+        """Analytic initial field computed on the device (CASE_VORTEX with
+        params (t, beta, mach, xc, yc) as a prefix, or CASE_TGV)."""
+        pa = np.ascontiguousarray(params, dtype=np.float64)
+        self.torch.cuda.synchronize()
+        _check(lib().atns_init_case(self.ctx, int(case), pa.ctypes.data if pa.size else None, int(pa.size),
+                                    int(step)), self.ctx)
+
+    def checkpoint(self):
+        """Restart record (bytes) of the current state, ring, step and dt."""
+        n = ctypes.c_size_t(0)
+        _check(lib().atns_checkpoint(self.ctx, None, ctypes.byref(n)), self.ctx)
+        buf = ctypes.create_string_buffer(n.value)
+        self.torch.cuda.synchronize()
+        _check(lib().atns_checkpoint(self.ctx, buf, ctypes.byref(n)), self.ctx)
+        return buf.raw[:n.value]
+
+    def restore(self, blob):
+        self.torch.cuda.synchronize()
+        _check(lib().atns_restore(self.ctx, ctypes.c_char_p(blob), len(blob)), self.ctx)
 
     def set_dt(self, dt):
         _check(lib().atns_set_dt(self.ctx, float(dt)), self.ctx)

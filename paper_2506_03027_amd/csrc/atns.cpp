@@ -756,11 +756,13 @@ atns_status atns_destroy(atns_ctx* ctx) {
   return ATNS_OK;
 }
 
-atns_status atns_set_state(atns_ctx* c, const void* dev_U, int64_t step) {
-  if (!c || !dev_U) return fail(c, ATNS_EINVAL, "null argument");
-  if (step < 0) return fail(c, ATNS_EINVAL, "negative step");
-  void* dst = state_ptr(c);
-  HIP_TRY(c, hipMemcpyAsync(dst, dev_U, (size_t)c->field * 5 * c->esz, hipMemcpyDeviceToDevice, c->stream));
+}  // extern "C"
+
+namespace {
+
+// The state now in state_ptr(c) becomes the state of `step`: its boundary
+// layers go into the ring slot of that step.
+atns_status adopt_state(atns_ctx* c, int64_t step) {
   c->step = step;
   c->state_set = true;
   c->nstep_synced = false;
@@ -768,12 +770,138 @@ atns_status atns_set_state(atns_ctx* c, const void* dev_U, int64_t step) {
     const int slot = (int)(step % c->D);
     if (c->esz == 4) {
       StageParams<float> p = base_params<float>(c);
-      HIP_TRY(c, launch_ring_fill<float>(p, (const float*)dst, slot, c->nb, c->stream));
+      HIP_TRY(c, launch_ring_fill<float>(p, (const float*)state_ptr(c), slot, c->nb, c->stream));
     } else {
       StageParams<double> p = base_params<double>(c);
-      HIP_TRY(c, launch_ring_fill<double>(p, (const double*)dst, slot, c->nb, c->stream));
+      HIP_TRY(c, launch_ring_fill<double>(p, (const double*)state_ptr(c), slot, c->nb, c->stream));
     }
   }
+  return ATNS_OK;
+}
+
+// Fingerprint of everything a restart record depends on (FNV-1a).
+uint64_t config_fingerprint(const atns_ctx* c) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  const atns_config& g = c->cfg;
+  mix(&g.ndim, sizeof g.ndim);
+  mix(g.n, sizeof g.n);
+  mix(g.len, sizeof g.len);
+  mix(&g.physics, sizeof g.physics);
+  mix(&g.gamma, sizeof g.gamma);
+  mix(&g.mach, sizeof g.mach);
+  mix(&g.re, sizeof g.re);
+  mix(&g.pr, sizeof g.pr);
+  mix(&g.rk, sizeof g.rk);
+  mix(&g.mode, sizeof g.mode);
+  mix(&g.algo, sizeof g.algo);
+  mix(&g.L, sizeof g.L);
+  mix(&g.seed, sizeof g.seed);
+  mix(&g.precision, sizeof g.precision);
+  for (const BlockDev& B : c->blocks) {
+    mix(B.o, sizeof B.o);
+    mix(B.s, sizeof B.s);
+  }
+  return h;
+}
+
+struct CkptHeader {
+  char magic[8];
+  uint64_t fingerprint;
+  int64_t step;
+  double dt;
+  uint64_t state_bytes, ring_bytes;
+};
+const char kCkptMagic[8] = {'A', 'T', 'N', 'S', 'C', 'K', 'P', '1'};
+
+}  // namespace
+
+extern "C" {
+
+atns_status atns_set_state(atns_ctx* c, const void* dev_U, int64_t step) {
+  if (!c || !dev_U) return fail(c, ATNS_EINVAL, "null argument");
+  if (step < 0) return fail(c, ATNS_EINVAL, "negative step");
+  HIP_TRY(c, hipMemcpyAsync(state_ptr(c), dev_U, (size_t)c->field * 5 * c->esz, hipMemcpyDeviceToDevice,
+                            c->stream));
+  return adopt_state(c, step);
+}
+
+atns_status atns_init_case(atns_ctx* c, int32_t case_id, const double* params, int32_t np, int64_t step) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  if (step < 0) return fail(c, ATNS_EINVAL, "negative step");
+  if (np < 0 || (np > 0 && !params)) return fail(c, ATNS_EINVAL, "bad parameter list");
+  // vortex parameters, in order, with their defaults: t, beta, mach, xc, yc
+  double vp[5] = {0.0, 5.0, 0.5, 5.0, 5.0};
+  if (case_id == ATNS_CASE_VORTEX) {
+    if (np > 5) return fail(c, ATNS_EINVAL, "the vortex takes at most 5 parameters");
+    for (int i = 0; i < np; ++i) vp[i] = params[i];
+  } else if (case_id == ATNS_CASE_TGV) {
+    if (np != 0) return fail(c, ATNS_EINVAL, "the Taylor-Green case takes no parameters");
+    if (c->cfg.ndim != 3) return fail(c, ATNS_EINVAL, "the Taylor-Green case is three-dimensional");
+    vp[2] = c->cfg.mach;
+  } else {
+    return fail(c, ATNS_EINVAL, "unknown case");
+  }
+  const int kind = case_id == ATNS_CASE_VORTEX ? 0 : 1;
+  const hipError_t e =
+      c->esz == 4 ? launch_init_case<float>((float*)state_ptr(c), c->n, c->h, c->cfg.len, kind, c->cfg.ndim,
+                                            c->cfg.gamma, vp[2], vp[1], vp[0], vp[3], vp[4], c->stream)
+                  : launch_init_case<double>((double*)state_ptr(c), c->n, c->h, c->cfg.len, kind, c->cfg.ndim,
+                                             c->cfg.gamma, vp[2], vp[1], vp[0], vp[3], vp[4], c->stream);
+  if (e != hipSuccess) return fail(c, ATNS_EHIP, std::string("init_case: ") + hipGetErrorString(e));
+  return adopt_state(c, step);
+}
+
+atns_status atns_checkpoint(atns_ctx* c, void* host_blob, size_t* bytes) {
+  if (!c || !bytes) return fail(c, ATNS_EINVAL, "null argument");
+  const size_t sb = (size_t)c->field * 5 * c->esz;
+  const size_t rb = c->ring ? (size_t)c->slot_stride * c->D * c->esz : 0;
+  const size_t need = sizeof(CkptHeader) + sb + rb;
+  if (!host_blob) {
+    *bytes = need;
+    return ATNS_OK;
+  }
+  if (*bytes < need) return fail(c, ATNS_EINVAL, "checkpoint buffer too small");
+  if (!c->state_set) return fail(c, ATNS_ESTATE, "no state to checkpoint");
+  CkptHeader h;
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.fingerprint = config_fingerprint(c);
+  h.step = c->step;
+  h.dt = c->dt;
+  h.state_bytes = sb;
+  h.ring_bytes = rb;
+  char* out = (char*)host_blob;
+  std::memcpy(out, &h, sizeof h);
+  HIP_TRY(c, hipMemcpyAsync(out + sizeof h, state_ptr(c), sb, hipMemcpyDeviceToHost, c->stream));
+  if (rb) HIP_TRY(c, hipMemcpyAsync(out + sizeof h + sb, c->ring, rb, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *bytes = need;
+  return ATNS_OK;
+}
+
+atns_status atns_restore(atns_ctx* c, const void* host_blob, size_t bytes) {
+  if (!c || !host_blob) return fail(c, ATNS_EINVAL, "null argument");
+  CkptHeader h;
+  if (bytes < sizeof h) return fail(c, ATNS_EINVAL, "not a restart record");
+  std::memcpy(&h, host_blob, sizeof h);
+  const size_t sb = (size_t)c->field * 5 * c->esz;
+  const size_t rb = c->ring ? (size_t)c->slot_stride * c->D * c->esz : 0;
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0) return fail(c, ATNS_EINVAL, "not a restart record");
+  if (h.fingerprint != config_fingerprint(c) || h.state_bytes != sb || h.ring_bytes != rb)
+    return fail(c, ATNS_EINVAL, "restart record of a different configuration");
+  if (bytes < sizeof h + sb + rb) return fail(c, ATNS_EINVAL, "truncated restart record");
+  const char* in = (const char*)host_blob;
+  HIP_TRY(c, hipMemcpyAsync(state_ptr(c), in + sizeof h, sb, hipMemcpyHostToDevice, c->stream));
+  if (rb) HIP_TRY(c, hipMemcpyAsync(c->ring, in + sizeof h + sb, rb, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (h.dt > 0 && h.dt != c->dt) drop_graphs(c);
+  if (h.dt > 0) c->dt = h.dt;
+  c->step = h.step;
+  c->state_set = true;
+  c->nstep_synced = false;
   return ATNS_OK;
 }
 

@@ -170,6 +170,98 @@ __global__ void __launch_bounds__(256) copy_probe_kernel(const float4* __restric
     dst[i] = src[i];
 }
 
+// Analytic initial fields, evaluated in FP64 and rounded to the state type.
+// kind 0: isentropic vortex (uniform freestream of speed mach*sqrt(gamma)
+// along the diagonal, Gaussian vortex of strength beta about (xc, yc) carried
+// by it for time t, minimum-image distance on the periodic box);
+// kind 1: Taylor-Green vortex (Sec. 5.2, Eq. 16, with the divergence-free sign
+// of v and uniform initial temperature).
+struct InitArgs {
+  int n[3];
+  double h[3], len[3];
+  int kind, ndim;
+  double gamma, mach, beta, t, xc, yc;
+};
+
+__device__ __forceinline__ double floor_mod(double a, double L) {
+  double m = fmod(a, L);
+  if (m < 0.0) m += L;
+  return m;
+}
+
+template <typename T>
+__global__ void init_case_kernel(T* __restrict__ U, InitArgs a, long long field) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= field) return;
+  const int x = (int)(i % a.n[0]);
+  const long long r = i / a.n[0];
+  const int y = (int)(r % a.n[1]);
+  const int z = (int)(r / a.n[1]);
+  const double X = x * a.h[0], Y = y * a.h[1], Z = z * a.h[2];
+  const double g = a.gamma;
+  double rho, u, v, w, p;
+  if (a.kind == 0) {
+    const double speed = a.mach * sqrt(g);
+    double ui[3];
+    if (a.ndim == 2) {
+      ui[0] = ui[1] = speed / sqrt(2.0);
+      ui[2] = 0.0;
+    } else {
+      ui[0] = ui[1] = ui[2] = speed / sqrt(3.0);
+    }
+    const double xc = a.xc + ui[0] * a.t, yc = a.yc + ui[1] * a.t;
+    const double dx = floor_mod(X - xc + 0.5 * a.len[0], a.len[0]) - 0.5 * a.len[0];
+    const double dy = floor_mod(Y - yc + 0.5 * a.len[1], a.len[1]) - 0.5 * a.len[1];
+    const double r2 = dx * dx + dy * dy;
+    const double f = exp(0.5 * (1.0 - r2));
+    const double pi = 3.14159265358979323846;
+    u = ui[0] - a.beta / (2.0 * pi) * dy * f;
+    v = ui[1] + a.beta / (2.0 * pi) * dx * f;
+    w = ui[2];
+    const double temp = 1.0 - (g - 1.0) * a.beta * a.beta * exp(1.0 - r2) / (8.0 * g * pi * pi);
+    rho = pow(temp, 1.0 / (g - 1.0));
+    p = rho * temp;
+  } else {
+    u = sin(X) * cos(Y) * cos(Z);
+    v = -cos(X) * sin(Y) * cos(Z);
+    w = 0.0;
+    p = 1.0 / (g * a.mach * a.mach) + (cos(2.0 * X) + cos(2.0 * Y)) * (cos(2.0 * Z) + 2.0) / 16.0;
+    rho = g * a.mach * a.mach * p;
+  }
+  const double et = p / (g - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
+  U[i] = (T)rho;
+  U[field + i] = (T)(rho * u);
+  U[2 * field + i] = (T)(rho * v);
+  U[3 * field + i] = (T)(rho * w);
+  U[4 * field + i] = (T)et;
+}
+
+template <typename T>
+hipError_t launch_init_case(T* U, const int n[3], const double h[3], const double len[3], int kind, int ndim,
+                            double gamma, double mach, double beta, double t, double xc, double yc, hipStream_t s) {
+  InitArgs a;
+  for (int d = 0; d < 3; ++d) {
+    a.n[d] = n[d];
+    a.h[d] = h[d];
+    a.len[d] = len[d];
+  }
+  a.kind = kind;
+  a.ndim = ndim;
+  a.gamma = gamma;
+  a.mach = mach;
+  a.beta = beta;
+  a.t = t;
+  a.xc = xc;
+  a.yc = yc;
+  const long long field = (long long)n[0] * n[1] * n[2];
+  init_case_kernel<T><<<(unsigned)((field + 255) / 256), 256, 0, s>>>(U, a, field);
+  return hipGetLastError();
+}
+template hipError_t launch_init_case<float>(float*, const int*, const double*, const double*, int, int, double, double,
+                                            double, double, double, double, hipStream_t);
+template hipError_t launch_init_case<double>(double*, const int*, const double*, const double*, int, int, double,
+                                             double, double, double, double, double, hipStream_t);
+
 hipError_t launch_copy_probe(const void* src, void* dst, long long bytes, hipStream_t s) {
   const long long n16 = bytes / 16;
   copy_probe_kernel<<<4096, 256, 0, s>>>((const float4*)src, (float4*)dst, n16);

@@ -142,3 +142,37 @@ WORKLOADS = {
                     algo="saa", L=5, re=1600.0, mach=0.1, cfl=0.01,
                     precision="f32"),
 }
+
+
+def block_split(n, bmax=32):
+    """Blocks of bmax points along an axis, the remainder as a last, smaller
+    block (uneven at the remainder)."""
+    q, r = divmod(n, bmax)
+    return [bmax] * q + ([r] if r else [])
+
+
+def batch_instances(seed=7, count=48, cubes=40):
+    """A seeded batch of independent 3-D instances of uneven sizes: `cubes`
+    cubes with sides drawn from {32, 48, ..., 160} and the rest boxes of
+    other aspect ratios; alternately the isentropic vortex (Euler, [0,10]^3)
+    and the Taylor-Green vortex (Navier-Stokes, Re 1600, Mach 0.1,
+    [0,2pi]^3); SAA delays with L drawn from {1, 2, 4}; blocks of at most
+    32^3 points, uneven at the remainders."""
+    rng = np.random.default_rng(seed)
+    aspect = [(192, 64, 48), (160, 96, 32), (128, 48, 80), (64, 160, 48),
+              (96, 32, 144), (176, 80, 32), (48, 112, 96), (144, 64, 64)]
+    out = []
+    for i in range(count):
+        if i < cubes:
+            s = int(rng.choice(np.arange(32, 161, 16)))
+            n = (s, s, s)
+        else:
+            n = aspect[(i - cubes) % len(aspect)]
+        ns = i % 2 == 1
+        split = tuple(block_split(n[d]) for d in range(3))
+        out.append(dict(n=n, length=(2 * math.pi,) * 3 if ns else (10.0, 10.0, 10.0), ndim=3,
+                        nblk=tuple(len(s) for s in split), split=split,
+                        physics="ns" if ns else "euler", rk="rk4", mode="at", algo="saa",
+                        L=int(rng.choice([1, 2, 4])), seed=1000 + i, re=1600.0, mach=0.1,
+                        cfl=0.02, precision="f32"))
+    return out

@@ -99,3 +99,34 @@ def test_batch_create_rejects_bad_members_without_device():
         assert len(atns.lib().atns_batch_last_error(None)) > 0
     arr = (atns.Config * 1)(atns.make_config(**good)[0])
     assert atns.lib().atns_batch_create(arr, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
+
+
+def test_new_entry_points_reject_null_without_device():
+    import ctypes
+    n = ctypes.c_size_t(0)
+    assert atns.lib().atns_checkpoint(None, None, ctypes.byref(n)) == -1
+    assert atns.lib().atns_restore(None, b"x", 1) == -1
+    assert atns.lib().atns_init_case(None, 0, None, 0, 0) == -1
+
+
+def test_batch_instances_are_valid_configs():
+    """The seeded batch workload: 48 instances whose block splits tile the
+    grid with blocks of at most 32 points and at least the halo depth; the
+    library's validation (which runs before any device call) accepts them."""
+    import ctypes
+    from paper_2506_03027_amd import inputs
+    ws = inputs.batch_instances()
+    assert len(ws) == 48 and sum(w["physics"] == "euler" for w in ws) == 24
+    assert {w["L"] for w in ws} <= {1, 2, 4}
+    for w in ws:
+        for d in range(3):
+            assert sum(w["split"][d]) == w["n"][d]
+            assert all(4 <= s <= 32 for s in w["split"][d])
+        cfg, keep = atns.make_config(n=w["n"], length=w["length"], ndim=3, nblk=w["nblk"], split=w["split"],
+                                     physics=atns.NS if w["physics"] == "ns" else atns.EULER, mode=atns.AT,
+                                     algo=atns.SAA, L=w["L"])
+        ctx = ctypes.c_void_p()
+        st = atns.lib().atns_create(ctypes.byref(cfg), None, ctypes.byref(ctx))
+        if ctx.value:
+            atns.lib().atns_destroy(ctx)
+        assert st != -1, atns.lib().atns_last_error(None)
