@@ -34,12 +34,9 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
 C_LEVELS = 5
 
 
-def algorithmic_bytes_per_point_stage(w, stages, esz):
-    """Bytes the method must move per owned point per RK stage: the state in
-    and out plus one RK register (80 B at FP32, averaged over the stages),
-    plus, for delayed halos, C ring levels (AT; one level for AS) of 5
-    values per halo point, plus the ring write of the boundary layers once
-    per step.  f = halo points per owned point of a block."""
+def halo_fraction(w):
+    """f = halo points per owned point of a block: faces of depth H (2 for
+    Euler, 4 for Navier-Stokes) and, for Navier-Stokes, the 2x2 edge prisms."""
     n, nb, ndim = w["n"], w["nblk"], w["ndim"]
     H = 4 if w["physics"] == "ns" else 2
     b = [n[d] // nb[d] for d in range(3)]
@@ -59,12 +56,34 @@ def algorithmic_bytes_per_point_stage(w, stages, esz):
                     other = [x for x in dims if x not in (d, e)]
                     length = b[other[0]] if other else 1
                     halo += 4 * 4 * length
-    f = halo / own
+    return halo / own
+
+
+def algorithmic_bytes_per_point_stage(w, stages, esz):
+    """Bytes the method must move per owned point per RK stage, whole step:
+    the state in and out plus one RK register (80 B at FP32, averaged over
+    the stages), plus, for delayed halos, C ring levels (AT; one level for
+    AS) of 5 values per halo point, plus the ring write of the boundary
+    layers once per step."""
+    f = halo_fraction(w)
     scale = esz / 4.0
     if w["mode"] == "sa":
         return 80.0 * scale, f
     levels = C_LEVELS if w["mode"] == "at" else 1
     return (80.0 + 20.0 * levels * f + 20.0 * f / stages) * scale, f
+
+
+def stage_kernel_bytes_per_point(w, stages, esz):
+    """Bytes the fused stage kernel itself must move per owned point and
+    launch: the 80 B of state and RK register, one assembled halo value of
+    5 variables per halo point (the sum over the C delayed levels is done
+    once per step by the halo kernel), and the ring write of the last stage
+    averaged over the stages."""
+    f = halo_fraction(w)
+    scale = esz / 4.0
+    if w["mode"] == "sa":
+        return 80.0 * scale
+    return (80.0 + 20.0 * f + 20.0 * f / stages) * scale
 
 
 def make_solver(w, precision, mode=None):
@@ -322,8 +341,10 @@ def main():
     ms, launches, kms, finite, tiles = gpu_run(torch, w, atns.F32, None, a.steps, warmup, U0, dt)
     value = npts * stages * a.steps / (ms * 1e-3)
     bpp, f = algorithmic_bytes_per_point_stage(w, stages, 4)
+    kbpp = stage_kernel_bytes_per_point(w, stages, 4)
     avg_launch_ms = kms / max(1, launches)
-    achieved = bpp * npts / (avg_launch_ms * 1e-3) / 1e9
+    achieved = kbpp * npts / (avg_launch_ms * 1e-3) / 1e9
+    step_achieved = bpp * npts * stages * a.steps / (ms * 1e-3) / 1e9
     out = {
         "metric": "grid-point-stage updates/s (FP32 AT vs FP64 SA)",
         "value": value,
@@ -345,8 +366,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(a.workload),
                      "kernel": "%s_stage_kernel" % ("ns" if w["physics"] == "ns" else "euler"),
-                     "bytes_per_point_stage": bpp, "halo_points_per_point": f,
-                     "avg_launch_ms": avg_launch_ms, "launches": launches},
+                     "bytes_per_point_launch": kbpp, "halo_points_per_point": f,
+                     "avg_launch_ms": avg_launch_ms, "launches": launches,
+                     "step": {"bytes_per_point_stage": bpp, "achieved": step_achieved,
+                              "frac": step_achieved / HBM_PEAK_GBS,
+                              "basis": "whole-step algorithmic bytes (C delayed levels per halo point and "
+                                       "stage) over the graph-launch time per step"}},
         "finite": finite,
     }
     probe = hbm_probe(torch)
@@ -355,7 +380,7 @@ def main():
     out["kernel_hash"] = kernel_source_hash()
     if not a.no_fp64:
         ms64, l64, k64, fin64, _ = gpu_run(torch, w, atns.F64, "sa", a.steps, warmup, U0, dt)
-        b64, _ = algorithmic_bytes_per_point_stage(dict(w, mode="sa"), stages, 8)
+        b64 = stage_kernel_bytes_per_point(dict(w, mode="sa"), stages, 8)
         out["fp64_sa"] = {"value": npts * stages * a.steps / (ms64 * 1e-3),
                           "ms_per_step": ms64 / a.steps,
                           "avg_launch_ms": k64 / max(1, l64),

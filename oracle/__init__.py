@@ -23,4 +23,25 @@ arXiv 2506.03027 (Arumugam, Goswami, Vadlamani, Aditya):
 * ``mlp``     -- FP64 reference of the learned-halo MLP (forward, backward).
 
 Everything is float64 numpy or exact ``fractions.Fraction`` arithmetic.
+
+What pins it (tests/test_oracle_*.py, all on the CPU):
+
+* coefficients -- Table 4 and Table 5 values, Eqs. 14-15 (with the AT4
+  k^2 coefficient read as 26), RK4/LSERK order conditions, observed temporal
+  order on an ODE, exactness of the extrapolation for polynomials, the
+  literal buffer recursion equal to the closed form;
+* flow -- the CD4 modified wavenumber, fourth-order convergence, closed-form
+  viscous solutions (shear wave, heat conduction, compression wave),
+  rotation covariance, the translating vortex, TGV initial kinetic energy and
+  enstrophy in closed form;
+* solver -- decomposed SA equal to one block bit for bit, Table 1 orders for
+  SA/AT/AS, AT with zero delay converging to SA, conservation under SA,
+  a brute-force pointwise halo rule, the delay patterns of Alg. 2 and
+  Alg. 3 and SplitMix64's published outputs;
+* mlp -- central-difference gradients, BF16 rounding, the fallback rule.
+
+Parity unpinned: the TGV kinetic-energy and enstrophy time series beyond
+t = 0 (the paper shows them only as plots, without data), and the
+flux-level form of the stage-0 extrapolation (the solver extrapolates the
+conserved variables and computes fluxes from them; see ``solver``).
 """

@@ -1,0 +1,60 @@
+"""Observed order of accuracy under grid refinement on the GPU (Table 1 and
+Sec. 5.1: the AT stencils keep the order of the synchronous scheme under
+delays; standard stencils reading delayed values drop to first order).
+
+The 3-D isentropic vortex on [0,10]^3 in 4x4x4 blocks, SAA delays with L = 4,
+classical RK4 and CD4, at 64^3, 128^3 and 256^3 with dt proportional to the
+grid spacing, to a fixed final time.  The order comes from self-convergence,
+e_N = |U_N - U_2N| / |U_2N| over the points the two grids share, all five
+conserved variables: the exact infinite-plane vortex is not a solution on the
+periodic box (the velocity tail reaching the box edge floors the error
+against it near 1e-7 at 256^3), while every grid here solves the same
+periodic problem.  FP64 state, so that rounding stays far below the
+truncation error."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import announce, need_gpu
+from paper_2506_03027_amd import atns, inputs
+
+pytestmark = pytest.mark.gpu
+
+BOX = (10.0, 10.0, 10.0)
+GRIDS = (64, 128, 256)
+T_END = 0.25
+CFL = 0.015        # stable for SAA with L = 4 on every grid
+
+
+def final_state(mode, N, dt, steps):
+    """Final FP64 state of one run, copied to the host."""
+    n = (N, N, N)
+    g = atns.Solver(n=n, length=BOX, ndim=3, nblk=(4, 4, 4), mode=mode, algo=atns.SAA, L=4, seed=3,
+                    precision=atns.F64)
+    g.set_dt(dt)
+    g.init_case(atns.CASE_VORTEX)
+    g.step(steps)
+    U = g.get_state()
+    g.close()
+    return U.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("mode, lo, hi", [(atns.SA, 3.5, 4.6), (atns.AT, 3.3, 4.8), (atns.AS, 0.6, 1.6)])
+def test_refinement_order(mode, lo, hi):
+    need_gpu()
+    U = inputs.vortex_state((GRIDS[0],) * 3, BOX, 3)
+    dt0 = inputs.cfl_dt(U, (GRIDS[0],) * 3, BOX, 3, 1.4, CFL)
+    steps0 = int(math.ceil(T_END / dt0))
+    dt0 = T_END / steps0
+    errs, prev = [], None
+    for i, N in enumerate(GRIDS):
+        announce("order", mode, N)
+        U = final_state(mode, N, dt0 / 2 ** i, steps0 * 2 ** i)
+        if prev is not None:
+            fine = U[:, ::2, ::2, ::2]
+            errs.append(float(np.linalg.norm(prev - fine) / np.linalg.norm(fine)))
+        prev = U
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    print("mode", mode, "errors", errs, "orders", orders)
+    assert lo < orders[-1] < hi, (errs, orders)

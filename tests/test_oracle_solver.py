@@ -195,6 +195,14 @@ def test_guard_resets_large_and_unavailable_delays():
     assert k.tolist() == [[0, 0, 0, 0, 0, 2]]
 
 
+def test_splitmix64_matches_published_outputs():
+    """The SAA delay draw is SplitMix64's i-th output for the seed; pinned to
+    the generator's published outputs from state 0."""
+    from conftest import read_golden
+    for i, hx in read_golden("splitmix64_state0.txt"):
+        assert dl.splitmix64_draw(0, int(i)) == int(hx, 16)
+
+
 def test_splitmix64_is_deterministic_and_seed_dependent():
     a = [dl.splitmix64_draw(1, i) for i in range(4)]
     assert a == [dl.splitmix64_draw(1, i) for i in range(4)]
