@@ -91,42 +91,120 @@ __device__ __forceinline__ void fetch(const StageParams<T>& p, const BlockDev* _
   for (int v = 0; v < 5; ++v) u[v] = r[v * vs];
 }
 
-// Write the values of owned point (lx, ly, lz) into every boundary layer of
-// block B that contains it, in ring slot `slot`.
+// Where the values of a column (fixed block-local lx, ly) come from for the
+// planes 0 <= lz < s_z of its block: an affine address, plane lz at
+// base + lz * zs and variable v at + v * vs.  Columns inside the block in x
+// and y, and every column under synchronous halos, read the stage field; the
+// others read the stage's halo region of their (x, y) slot.  Planes outside
+// the block in z go through fetch()'s general rule.  Equal to fetch() value
+// for value; it only hoists the column's address arithmetic out of the
+// plane loop.
 template <typename T>
-__device__ __forceinline__ void ring_store(const StageParams<T>& p, const BlockDev* __restrict__ B,
-                                           int lx, int ly, int lz, const T u[5], T* slot) {
-  const int l[3] = {lx, ly, lz};
+struct ColumnSource {
+  const T* base;
+  long long vs;
+  long long zs;
+};
+
+template <typename T>
+__device__ __forceinline__ ColumnSource<T> column_source(const StageParams<T>& p, const BlockDev* __restrict__ B,
+                                                        int lx, int ly) {
+  ColumnSource<T> c;
+  const int sx = (lx < 0) ? -1 : (lx >= B->s[0] ? 1 : 0);
+  const int sy = (ly < 0) ? -1 : (ly >= B->s[1] ? 1 : 0);
+  if (((sx | sy) == 0) || p.halo == kHaloSync) {
+    const int gx = wrap(B->o[0] + lx, p.n[0]);
+    const int gy = wrap(B->o[1] + ly, p.n[1]);
+    const long long gplane = (long long)p.n[0] * p.n[1];
+    c.base = p.Y + (long long)B->o[2] * gplane + (long long)gy * p.n[0] + gx;
+    c.vs = p.field;
+    c.zs = gplane;
+  } else {
+    const int s = slot_index(sx, sy, 0);
+    const int dep = (sx != 0 && sy != 0) ? 2 : p.H;
+    const int ix = sx < 0 ? lx + dep : (sx > 0 ? lx - B->s[0] : lx);
+    const int iy = sy < 0 ? ly + dep : (sy > 0 ? ly - B->s[1] : ly);
+    const int ex = sx ? dep : B->s[0];
+    const int ey = sy ? dep : B->s[1];
+    c.base = p.hbuf + B->hoff[s] + (long long)iy * ex + ix;
+    c.zs = (long long)ex * ey;
+    c.vs = c.zs * B->s[2];
+  }
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ void fetch_col(const StageParams<T>& p, const BlockDev* __restrict__ B,
+                                          const ColumnSource<T>& c, int blk, int lx, int ly, int lz, T u[5]) {
+  if (lz >= 0 && lz < B->s[2]) {
+    const T* r = c.base + lz * c.zs;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = r[v * c.vs];
+  } else {
+    fetch(p, B, blk, lx, ly, lz, u);
+  }
+}
+
+// Ring slots of block B whose boundary layer contains the column (lx, ly):
+// the x and y conditions only, the z condition is checked per plane.
+template <typename T>
+__device__ __forceinline__ unsigned ring_mask(const StageParams<T>& p, const BlockDev* __restrict__ B, int lx,
+                                              int ly) {
+  unsigned m = 0;
   const int ns = (p.H == 4) ? kNumSlots : 6;
   for (int s = 0; s < ns; ++s) {
-    const long long off = B->lay[s];
-    if (off < 0) continue;
+    if (B->lay[s] < 0) continue;
     int d[3];
     slot_dir(s, d);
     const int dep = (s < 6) ? p.H : 2;
-    int idx[3], ext[3];
     bool in = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (d[a] == 0) {
-        idx[a] = l[a];
-        ext[a] = B->s[a];
-      } else if (d[a] > 0) {
-        idx[a] = l[a] - (B->s[a] - dep);
-        ext[a] = dep;
-        in = in && idx[a] >= 0;
-      } else {
-        idx[a] = l[a];
-        ext[a] = dep;
-        in = in && l[a] < dep;
-      }
-    }
-    if (!in) continue;
-    const long long li = ((long long)idx[2] * ext[1] + idx[1]) * ext[0] + idx[0];
-    const long long vs = (long long)ext[0] * ext[1] * ext[2];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) slot[off + li + v * vs] = u[v];
+    if (d[0] > 0) in = in && lx >= B->s[0] - dep;
+    if (d[0] < 0) in = in && lx < dep;
+    if (d[1] > 0) in = in && ly >= B->s[1] - dep;
+    if (d[1] < 0) in = in && ly < dep;
+    if (in) m |= 1u << s;
   }
+  return m;
+}
+
+// Write the values of owned point (lx, ly, lz) into every boundary layer of
+// block B that contains it, in ring slot `slot`; `mask` is ring_mask() of
+// the point's column.
+template <typename T>
+__device__ __forceinline__ void ring_store(const StageParams<T>& p, const BlockDev* __restrict__ B, unsigned mask,
+                                           int lx, int ly, int lz, const T u[5], T* slot) {
+  while (mask) {
+    const int s = __builtin_ctz(mask);
+    mask &= mask - 1;
+    int d[3];
+    slot_dir(s, d);
+    const int dep = (s < 6) ? p.H : 2;
+    if (d[2] > 0 && lz < B->s[2] - dep) continue;
+    if (d[2] < 0 && lz >= dep) continue;
+    const int ix = d[0] > 0 ? lx - (B->s[0] - dep) : lx;
+    const int iy = d[1] > 0 ? ly - (B->s[1] - dep) : ly;
+    const int iz = d[2] > 0 ? lz - (B->s[2] - dep) : lz;
+    const int ex = d[0] ? dep : B->s[0];
+    const int ey = d[1] ? dep : B->s[1];
+    const int ez = d[2] ? dep : B->s[2];
+    const long long li = ((long long)iz * ey + iy) * ex + ix;
+    const long long vs = (long long)ex * ey * ez;
+    T* w = slot + B->lay[s] + li;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[v * vs] = u[v];
+  }
+}
+
+// 1 / a: IEEE division in FP64; in FP32 the hardware reciprocal estimate
+// refined by one Newton-Raphson step, r' = r + r (1 - a r).
+template <typename T>
+__device__ __forceinline__ T recip(T a) {
+  return T(1) / a;
+}
+template <>
+__device__ __forceinline__ float recip<float>(float a) {
+  const float r = __builtin_amdgcn_rcpf(a);
+  return fmaf(r, fmaf(-a, r, 1.0f), r);
 }
 
 // Operands the RK epilogue reads at a point besides the stage input: the

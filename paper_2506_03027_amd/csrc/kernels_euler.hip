@@ -92,7 +92,11 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
   if (arole) fetch(p, B, t.blk, t.x0 + ax, t.y0 + ay, t.z0, na);
 
   T* ring_slot = nullptr;
-  if (p.ring_write) ring_slot = p.ring + (long long)((p.slot_now + 1) % p.D) * p.slot_stride;
+  unsigned rmask = 0;
+  if (p.ring_write) {
+    ring_slot = p.ring + (long long)((p.slot_now + 1) % p.D) * p.slot_stride;
+    if (act) rmask = ring_mask(p, B, lx, ly);
+  }
 
   // global index of the thread's column at plane z0, and the stride per plane
   const long long g0 = ((long long)(B->o[2] + t.z0) * p.n[1] + (B->o[1] + ly)) * p.n[0] + (B->o[0] + lx);
@@ -163,7 +167,7 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
       T out[5];
       epilogue_pre<T, KIND>(p, g, q[2], R, accv, u0v, out);
       if (iz + 1 < t.nz) epilogue_load<T, KIND>(p, g + gplane, accv, u0v);
-      if (ring_slot) ring_store(p, B, lx, ly, lz, out, ring_slot);
+      if (ring_slot) ring_store(p, B, rmask, lx, ly, lz, out, ring_slot);
     }
   }
 }

@@ -20,10 +20,13 @@
 //   3. threads at the tile and its 2-point cross apron compute the full
 //      gradient at plane m and their fluxes: the x-flux F - Fv_x/Re on the
 //      x-cross, the y-flux on the y-cross (both into LDS), the z-flux at the
-//      tile, which is scattered straight into a register accumulator of the
-//      five planes m-2..m+2;
-//   4. tile threads add the x and y divergences of plane m;
+//      tile, which joins a register queue of the last four planes' z-fluxes
+//      and completes the z-divergence of plane m-2;
+//   4. tile threads form the x and y divergence of plane m-1 from the
+//      previous plane's flux planes and hold it in registers;
 //   5. plane m-2 is complete: its RK epilogue and ring write run.
+// Each thread resolves the address of its column once (column_source); the
+// ring write visits only the slots whose layer contains the column.
 #include "kernels_common.hpp"
 
 namespace atns {
@@ -52,6 +55,7 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
                      (dx >= 1 && dx <= 2 && dy >= 1 && dy <= 2);
   const bool grad_pt = core || crossx || crossy;
   const int lx = t.x0 + x, ly = t.y0 + y;
+  const ColumnSource<T> col = column_source(p, B, lx, ly);
 
   const T gm1 = (T)(p.gamma - 1.0);
   const T gM2 = (T)p.mach2_gamma;
@@ -63,7 +67,6 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
   __shared__ T sP[2][4][EY][EX];        // u, v, w, T of plane m (double-buffered)
   __shared__ T sFX[2][5][TY][TX + 4];   // F - Fv_x/Re on the x-cross of plane m
   __shared__ T sFY[2][5][TY + 4][TX];   // G - Fv_y/Re on the y-cross of plane m
-  __shared__ T sAcc[5][5][TY][TX];      // RHS accumulators, plane q at q mod 5
 
   // queues: q*[j] holds plane f-4+j; r*[j] holds plane f-2+j
   T qu[5], qv[5], qw[5], qT[5];
@@ -72,15 +75,22 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
   for (int j = 0; j < 5; ++j) qu[j] = qv[j] = qw[j] = qT[j] = T(0);
 #pragma unroll
   for (int j = 0; j < 3; ++j) rr[j] = rp[j] = re[j] = T(0);
-  if (core) {
+  // z-fluxes of the last four gradient planes (core), and the x/y divergence
+  // of the plane that finishes next
+  T hq[4][5], xyd[5];
 #pragma unroll
-    for (int j = 0; j < 5; ++j)
+  for (int v = 0; v < 5; ++v) {
+    xyd[v] = T(0);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sAcc[j][v][y][x] = T(0);
+    for (int j = 0; j < 4; ++j) hq[j][v] = T(0);
   }
 
   T* ring_slot = nullptr;
-  if (p.ring_write) ring_slot = p.ring + (long long)((p.slot_now + 1) % p.D) * p.slot_stride;
+  unsigned rmask = 0;
+  if (p.ring_write) {
+    ring_slot = p.ring + (long long)((p.slot_now + 1) % p.D) * p.slot_stride;
+    if (core) rmask = ring_mask(p, B, lx, ly);
+  }
 
   const int z0 = t.z0, nz = t.nz;
   const int f_begin = three ? z0 - 4 : 0;
@@ -98,17 +108,16 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
     const bool far = (rel >= -4 && rel < -2) || (rel >= nz + 2 && rel < nz + 4);
     return core ? (tileplane || near || far) : ((crossx || crossy) ? (tileplane || near) : (outer && tileplane));
   };
-  auto slot5 = [](int q) { return ((q % 5) + 5) % 5; };
   T nxt[5] = {T(1), T(0), T(0), T(0), T(1)};
-  if (need_plane(f_begin)) fetch(p, B, t.blk, lx, ly, f_begin, nxt);
+  if (need_plane(f_begin)) fetch_col(p, B, col, t.blk, lx, ly, f_begin, nxt);
   // epilogue operands of the next plane to finish (the tile's first plane)
-  const long long g0 = core ? ((long long)(B->o[2] + z0) * p.n[1] + (B->o[1] + ly)) * p.n[0] + (B->o[0] + lx) : 0;
   const long long gplane = (long long)p.n[0] * p.n[1];
+  long long gi = core ? ((long long)(B->o[2] + z0) * p.n[1] + (B->o[1] + ly)) * p.n[0] + (B->o[0] + lx) : 0;
   T Yv[5], accv[5], u0v[5];
   if (core) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + g0];
-    epilogue_load<T, KIND>(p, g0, accv, u0v);
+    for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + gi];
+    epilogue_load<T, KIND>(p, gi, accv, u0v);
   }
 
   for (int f = f_begin; f < f_end; ++f) {
@@ -139,7 +148,7 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
     constexpr int ri = three ? 2 : 0;
     if (need) {
       // plane f was prefetched during the previous iteration
-      const T ir = T(1) / nxt[0];
+      const T ir = recip(nxt[0]);
       const T vx = nxt[1] * ir, vy = nxt[2] * ir, vz = nxt[3] * ir;
       const T pr = gm1 * (nxt[4] - T(0.5) * (nxt[1] * vx + nxt[2] * vy + nxt[3] * vz));
       qu[qi] = vx;
@@ -151,7 +160,7 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
       re[ri] = nxt[4];
     }
     // issue the loads of plane f + 1; they complete behind this plane's work
-    if (three && f + 1 < f_end && need_plane(f + 1)) fetch(p, B, t.blk, lx, ly, f + 1, nxt);
+    if (three && f + 1 < f_end && need_plane(f + 1)) fetch_col(p, B, col, t.blk, lx, ly, f + 1, nxt);
     if (m_grad) {
       const bool has_m = core || ((crossx || crossy) && (mrel >= -2 && mrel < nz + 2)) || (outer && m_tile);
       if (has_m) {
@@ -163,6 +172,7 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
     }
     lds_barrier();
     // ------------------------------------- B. gradients and fluxes of plane m
+    T zd[5] = {T(0), T(0), T(0), T(0), T(0)};   // z-divergence of plane m - 2
     if (m_grad && (core || (m_tile && grad_pt))) {
       const int sx = x + 4, sy = y + 4;
       T g[3][3], gT[3];   // g[i][j] = d u_i / d x_j
@@ -220,20 +230,16 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
       }
       if constexpr (three) {
         if (core) {
-          // z-divergence contributions of plane m to planes m-2 .. m+2
-          T zf[5];
-          flux(2, zf);
-          // only planes of the tile accumulate (the slots are recycled)
-          const bool t0 = mrel - 2 >= 0 && mrel - 2 < nz, t1 = mrel - 1 >= 0 && mrel - 1 < nz;
-          const bool t3 = mrel + 1 >= 0 && mrel + 1 < nz, t4 = mrel + 2 >= 0 && mrel + 2 < nz;
-          const int a0 = slot5(m - 2), a1 = slot5(m - 1), a3 = slot5(m + 1), a4 = slot5(m + 2);
+          // z-flux of plane m joins the queue of planes m-4 .. m-1; the CD4
+          // z-divergence of plane m-2 is then complete
+          T hz[5];
+          flux(2, hz);
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            const T z = zf[v] * ihz;
-            if (t0) sAcc[a0][v][y][x] += z;
-            if (t1) sAcc[a1][v][y][x] -= T(8) * z;
-            if (t3) sAcc[a3][v][y][x] += T(8) * z;
-            if (t4) sAcc[a4][v][y][x] -= z;
+            zd[v] = (T(8) * (hq[3][v] - hq[1][v]) - (hz[v] - hq[0][v])) * ihz;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) hq[j][v] = hq[j + 1][v];
+            hq[3][v] = hz[v];
           }
         }
       }
@@ -241,37 +247,35 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
     // ------------------------- C. x and y divergence of plane m - 1 (3D) / m (2D)
     const int dm = m - 1;
     const int dbuf = buf ^ 1;
+    T xyn[5] = {T(0), T(0), T(0), T(0), T(0)};
     if (core && (dm - z0) >= 0 && (dm - z0) < nz) {
-      const int a = slot5(dm);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const T ddx = (T(8) * (sFX[dbuf][v][y][x + 3] - sFX[dbuf][v][y][x + 1]) -
                        (sFX[dbuf][v][y][x + 4] - sFX[dbuf][v][y][x])) * ihx;
         const T ddy = (T(8) * (sFY[dbuf][v][y + 3][x] - sFY[dbuf][v][y + 1][x]) -
                        (sFY[dbuf][v][y + 4][x] - sFY[dbuf][v][y][x])) * ihy;
-        sAcc[a][v][y][x] -= ddx + ddy;
+        xyn[v] = ddx + ddy;
       }
     }
     // ------------------------------------------------- D. finish plane pz
     const int pz = three ? m - 2 : m - 1;
     if (core && pz >= z0 && pz < z0 + nz) {
-      const int a = slot5(pz);
       T R[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        R[v] = sAcc[a][v][y][x];
-        sAcc[a][v][y][x] = T(0);   // the slot is reused for plane pz + 5
-      }
-      const long long gi = g0 + (pz - z0) * gplane;
+      for (int v = 0; v < 5; ++v) R[v] = three ? -(xyd[v] + zd[v]) : -xyn[v];
       T out[5];
       epilogue_pre<T, KIND>(p, gi, Yv, R, accv, u0v, out);
       if (pz + 1 < z0 + nz) {
+        gi += gplane;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + gi + gplane];
-        epilogue_load<T, KIND>(p, gi + gplane, accv, u0v);
+        for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + gi];
+        epilogue_load<T, KIND>(p, gi, accv, u0v);
       }
-      if (ring_slot) ring_store(p, B, lx, ly, pz, out, ring_slot);
+      if (ring_slot) ring_store(p, B, rmask, lx, ly, pz, out, ring_slot);
     }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) xyd[v] = xyn[v];
   }
 }
 
