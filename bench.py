@@ -313,6 +313,121 @@ def batch_main(a, torch):
     print(json.dumps(out))
 
 
+def mlp_main(a, torch):
+    """Learned-halo run at the workload's size.  The network is trained on
+    FP64 synchronous Taylor-Green runs the solver generates at 256^3 in
+    16x16x8 blocks (same dt as the run), then the FP32 AT solver runs with
+    and without the correction from the same state; the FP64 synchronous
+    solver at the same size is the reference of both errors."""
+    w = inputs.WORKLOADS[a.workload]
+    stages = 4
+    n = w["n"]
+    npts = n[0] * n[1] * n[2]
+    coarse = tuple(min(64, x) for x in n)
+    dt = inputs.cfl_dt(inputs.tgv_state(coarse, mach=w.get("mach", 0.1)), n, w["length"], 3, 1.4, w["cfl"])
+    # 1. training on FP64 synchronous runs at 256^3
+    tw = dict(inputs.WORKLOADS["tgv_256"], mode="sa", L=w["L"])
+    tr = make_solver(tw, atns.F64)
+    tr.set_dt(dt)
+    tr.init_case(atns.CASE_TGV)
+    tr.step(C_LEVELS + w["L"] + 2)
+    tr.mlp_set_scales(np.ones(5), np.ones(5))
+    X, Y = tr.mlp_sample(8192, 1)
+    X, Y = X.double().cpu().numpy(), Y.double().cpu().numpy()
+    s = (np.sqrt((X[:, :60].reshape(-1, 4, 5, 3) ** 2).mean(axis=(0, 1, 3))) + 1e-30).astype(np.float32)
+    r = (np.sqrt((Y[:, :5] ** 2).mean(axis=0)) + 1e-30).astype(np.float32)
+    tr.mlp_set_scales(s, r)
+    rng = np.random.default_rng(0)
+    theta0 = np.concatenate([rng.standard_normal(64 * 64) * math.sqrt(2.0 / 64), np.zeros(64),
+                             rng.standard_normal(64 * 64) * math.sqrt(2.0 / 64), np.zeros(64),
+                             rng.standard_normal(16 * 64) * math.sqrt(2.0 / 64), np.zeros(16)])
+    tr.mlp_set_params((0.5 * theta0).astype(np.float32))
+    losses = []
+    t0 = time.perf_counter()
+    for rnd in range(6):
+        tr.step(2)
+        losses.extend(tr.mlp_train(100, 1024, 1e-3, 100 + rnd).tolist())
+    train_s = time.perf_counter() - t0
+    theta = tr.mlp_get_params()
+    Xv, Yv = tr.mlp_sample(4096, 999)
+    out = tr.mlp_forward(Xv)[:, :5].double().cpu().numpy()
+    Yn = Yv[:, :5].double().cpu().numpy()
+    mse_mlp, mse_at = float(((out - Yn) ** 2).mean()), float((Yn ** 2).mean())
+    tr.close()
+    tau = 10.0
+    total = C_LEVELS + 1 + a.warmup + a.steps
+
+    # 2. FP32 AT without and with the correction, same start and delays
+    def run(use_mlp):
+        g = make_solver(w, atns.F32)
+        g.set_dt(dt)
+        g.init_case(atns.CASE_TGV)
+        if use_mlp:
+            g.mlp_set_params(theta)
+            g.mlp_set_scales(s, r)
+            g.mlp_enable(True, tau)
+        tiles = g.autotune(reps=2, cache=TUNE_CACHE)
+        g.step(C_LEVELS + 1 + a.warmup)
+        g.mlp_stats() if use_mlp else None
+        ms = time_steps(torch, g, a.steps)
+        stats = g.mlp_stats() if use_mlp else (0, 0)
+        U = g.get_state().double()
+        g.close()
+        return ms, stats, U, tiles
+
+    ms_at, _, U_at, tiles = run(False)
+    ms_mlp, stats, U_mlp, _ = run(True)
+    # 3. FP64 synchronous reference at the same size and step count
+    ref = make_solver(dict(w, mode="sa", L=1), atns.F64)
+    ref.set_dt(dt)
+    ref.init_case(atns.CASE_TGV)
+    ref.step(total)
+    U_ref = ref.get_state()
+    ref.close()
+    nrm = float(torch.linalg.vector_norm(U_ref))
+
+    def rel(U):
+        return float(torch.linalg.vector_norm(U - U_ref)) / nrm
+
+    l2_at, l2_mlp = rel(U_at), rel(U_mlp)
+    l2_pair = float(torch.linalg.vector_norm(U_mlp - U_at)) / nrm
+    del U_at, U_mlp, U_ref
+    face_pts = (stats[0] + stats[1]) / a.steps
+    flops = face_pts * 2.0 * (64 * 64 + 64 * 64 + 16 * 64)
+    extra_ms = (ms_mlp - ms_at) / a.steps
+    tflops = flops / (extra_ms * 1e-3) / 1e12 if extra_ms > 0 else None
+    out = {
+        "metric": "grid-point-stage updates/s (FP32 AT+MLP vs FP64 SA)",
+        "value": npts * stages * a.steps / (ms_mlp * 1e-3),
+        "unit": "grid-point-stage/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": C_LEVELS + 1 + a.warmup,
+        "ms_per_step": ms_mlp / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "grid": list(n), "blocks": list(w["nblk"]), "physics": "ns",
+                   "scheme": "CD4 + AT halos + learned face-halo correction, RK4", "algo": "SAA",
+                   "L": w["L"], "cfl": w["cfl"], "tiles": list(tiles), "tau": tau},
+        "without_mlp": {"value": npts * stages * a.steps / (ms_at * 1e-3), "ms_per_step": ms_at / a.steps},
+        "mlp": {"face_points_per_step": face_pts, "applied": stats[0], "fallback": stats[1],
+                "flops_per_step": flops, "extra_ms_per_step": extra_ms, "achieved_tflops": tflops,
+                "mfma_frac_of_bf16_peak": (tflops / 2500.0) if tflops else None,
+                "training": {"grid": list(tw["n"]), "blocks": list(tw["nblk"]), "precision": "f64",
+                             "mode": "sa", "iters": len(losses), "batch": 1024, "seconds": train_s,
+                             "loss_first10": float(np.mean(losses[:10])),
+                             "loss_last50": float(np.mean(losses[-50:])),
+                             "halo_mse_at": mse_at, "halo_mse_mlp": mse_mlp}},
+        "rel_l2_vs_fp64_sa": {"at": l2_at, "at_mlp": l2_mlp, "at_mlp_minus_at": l2_pair,
+                              "steps": total, "reference": "FP64 synchronous GPU run, same grid and dt"},
+        "kernel_hash": kernel_source_hash(),
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +436,8 @@ def main():
     ap.add_argument("--workload", default="vortex3d_128")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--mlp", action="store_true",
+                    help="learned-halo run (Taylor-Green workloads): train, then AT with and without it")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus 1 only)",
@@ -330,6 +447,9 @@ def main():
     torch.cuda.set_device(0)
     if a.workload == "batch48":
         batch_main(a, torch)
+        return
+    if a.mlp:
+        mlp_main(a, torch)
         return
     w = inputs.WORKLOADS[a.workload]
     stages = 4 if w["rk"] == "rk4" else 5

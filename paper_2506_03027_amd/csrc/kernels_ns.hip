@@ -20,8 +20,8 @@
 //   3. threads at the tile and its 2-point cross apron compute the full
 //      gradient at plane m and their fluxes: the x-flux F - Fv_x/Re on the
 //      x-cross, the y-flux on the y-cross (both into LDS), the z-flux at the
-//      tile, which joins a register queue of the last four planes' z-fluxes
-//      and completes the z-divergence of plane m-2;
+//      tile, which with the z-fluxes of the last four planes (kept in LDS,
+//      each thread its own cells) completes the z-divergence of plane m-2;
 //   4. tile threads form the x and y divergence of plane m-1 from the
 //      previous plane's flux planes and hold it in registers;
 //   5. plane m-2 is complete: its RK epilogue and ring write run.
@@ -43,8 +43,52 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
   stage_block(p.blocks + t.blk, &sB);
   const BlockDev* __restrict__ B = &sB;
   const int tid = threadIdx.x;
-  const int x = tid % EX - 4, y = tid / EX - 4;   // tile-local, -4 .. T+3
+  // Thread -> footprint point, grouped so that whole waves share a role: the
+  // TX x TY tile first, then the 2-point cross apron, then the outer apron
+  // (3-4 points out along x or y, and the 2 x 2 xy corners).  Phases that
+  // only tile points (or tile and cross points) take part in then run on
+  // full waves.  Threads beyond the footprint sit at a point no role needs.
+  int x, y;
+  {
+    int r = tid;
+    if (r < TX * TY) {
+      x = r % TX;
+      y = r / TX;
+    } else if ((r -= TX * TY) < 4 * TY) {   // x-cross: 2 columns each side
+      const int side = r / (2 * TY), q = r % (2 * TY);
+      y = q >> 1;
+      x = side ? TX + (q & 1) : -1 - (q & 1);
+    } else if ((r -= 4 * TY) < 4 * TX) {    // y-cross: 2 rows each side
+      const int side = r / (2 * TX), q = r % (2 * TX);
+      x = q % TX;
+      y = side ? TY + q / TX : -1 - q / TX;
+    } else if ((r -= 4 * TX) < 4 * TY) {    // x-outer: columns 3-4 out
+      const int side = r / (2 * TY), q = r % (2 * TY);
+      y = q >> 1;
+      x = side ? TX + 2 + (q & 1) : -3 - (q & 1);
+    } else if ((r -= 4 * TY) < 4 * TX) {    // y-outer: rows 3-4 out
+      const int side = r / (2 * TX), q = r % (2 * TX);
+      x = q % TX;
+      y = side ? TY + 2 + q / TX : -3 - q / TX;
+    } else if ((r -= 4 * TX) < 16) {        // 2 x 2 corners
+      const int c = r >> 2, q = r & 3;
+      x = (c & 1) ? TX + (q & 1) : -1 - (q & 1);
+      y = (c & 2) ? TY + (q >> 1) : -1 - (q >> 1);
+    } else {
+      x = -4;
+      y = -4;
+    }
+  }
   const int nx = t.nx, ny = t.ny;
+  // A ragged tile (nx < TX or ny < TY): the far-side apron moves in to the
+  // tile's real edge, and tile or apron threads beyond that edge go idle at
+  // (-4, -4), a point no role needs.
+  {
+    const bool idle = (x >= nx && x < TX) || (y >= ny && y < TY);
+    if (x >= TX) x -= TX - nx;
+    if (y >= TY) y -= TY - ny;
+    if (idle) x = y = -4;
+  }
   const int dx = x < 0 ? -x : (x >= nx ? x - nx + 1 : 0);   // distance outside, 1-based
   const int dy = y < 0 ? -y : (y >= ny ? y - ny + 1 : 0);
   const bool inx = dx == 0, iny = dy == 0;
@@ -67,23 +111,23 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
   __shared__ T sP[2][4][EY][EX];        // u, v, w, T of plane m (double-buffered)
   __shared__ T sFX[2][5][TY][TX + 4];   // F - Fv_x/Re on the x-cross of plane m
   __shared__ T sFY[2][5][TY + 4][TX];   // G - Fv_y/Re on the y-cross of plane m
+  // z-fluxes of the last four gradient planes at the tile, plane q in slot
+  // q mod 4; each thread reads only its own cells (no barrier needed)
+  __shared__ T sH[4][5][TY][TX];
 
-  // queues: q*[j] holds plane f-4+j; r*[j] holds plane f-2+j
+  // queues: q*[j] holds plane f-4+j; rr[j] holds the density of plane f-2+j
+  // (pressure and energy at the gradient plane are rebuilt from rho, T and u)
   T qu[5], qv[5], qw[5], qT[5];
-  T rr[3], rp[3], re[3];
+  T rr[3];
 #pragma unroll
   for (int j = 0; j < 5; ++j) qu[j] = qv[j] = qw[j] = qT[j] = T(0);
 #pragma unroll
-  for (int j = 0; j < 3; ++j) rr[j] = rp[j] = re[j] = T(0);
-  // z-fluxes of the last four gradient planes (core), and the x/y divergence
-  // of the plane that finishes next
-  T hq[4][5], xyd[5];
+  for (int j = 0; j < 3; ++j) rr[j] = T(1);
+  // x/y divergence of the plane that finishes next
+  T xyd[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    xyd[v] = T(0);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) hq[j][v] = T(0);
-  }
+  for (int v = 0; v < 5; ++v) xyd[v] = T(0);
+  const T igM2 = (T)(1.0 / p.mach2_gamma), igm1 = (T)(1.0 / (p.gamma - 1.0));
 
   T* ring_slot = nullptr;
   unsigned rmask = 0;
@@ -113,10 +157,15 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
   // epilogue operands of the next plane to finish (the tile's first plane)
   const long long gplane = (long long)p.n[0] * p.n[1];
   long long gi = core ? ((long long)(B->o[2] + z0) * p.n[1] + (B->o[1] + ly)) * p.n[0] + (B->o[0] + lx) : 0;
-  T Yv[5], accv[5], u0v[5];
+  // the stage input at the point enters only the first RK4 stage and the
+  // low-storage updates
+  constexpr bool needY = KIND == kRK4First || KIND == kLSFirst || KIND == kLSMid || KIND == kRhsOnly;
+  T Yv[5] = {T(0), T(0), T(0), T(0), T(0)}, accv[5], u0v[5];
   if (core) {
+    if (needY) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + gi];
+      for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + gi];
+    }
     epilogue_load<T, KIND>(p, gi, accv, u0v);
   }
 
@@ -138,11 +187,7 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
         qT[j] = qT[j + 1];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        rr[j] = rr[j + 1];
-        rp[j] = rp[j + 1];
-        re[j] = re[j + 1];
-      }
+      for (int j = 0; j < 2; ++j) rr[j] = rr[j + 1];
     }
     constexpr int qi = three ? 4 : 2;   // queue slot of the fetched plane
     constexpr int ri = three ? 2 : 0;
@@ -156,8 +201,6 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
       qw[qi] = vz;
       qT[qi] = gM2 * pr * ir;
       rr[ri] = nxt[0];
-      rp[ri] = pr;
-      re[ri] = nxt[4];
     }
     // issue the loads of plane f + 1; they complete behind this plane's work
     if (three && f + 1 < f_end && need_plane(f + 1)) fetch_col(p, B, col, t.blk, lx, ly, f + 1, nxt);
@@ -201,7 +244,9 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
       }
       const T div = g[0][0] + g[1][1] + g[2][2];
       const T vel[3] = {qu[2], qv[2], qw[2]};
-      const T rho = rr[0], pres = rp[0], et = re[0];
+      const T rho = rr[0];
+      const T pres = rho * qT[2] * igM2;
+      const T et = pres * igm1 + T(0.5) * rho * (vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2]);
       // flux along direction d: inviscid minus viscous / Re
       auto flux = [&](int d, T out[5]) {
         T tau[3];
@@ -230,16 +275,16 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
       }
       if constexpr (three) {
         if (core) {
-          // z-flux of plane m joins the queue of planes m-4 .. m-1; the CD4
-          // z-divergence of plane m-2 is then complete
+          // the z-flux of plane m completes the CD4 z-divergence of plane
+          // m-2 with those of planes m-4, m-3, m-1, then takes plane m-4's slot
           T hz[5];
           flux(2, hz);
+          const int s0 = m & 3, s1 = (m - 3) & 3, s3 = (m - 1) & 3;
+          const bool zt = mrel - 2 >= 0 && mrel - 2 < nz;
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            zd[v] = (T(8) * (hq[3][v] - hq[1][v]) - (hz[v] - hq[0][v])) * ihz;
-#pragma unroll
-            for (int j = 0; j < 3; ++j) hq[j][v] = hq[j + 1][v];
-            hq[3][v] = hz[v];
+            if (zt) zd[v] = (T(8) * (sH[s3][v][y][x] - sH[s1][v][y][x]) - (hz[v] - sH[s0][v][y][x])) * ihz;
+            sH[s0][v][y][x] = hz[v];
           }
         }
       }
@@ -268,8 +313,10 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
       epilogue_pre<T, KIND>(p, gi, Yv, R, accv, u0v, out);
       if (pz + 1 < z0 + nz) {
         gi += gplane;
+        if (needY) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + gi];
+          for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + gi];
+        }
         epilogue_load<T, KIND>(p, gi, accv, u0v);
       }
       if (ring_slot) ring_store(p, B, rmask, lx, ly, pz, out, ring_slot);
@@ -280,7 +327,8 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
 }
 
 template <typename T, int TX, int TY, int KIND, int NDIM>
-__global__ void __launch_bounds__((TX + 8) * (TY + 8)) ns_stage_kernel(const StageParams<T> p) {
+// Five waves per SIMD: two 16x16 (or three 16x8) workgroups per CU.
+__global__ void __launch_bounds__((TX + 8) * (TY + 8)) __attribute__((amdgpu_waves_per_eu(5, 8))) ns_stage_kernel(const StageParams<T> p) {
   const StageParams<T> q = resolve_step(p);
   ns_tile<T, TX, TY, KIND, NDIM>(q, p.tiles[blockIdx.x]);
 }

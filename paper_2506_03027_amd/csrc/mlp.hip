@@ -19,6 +19,8 @@
 #include "kernels_common.hpp"
 #include "mlp.hpp"
 
+#include <algorithm>
+
 namespace atns {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
@@ -177,9 +179,46 @@ __device__ __forceinline__ void face_features(const MlpFeatArgs<T>& a, const Hal
 }
 
 // ------------------------------------------------------------ halo inference
-// One wave per chunk of 16 face-halo points: features from the ring (each
-// point's own delay), forward pass, fallback test, and delta added to every
-// stage halo value of the point.
+// Features of level l (15 values: 5 variables x normal offsets j-1, j, j+1,
+// relative to level 0 at the point) of the face-halo point `pt`, written as
+// BF16 at x[l*15 ..]; the same values as face_features().
+template <typename T>
+__device__ __forceinline__ void level_features(const MlpFeatArgs<T>& a, const HaloRegion& rg, const FaceInfo& fi,
+                                               int pt, int k, int l, unsigned short* x) {
+  // no arrays indexed by the (run-time) normal axis: they would live in scratch
+  const int e0 = fi.ext[0], e1 = fi.ext[1], e2 = fi.ext[2];
+  const int cx = pt % e0, cy = (pt / e0) % e1, cz = pt / (e0 * e1);
+  const int ax = fi.axis;
+  int idx[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int nx = ax == 0 ? min(max(cx + j - 1, 0), e0 - 1) : cx;
+    const int ny = ax == 1 ? min(max(cy + j - 1, 0), e1 - 1) : cy;
+    const int nz = ax == 2 ? min(max(cz + j - 1, 0), e2 - 1) : cz;
+    idx[j] = (nz * e1 + ny) * e0 + nx;
+  }
+  const int snow = a.nstep ? (int)(*a.nstep % a.D) : a.slot_now;
+  int sl0 = snow - k;
+  sl0 += (sl0 < 0) ? a.D : 0;
+  int sl = snow - k - l;
+  sl += (sl < 0) ? a.D : 0;
+  const T* base0 = a.ring + (long long)sl0 * a.slot_stride + rg.src;
+  const T* base = a.ring + (long long)sl * a.slot_stride + rg.src;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const float centre = (float)base0[(long long)v * rg.npts + idx[1]];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      x[l * 15 + v * 3 + j] = f2bf(((float)base[(long long)v * rg.npts + idx[j]] - centre) * a.inv_s[v]);
+  }
+}
+
+// Persistent workgroups (the network is staged in LDS once); each wave takes
+// chunks of 16 face-halo points: four lanes per point gather its features
+// (one delayed level each, the point's own delay), the wave runs the forward
+// pass on the matrix cores, and the lanes of accepted points add delta to
+// every stage halo value of the point.  Applied / fallback counts are summed
+// per wave and added once at the end.
 template <typename T>
 __global__ void __launch_bounds__(256) mlp_halo_kernel(MlpFeatArgs<T> a, MlpNet net, const HaloRegion* regions,
                                                         const FaceInfo* faces, const HaloWork* chunks,
@@ -191,38 +230,54 @@ __global__ void __launch_bounds__(256) mlp_halo_kernel(MlpFeatArgs<T> a, MlpNet 
   load_net(net, L);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long c = (long long)blockIdx.x * 4 + wave;
-  if (c >= nchunks) return;
   WaveScratch& W = S[wave];
-  const HaloWork ck = chunks[c];
-  const HaloRegion rg = regions[ck.region];
-  const int pt = ck.start + lane;
-  const bool valid = lane < kMlpChunk && pt < rg.npts;
-  if (lane < kMlpChunk) {
-    float feat[64];
-    if (valid) {
-      face_features(a, rg, faces[ck.region], pt, (int)delays[rg.kidx], feat);
-    } else {
-      for (int f = 0; f < 64; ++f) feat[f] = 0.f;
-    }
-    for (int f = 0; f < 64; ++f) W.x[lane * kMlpIn + f] = f2bf(feat[f]);
-  }
-  wave_sync();
-  wave_forward(L, W.fwd());
-  if (valid) {
-    float n2 = 0.f;
+  unsigned long long n_ok = 0, n_fb = 0;
+  for (long long c = (long long)blockIdx.x * 4 + wave; c < nchunks; c += (long long)gridDim.x * 4) {
+    const HaloWork ck = chunks[c];
+    const HaloRegion rg = regions[ck.region];
+    const FaceInfo fi = faces[ck.region];
+    const int k = (int)delays[rg.kidx];
+    {
+      const int p = lane & 15, l = lane >> 4;
+      const int pt = ck.start + p;
+      unsigned short* x = W.x + p * kMlpIn;
+      if (pt < rg.npts) {
+        level_features(a, rg, fi, pt, k, l, x);
+      } else {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) n2 += W.o[lane * kMlpOut + v] * W.o[lane * kMlpOut + v];
-    const bool ok = n2 <= a.tau2;
-    if (ok) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const double d = (double)a.r[v] * (double)W.o[lane * kMlpOut + v];
-        const long long o = rg.dst + (long long)v * rg.npts + pt;
-        for (int e = 0; e < stages; ++e) hbuf[e * halo_stride + o] = (T)((double)hbuf[e * halo_stride + o] + d);
+        for (int f = 0; f < 15; ++f) x[l * 15 + f] = 0;
+      }
+      if (l == 0) {
+        x[60] = f2bf(pt < rg.npts && a.L > 1 ? (float)k / (float)(a.L - 1) : 0.f);
+        x[61] = x[62] = x[63] = 0;
       }
     }
-    atomicAdd(&counters[ok ? 0 : 1], 1ull);
+    wave_sync();
+    wave_forward(L, W.fwd());
+    const int pt = ck.start + lane;
+    const bool valid = lane < kMlpChunk && pt < rg.npts;
+    bool ok = false;
+    if (valid) {
+      float n2 = 0.f;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) n2 += W.o[lane * kMlpOut + v] * W.o[lane * kMlpOut + v];
+      ok = n2 <= a.tau2;
+      if (ok) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const double d = (double)a.r[v] * (double)W.o[lane * kMlpOut + v];
+          const long long o = rg.dst + (long long)v * rg.npts + pt;
+          for (int e = 0; e < stages; ++e) hbuf[e * halo_stride + o] = (T)((double)hbuf[e * halo_stride + o] + d);
+        }
+      }
+    }
+    n_ok += __popcll(__ballot(valid && ok));
+    n_fb += __popcll(__ballot(valid && !ok));
+    wave_sync();   // the next chunk overwrites this wave's scratch
+  }
+  if (lane == 0) {
+    if (n_ok) atomicAdd(&counters[0], n_ok);
+    if (n_fb) atomicAdd(&counters[1], n_fb);
   }
 }
 
@@ -513,7 +568,11 @@ template <typename T>
 hipError_t mlp_halo(const MlpFeatArgs<T>& a, const MlpNet& net, const HaloRegion* regions, const FaceInfo* faces,
                     const HaloWork* chunks, long long nchunks, const int8_t* delays, T* hbuf, long long halo_stride,
                     int stages, unsigned long long* counters, hipStream_t s) {
-  const long long nblk = (nchunks + 3) / 4;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const long long nblk = std::min<long long>((nchunks + 3) / 4, (long long)cus * 4);
+  if (nblk < 1) return hipSuccess;
   mlp_halo_kernel<T><<<(unsigned)nblk, 256, 0, s>>>(a, net, regions, faces, chunks, nchunks, delays, hbuf,
                                                     halo_stride, stages, counters);
   return hipGetLastError();
