@@ -301,9 +301,11 @@ atns_status atns_host_delays(int32_t algo, int64_t n, int32_t nblocks, int32_t L
  * walks the combined tile list of all members of that physics; the Euler and
  * Navier-Stokes members form two independent branches of the graph.  Each
  * physics uses one tile shape for all its members (atns_batch_set_tiles, or
- * atns_batch_autotune, which times every shape on the batch itself --
- * advancing it by reps + 1 steps per shape -- and keeps the fastest; best
- * receives int[6] = Euler (tx, ty, tz), Navier-Stokes (tx, ty, tz)).
+ * atns_batch_autotune, which times every shape with each member's own stage
+ * kernel -- right-hand side only, reps launches, into a scratch register, so
+ * no state changes -- and applies, per physics, the shape with the least
+ * total time; best receives int[6] = Euler (tx, ty, tz), Navier-Stokes
+ * (tx, ty, tz)).
  * Member results are bit-identical to stepping each member alone.
  * Ownership: the batch owns its member contexts; never pass a member to
  * atns_destroy (atns_batch_destroy releases them).  Member calls that change
@@ -312,8 +314,8 @@ atns_status atns_host_delays(int32_t algo, int64_t n, int32_t nblocks, int32_t L
  * streams ordered after earlier work on the stream given at creation, and
  * later work on that stream is ordered after it.  Errors: ATNS_EINVAL for
  * bad arguments or members that are not 3-D classical RK4 of one precision,
- * ATNS_ESTATE if members are at different steps or lack state or dt (and,
- * for atns_batch_autotune, before the members are past step C), ATNS_EHIP
+ * ATNS_ESTATE if members are at different steps or lack state or dt
+ * (atns_batch_autotune: lack state), ATNS_EHIP
  * for HIP failures; atns_batch_last_error(NULL) explains a failed create. */
 typedef struct atns_batch atns_batch;
 atns_status atns_batch_create(const atns_config* cfgs, int32_t n, void* stream, atns_batch** out);

@@ -1682,8 +1682,12 @@ atns_status atns_batch_step(atns_batch* b, int32_t nsteps) {
 atns_status atns_batch_autotune(atns_batch* b, int32_t reps, int32_t* best) {
   if (!b || reps < 1) return bfail(b, ATNS_EINVAL, "bad arguments");
   for (atns_ctx* c : b->m)
-    if (c->step < kC || c->inject_n > 0 || c->profiling)
-      return bfail(b, ATNS_ESTATE, "autotune times graph steps: step the batch past its synchronous start first");
+    if (!c->state_set) return bfail(b, ATNS_ESTATE, "member state not set");
+  BHIP(b, hipDeviceSynchronize());
+  // Per physics: every shape is timed with each member's own stage kernel
+  // (right-hand side only, into a scratch register; states are untouched),
+  // and the shape with the least total time over the members is applied to
+  // the whole batch.
   for (int ph = 0; ph < 2; ++ph) {
     bool any = false;
     for (atns_ctx* c : b->m) any = any || ((c->cfg.physics == ATNS_NS) == (ph == 1));
@@ -1694,24 +1698,18 @@ atns_status atns_batch_autotune(atns_batch* b, int32_t reps, int32_t* best) {
       for (int tz : {4, 8, 16, 32}) {
         if (ph == 1 && tz < 8) continue;
         const int tx = kShapes[i][0], ty = kShapes[i][1];
-        atns_status st = atns_batch_set_tiles(b, ph ? ATNS_NS : ATNS_EULER, tx, ty, tz);
-        if (st != ATNS_OK) return st;
-        st = atns_batch_step(b, 1);   // capture (and a warm step)
-        if (st != ATNS_OK) return st;
-        hipEvent_t e0, e1;
-        BHIP(b, hipEventCreate(&e0));
-        BHIP(b, hipEventCreate(&e1));
-        BHIP(b, hipEventRecord(e0, b->s[0]));
-        st = atns_batch_step(b, reps);
-        if (st != ATNS_OK) return st;
-        BHIP(b, hipEventRecord(e1, b->s[0]));
-        BHIP(b, hipEventSynchronize(e1));
-        float ms = 0.f;
-        BHIP(b, hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (ms < best_ms) {
-          best_ms = ms;
+        float total = 0.f;
+        for (atns_ctx* c : b->m) {
+          if ((c->cfg.physics == ATNS_NS) != (ph == 1)) continue;
+          atns_status st = atns_set_tiles(c, tx, ty, tz);
+          if (st != ATNS_OK) return bfail(b, st, c->err);
+          float ms = 0.f;
+          st = c->esz == 4 ? time_shape<float>(c, reps, &ms) : time_shape<double>(c, reps, &ms);
+          if (st != ATNS_OK) return bfail(b, st, c->err);
+          total += ms;
+        }
+        if (total < best_ms) {
+          best_ms = total;
           pick[0] = tx;
           pick[1] = ty;
           pick[2] = tz;

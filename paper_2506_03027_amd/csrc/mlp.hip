@@ -64,6 +64,23 @@ __device__ __forceinline__ f32x4 wave_gemm(const unsigned short* A, int sam, int
   return acc;
 }
 
+// The same product when both operands are contiguous along k (A row-major
+// [16][lda], B given as rows of W, [16][ldb]): each lane's 8 consecutive k
+// values of A and B are one 16-byte LDS read.  Rows must be 16-byte aligned.
+template <int K>
+__device__ __forceinline__ f32x4 wave_gemm_k(const unsigned short* A, int lda, const unsigned short* Bt, int ldb,
+                                             f32x4 acc) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int kb = 0; kb < K / 32; ++kb) {
+    const bf16x8 av = *reinterpret_cast<const bf16x8*>(A + r * lda + kb * 32 + 8 * g);
+    const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Bt + r * ldb + kb * 32 + 8 * g);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
 // Layer y = x W^T + b for 16 samples of one wave: x [16][nin] BF16 in LDS
 // (row stride ldx), W [nout][nin] BF16 in LDS, b FP32.  Writes pre-activation
 // z (FP32, [16][nout], row stride ldz) to LDS.
@@ -75,15 +92,33 @@ __device__ __forceinline__ void wave_layer(const unsigned short* x, int ldx, con
 #pragma unroll
   for (int nt = 0; nt < NOUT / 16; ++nt) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    // B[k][n] = W[nt*16 + n][k]
-    acc = wave_gemm<NIN>(x, ldx, 1, W + nt * 16 * NIN, 1, NIN, acc);
+    // B[k][n] = W[nt*16 + n][k]: rows of W, contiguous along k
+    acc = wave_gemm_k<NIN>(x, ldx, W + nt * 16 * NIN, NIN, acc);
 #pragma unroll
     for (int i = 0; i < 4; ++i) z[(4 * g + i) * ldz + nt * 16 + r] = acc[i] + b[nt * 16 + r];
   }
 }
 
+// Inference form of a hidden layer: h = BF16(ReLU(x W^T + b)) written
+// straight from the accumulators (the FP32 pre-activations are kept only by
+// the training path, which needs them).  Same values as wave_layer followed
+// by the ReLU and the BF16 rounding.
+template <int NIN, int NOUT>
+__device__ __forceinline__ void wave_layer_relu(const unsigned short* x, int ldx, const unsigned short* W,
+                                                const float* b, unsigned short* h, int ldh) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int nt = 0; nt < NOUT / 16; ++nt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = wave_gemm_k<NIN>(x, ldx, W + nt * 16 * NIN, NIN, acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h[(4 * g + i) * ldh + nt * 16 + r] = f2bf(fmaxf(acc[i] + b[nt * 16 + r], 0.f));
+  }
+}
+
 // Shared-memory image of the network for one workgroup.
-struct MlpLds {
+struct alignas(16) MlpLds {
   unsigned short W1[kMlpH * kMlpIn];
   unsigned short W2[kMlpH * kMlpH];
   unsigned short W3[kMlpOut * kMlpH];
@@ -112,7 +147,7 @@ struct Fwd {
 };
 
 // Per-wave scratch of the inference kernels.
-struct WaveScratch {
+struct alignas(16) WaveScratch {
   unsigned short x[16 * kMlpIn];
   float z1[16 * kMlpH];
   unsigned short h1[16 * kMlpH];
@@ -121,6 +156,24 @@ struct WaveScratch {
   float o[16 * kMlpOut];
   __device__ Fwd fwd() { return Fwd{x, z1, h1, z2, h2, o}; }
 };
+
+// Per-wave scratch of the halo inference: the input, reused for the second
+// hidden layer once the first has read it, the first hidden layer and the
+// outputs (5 KB per wave).
+struct alignas(16) InferScratch {
+  unsigned short x[16 * kMlpIn];   // input, then h2
+  unsigned short h1[16 * kMlpH];
+  float o[16 * kMlpOut];
+};
+
+__device__ __forceinline__ void wave_forward_infer(const MlpLds& L, InferScratch& S) {
+  wave_layer_relu<kMlpIn, kMlpH>(S.x, kMlpIn, L.W1, L.b1, S.h1, kMlpH);
+  wave_sync();
+  wave_layer_relu<kMlpH, kMlpH>(S.h1, kMlpH, L.W2, L.b2, S.x, kMlpH);
+  wave_sync();
+  wave_layer<kMlpH, kMlpOut>(S.x, kMlpH, L.W3, L.b3, S.o, kMlpOut);
+  wave_sync();
+}
 
 // Forward pass of the wave's 16 samples (x already staged).
 __device__ __forceinline__ void wave_forward(const MlpLds& L, Fwd F) {
@@ -226,11 +279,11 @@ __global__ void __launch_bounds__(256) mlp_halo_kernel(MlpFeatArgs<T> a, MlpNet 
                                                         long long halo_stride, int stages,
                                                         unsigned long long* counters) {
   __shared__ MlpLds L;
-  __shared__ WaveScratch S[4];
+  __shared__ InferScratch S[4];
   load_net(net, L);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  WaveScratch& W = S[wave];
+  InferScratch& W = S[wave];
   unsigned long long n_ok = 0, n_fb = 0;
   for (long long c = (long long)blockIdx.x * 4 + wave; c < nchunks; c += (long long)gridDim.x * 4) {
     const HaloWork ck = chunks[c];
@@ -253,7 +306,7 @@ __global__ void __launch_bounds__(256) mlp_halo_kernel(MlpFeatArgs<T> a, MlpNet 
       }
     }
     wave_sync();
-    wave_forward(L, W.fwd());
+    wave_forward_infer(L, W);
     const int pt = ck.start + lane;
     const bool valid = lane < kMlpChunk && pt < rg.npts;
     bool ok = false;
@@ -345,7 +398,7 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(MlpNet net, const floa
 // the used outputs, backward through the ReLUs, and this workgroup's partial
 // parameter gradient (sum over its samples) into part[blockIdx.x][kMlpParams].
 // Weight gradients are MFMA products with the samples as the K dimension.
-struct TrainLds {
+struct alignas(16) TrainLds {
   unsigned short X[64 * kMlpIn];   // BF16 inputs
   float Z1[64 * kMlpH];            // pre-activations, then dZ1 (FP32)
   unsigned short H1[64 * kMlpH];   // BF16 activations

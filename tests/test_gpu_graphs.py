@@ -167,6 +167,10 @@ def test_batch_matches_individual_bitwise():
         s.close()
 
 
+@pytest.mark.skip(reason="aborted (SIGABRT inside the former batch autotuner, which re-captured the batch "
+                         "graph for every tile shape) with no GPU fault and no cause found by reading; that "
+                         "autotuner is switched off (the batch now tunes with each member's stage kernel) and "
+                         "this case stays off the GPU")
 def test_batch_autotune_and_errors():
     torch = need_gpu()
     announce("batch-autotune")
@@ -190,3 +194,39 @@ def test_batch_autotune_and_errors():
     bad = dict(cfgs[0], rk=atns.LSERK4)
     with pytest.raises(atns.AtnsError):
         atns.Batch([cfgs[0], bad])
+
+
+def test_batch_autotune_leaves_states_and_picks_shapes():
+    torch = need_gpu()
+    announce("batch-autotune-members")
+    cfgs = _batch_configs()
+    b = atns.Batch(cfgs)
+    for i, kw in enumerate(cfgs):
+        _start(b.members[i], kw, i, torch)
+    before = [to_np(m.get_state()) for m in b.members]
+    eu, ns = b.autotune(1)
+    assert eu[:2] in [(16, 16), (32, 8), (16, 8)] and eu[2] in (4, 8, 16, 32)
+    assert ns[:2] in [(16, 16), (32, 8), (16, 8)] and ns[2] in (8, 16, 32)
+    for m, kw, U in zip(b.members, cfgs, before):
+        assert m.get_tiles() == (eu if kw["physics"] == atns.EULER else ns)
+        assert np.array_equal(to_np(m.get_state()), U)      # timing never touches the state
+        assert m.step_number() == 0
+    b.step(7)
+    assert all(np.isfinite(to_np(m.get_state())).all() for m in b.members)
+    b.close()
+
+
+def test_batch_refuses_members_at_different_steps():
+    torch = need_gpu()
+    announce("batch-errors")
+    cfgs = _batch_configs()[:2]
+    b = atns.Batch(cfgs)
+    for i, kw in enumerate(cfgs):
+        _start(b.members[i], kw, i, torch)
+    b.step(6)
+    b.members[0].step(1)
+    with pytest.raises(atns.AtnsError):
+        b.step(1)
+    b.close()
+    with pytest.raises(atns.AtnsError):
+        atns.Batch([cfgs[0], dict(cfgs[0], rk=atns.LSERK4)])
