@@ -114,6 +114,8 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
   // z-fluxes of the last four gradient planes at the tile, plane q in slot
   // q mod 4; each thread reads only its own cells (no barrier needed)
   __shared__ T sH[4][5][TY][TX];
+  // x/y divergence of the tile's points, by plane parity (3D)
+  __shared__ T sXY[2][5][TY][TX];
 
   // queues: q*[j] holds plane f-4+j; rr[j] holds the density of plane f-2+j
   // (pressure and energy at the gradient plane are rebuilt from rho, T and u)
@@ -123,10 +125,6 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
   for (int j = 0; j < 5; ++j) qu[j] = qv[j] = qw[j] = qT[j] = T(0);
 #pragma unroll
   for (int j = 0; j < 3; ++j) rr[j] = T(1);
-  // x/y divergence of the plane that finishes next
-  T xyd[5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) xyd[v] = T(0);
   const T igM2 = (T)(1.0 / p.mach2_gamma), igm1 = (T)(1.0 / (p.gamma - 1.0));
 
   T* ring_slot = nullptr;
@@ -290,17 +288,33 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
       }
     }
     // ------------------------- C. x and y divergence of plane m - 1 (3D) / m (2D)
+    // 3D: the threads outside the tile form it for every tile point, into
+    // an LDS plane that the tile threads read one iteration later (after
+    // the next barrier); the tile threads meanwhile go on to finish their
+    // plane.  2D: the tile threads form it and use it at once.
     const int dm = m - 1;
     const int dbuf = buf ^ 1;
     T xyn[5] = {T(0), T(0), T(0), T(0), T(0)};
-    if (core && (dm - z0) >= 0 && (dm - z0) < nz) {
+    auto xy_div = [&](int v, int px, int py) {
+      const T ddx = (T(8) * (sFX[dbuf][v][py][px + 3] - sFX[dbuf][v][py][px + 1]) -
+                     (sFX[dbuf][v][py][px + 4] - sFX[dbuf][v][py][px])) * ihx;
+      const T ddy = (T(8) * (sFY[dbuf][v][py + 3][px] - sFY[dbuf][v][py + 1][px]) -
+                     (sFY[dbuf][v][py + 4][px] - sFY[dbuf][v][py][px])) * ihy;
+      return ddx + ddy;
+    };
+    if constexpr (three) {
+      if (tid >= TX * TY && (dm - z0) >= 0 && (dm - z0) < nz) {
+        constexpr int nthr = EX * EY - TX * TY;
+        for (int i = tid - TX * TY; i < 5 * TX * TY; i += nthr) {
+          const int v = i / (TX * TY), q = i % (TX * TY);
+          const int px = q % TX, py = q / TX;
+          if (px < nx && py < ny) sXY[dbuf][v][py][px] = xy_div(v, px, py);
+        }
+      }
+    } else {
+      if (core && (dm - z0) >= 0 && (dm - z0) < nz) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const T ddx = (T(8) * (sFX[dbuf][v][y][x + 3] - sFX[dbuf][v][y][x + 1]) -
-                       (sFX[dbuf][v][y][x + 4] - sFX[dbuf][v][y][x])) * ihx;
-        const T ddy = (T(8) * (sFY[dbuf][v][y + 3][x] - sFY[dbuf][v][y + 1][x]) -
-                       (sFY[dbuf][v][y + 4][x] - sFY[dbuf][v][y][x])) * ihy;
-        xyn[v] = ddx + ddy;
+        for (int v = 0; v < 5; ++v) xyn[v] = xy_div(v, x, y);
       }
     }
     // ------------------------------------------------- D. finish plane pz
@@ -308,7 +322,7 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
     if (core && pz >= z0 && pz < z0 + nz) {
       T R[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) R[v] = three ? -(xyd[v] + zd[v]) : -xyn[v];
+      for (int v = 0; v < 5; ++v) R[v] = three ? -(sXY[buf][v][y][x] + zd[v]) : -xyn[v];
       T out[5];
       epilogue_pre<T, KIND>(p, gi, Yv, R, accv, u0v, out);
       if (pz + 1 < z0 + nz) {
@@ -321,8 +335,6 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
       }
       if (ring_slot) ring_store(p, B, rmask, lx, ly, pz, out, ring_slot);
     }
-#pragma unroll
-    for (int v = 0; v < 5; ++v) xyd[v] = xyn[v];
   }
 }
 
