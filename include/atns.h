@@ -215,8 +215,8 @@ atns_status atns_profile_enable(atns_ctx* ctx, int32_t on);
 atns_status atns_profile_read(atns_ctx* ctx, int64_t* launches, double* total_ms);
 
 /* Tile shape of the stage kernels: a workgroup walks a TX x TY column of one
- * block through TZ planes.  Supported (TX, TY), both physics: (16,16) (32,8)
- * (16,8).  Tiles never straddle
+ * block through TZ planes.  Supported (TX, TY): Euler (16,16) (32,8) (16,8)
+ * (64,8) (32,16); Navier-Stokes (16,16) (32,8) (16,8).  Tiles never straddle
  * blocks; ragged edges are handled.  EINVAL for other shapes or tz < 1. */
 atns_status atns_set_tiles(atns_ctx* ctx, int32_t tx, int32_t ty, int32_t tz);
 atns_status atns_get_tiles(const atns_ctx* ctx, int32_t* tx, int32_t* ty, int32_t* tz);

@@ -279,13 +279,20 @@ void build_tiles(atns_ctx* c, int TX, int TY, int TZ) {
   }
 }
 
-// (TX, TY) column shapes the stage kernels are instantiated for (both physics).
-constexpr int kNumShapes = 3;
-constexpr int kShapes[kNumShapes][2] = {{16, 16}, {32, 8}, {16, 8}};
+// (TX, TY) column shapes the stage kernels are instantiated for.  The
+// Navier-Stokes kernel runs one thread per point of the tile plus a 4-point
+// apron, which caps its tiles at (16,16) and (32,8) (at most 1024 threads).
+constexpr int kNumEulerShapes = 5;
+constexpr int kEulerShapes[kNumEulerShapes][2] = {{16, 16}, {32, 8}, {16, 8}, {64, 8}, {32, 16}};
+constexpr int kNumNsShapes = 3;
+constexpr int kNsShapes[kNumNsShapes][2] = {{16, 16}, {32, 8}, {16, 8}};
 
-bool shape_supported(int /*physics*/, int tx, int ty) {
-  for (const auto& s : kShapes)
-    if (s[0] == tx && s[1] == ty) return true;
+int num_shapes(int physics) { return physics == ATNS_NS ? kNumNsShapes : kNumEulerShapes; }
+const int* shape_at(int physics, int i) { return physics == ATNS_NS ? kNsShapes[i] : kEulerShapes[i]; }
+
+bool shape_supported(int physics, int tx, int ty) {
+  for (int i = 0; i < num_shapes(physics); ++i)
+    if (shape_at(physics, i)[0] == tx && shape_at(physics, i)[1] == ty) return true;
   return false;
 }
 
@@ -1158,11 +1165,11 @@ atns_status atns_autotune(atns_ctx* c, int32_t reps, const char* cache_path, int
     pick[0] = c->tile[0];
     pick[1] = c->tile[1];
     pick[2] = c->tile[2];
-    for (int i = 0; i < kNumShapes; ++i)
+    for (int i = 0; i < num_shapes(c->cfg.physics); ++i)
       for (int tz : tzs) {
         if (c->cfg.ndim == 2 && tz != 4) continue;
         if (ns && tz < 8) continue;   // 8 extra planes per column: short ones waste work
-        const int tx = kShapes[i][0], ty = kShapes[i][1];
+        const int tx = shape_at(c->cfg.physics, i)[0], ty = shape_at(c->cfg.physics, i)[1];
         atns_status st = atns_set_tiles(c, tx, ty, tz);
         if (st != ATNS_OK) return st;
         float ms = 0.f;
@@ -1694,10 +1701,11 @@ atns_status atns_batch_autotune(atns_batch* b, int32_t reps, int32_t* best) {
     if (!any) continue;
     float best_ms = 1e30f;
     int pick[3] = {b->shape[ph][0], b->shape[ph][1], b->shape[ph][2]};
-    for (int i = 0; i < kNumShapes; ++i)
+    const int phys = ph ? ATNS_NS : ATNS_EULER;
+    for (int i = 0; i < num_shapes(phys); ++i)
       for (int tz : {4, 8, 16, 32}) {
         if (ph == 1 && tz < 8) continue;
-        const int tx = kShapes[i][0], ty = kShapes[i][1];
+        const int tx = shape_at(phys, i)[0], ty = shape_at(phys, i)[1];
         float total = 0.f;
         for (atns_ctx* c : b->m) {
           if ((c->cfg.physics == ATNS_NS) != (ph == 1)) continue;

@@ -82,14 +82,19 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
     arole = 2;
   }
 
+  // each thread's column(s) resolved once: its own, and its apron column
+  ColumnSource<T> colq{}, cola{};
+  if (act) colq = column_source(p, B, lx, ly);
+  if (arole) cola = column_source(p, B, t.x0 + ax, t.y0 + ay);
+
   T q[5][5];
   T nq[5], na[5];   // prefetched: own column at z+2 and the apron point at z
   if (act && three) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) fetch(p, B, t.blk, lx, ly, t.z0 - 2 + j, q[j + 1]);
-    fetch(p, B, t.blk, lx, ly, t.z0 + 2, nq);
+    for (int j = 0; j < 4; ++j) fetch_col(p, B, colq, t.blk, lx, ly, t.z0 - 2 + j, q[j + 1]);
+    fetch_col(p, B, colq, t.blk, lx, ly, t.z0 + 2, nq);
   }
-  if (arole) fetch(p, B, t.blk, t.x0 + ax, t.y0 + ay, t.z0, na);
+  if (arole) fetch_col(p, B, cola, t.blk, t.x0 + ax, t.y0 + ay, t.z0, na);
 
   T* ring_slot = nullptr;
   unsigned rmask = 0;
@@ -116,9 +121,9 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
 #pragma unroll
         for (int v = 0; v < 5; ++v) q[4][v] = nq[v];
         // next plane's column value: in flight while this plane is computed
-        if (iz + 1 < t.nz) fetch(p, B, t.blk, lx, ly, lz + 3, nq);
+        if (iz + 1 < t.nz) fetch_col(p, B, colq, t.blk, lx, ly, lz + 3, nq);
       } else {
-        fetch(p, B, t.blk, lx, ly, lz, q[2]);
+        fetch_col(p, B, colq, t.blk, lx, ly, lz, q[2]);
       }
       T f[5];
       euler_flux(q[2], 0, gm1, f);
@@ -132,7 +137,7 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
       T u[5], f[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) u[v] = na[v];
-      if (iz + 1 < t.nz) fetch(p, B, t.blk, t.x0 + ax, t.y0 + ay, lz + 1, na);
+      if (iz + 1 < t.nz) fetch_col(p, B, cola, t.blk, t.x0 + ax, t.y0 + ay, lz + 1, na);
       if (arole == 1) {
         euler_flux(u, 0, gm1, f);
 #pragma unroll
@@ -213,6 +218,8 @@ hipError_t launch_euler_batch(const StageParams<T>* ps, const BatchTile* tl, int
   if (tx == 16 && ty == 16) return launch_euler_batch_shape<T, 16, 16>(ps, tl, ntiles, grid, kind, s);
   if (tx == 32 && ty == 8) return launch_euler_batch_shape<T, 32, 8>(ps, tl, ntiles, grid, kind, s);
   if (tx == 16 && ty == 8) return launch_euler_batch_shape<T, 16, 8>(ps, tl, ntiles, grid, kind, s);
+  if (tx == 64 && ty == 8) return launch_euler_batch_shape<T, 64, 8>(ps, tl, ntiles, grid, kind, s);
+  if (tx == 32 && ty == 16) return launch_euler_batch_shape<T, 32, 16>(ps, tl, ntiles, grid, kind, s);
   return hipErrorInvalidValue;
 }
 template hipError_t launch_euler_batch<float>(const StageParams<float>*, const BatchTile*, int, int, int, int, int,
@@ -240,6 +247,8 @@ hipError_t launch_euler_stage(const StageParams<T>& p, int ntiles, int kind, int
   if (tx == 16 && ty == 16) return launch_euler_shape<T, 16, 16>(p, ntiles, kind, s);
   if (tx == 32 && ty == 8) return launch_euler_shape<T, 32, 8>(p, ntiles, kind, s);
   if (tx == 16 && ty == 8) return launch_euler_shape<T, 16, 8>(p, ntiles, kind, s);
+  if (tx == 64 && ty == 8) return launch_euler_shape<T, 64, 8>(p, ntiles, kind, s);
+  if (tx == 32 && ty == 16) return launch_euler_shape<T, 32, 16>(p, ntiles, kind, s);
   return hipErrorInvalidValue;
 }
 

@@ -11,7 +11,7 @@ from paper_2506_03027_amd import atns, inputs
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = {"euler": [(16, 16), (32, 8), (16, 8)],
+SHAPES = {"euler": [(16, 16), (32, 8), (16, 8), (64, 8), (32, 16)],
           "ns": [(16, 16), (32, 8), (16, 8)]}
 
 
