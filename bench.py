@@ -177,7 +177,7 @@ def stored_traffic(workload):
     return rec.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(torch, w, budget_s=20.0):
+def cpu_baseline(torch, w, budget_s=15.0):
     """The FP64 oracle on a bounded sample of the workload: the same block
     shape and halo scheme on a smaller grid, started from a delayed history
     of the translating vortex so that every timed step is asynchronous.  The
@@ -207,7 +207,7 @@ def cpu_baseline(torch, w, budget_s=20.0):
         o.set_state(hist[m], step=m)
     t0 = time.perf_counter()
     done = 0
-    while done < 1 or (time.perf_counter() - t0 < budget_s * 0.5 and done < 8):
+    while done < 1 or (time.perf_counter() - t0 < budget_s and done < 64):
         o.step(1)
         done += 1
     elapsed = time.perf_counter() - t0
