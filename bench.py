@@ -428,6 +428,73 @@ def mlp_main(a, torch):
     print(json.dumps(out))
 
 
+def series_main(a, torch):
+    """The workload run for a.series steps with the FP64 diagnostics (conserved
+    totals, kinetic energy, enstrophy) reduced on the GPU after every step."""
+    w = inputs.WORKLOADS[a.workload]
+    g = make_solver(w, atns.F32)
+    n = w["n"]
+    coarse = tuple(min(64, x) for x in n)
+    U0 = (inputs.tgv_state(coarse, mach=w.get("mach", 0.1)) if w["physics"] == "ns"
+          else inputs.vortex_state(coarse, w["length"], w["ndim"]))
+    dt = inputs.cfl_dt(U0, n, w["length"], w["ndim"], 1.4, w["cfl"])
+    g.set_dt(dt)
+    g.init_case(atns.CASE_TGV if w["physics"] == "ns" else atns.CASE_VORTEX)
+    g.autotune(reps=2, cache=TUNE_CACHE)
+    rows = [(0, 0.0) + tuple(g.reduce()[0])]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    finite = True
+    for s in range(1, a.series + 1):
+        g.step(1)
+        d, ok = g.reduce()
+        finite = finite and ok
+        rows.append((s, s * dt) + tuple(d))
+        if not ok:
+            break
+    wall = time.perf_counter() - t0
+    g.close()
+    R = np.array(rows)
+    ref = None
+    if a.series_ref:
+        # the same series from the FP64 synchronous solver (the scheme without
+        # delays or FP32 rounding), step for step
+        def sa_series(precision):
+            r = make_solver(dict(w, mode="sa", L=1), precision)
+            r.set_dt(dt)
+            r.init_case(atns.CASE_TGV if w["physics"] == "ns" else atns.CASE_VORTEX)
+            rr = [tuple(r.reduce()[0])]
+            for s in range(1, len(rows)):
+                r.step(1)
+                rr.append(tuple(r.reduce()[0]))
+            r.close()
+            return np.array(rr)
+
+        Q = sa_series(atns.F64)
+        Q32 = sa_series(atns.F32)
+        ref = {"solver": "FP64 synchronous (SA), same grid and dt",
+               "max_rel_diff_kinetic_energy": float(np.abs(R[:, 7] - Q[:, 5]).max() / abs(Q[0, 5])),
+               "max_rel_diff_enstrophy": float(np.abs(R[:, 8] - Q[:, 6]).max() / abs(Q[0, 6])),
+               "kinetic_energy_end": float(Q[-1, 5]), "enstrophy_end": float(Q[-1, 6]),
+               "fp32_sa_max_rel_diff_kinetic_energy": float(np.abs(Q32[:, 5] - Q[:, 5]).max() / abs(Q[0, 5])),
+               "fp32_sa_max_rel_diff_enstrophy": float(np.abs(Q32[:, 6] - Q[:, 6]).max() / abs(Q[0, 6]))}
+    if a.series_out:
+        np.savetxt(a.series_out, R, delimiter=",",
+                   header="step,t,mass,mom_x,mom_y,mom_z,energy,kinetic_energy,enstrophy", comments="")
+    K, E = R[:, 7], R[:, 8]
+    out = {"workload": a.workload, "steps": int(R[-1, 0]), "dt": dt, "t_end": float(R[-1, 1]),
+           "finite": bool(finite), "wall_s_with_per_step_reductions": wall,
+           "kinetic_energy": {"t0": float(K[0]), "end": float(K[-1]),
+                              "monotone_nonincreasing": bool(np.all(np.diff(K) <= 1e-12 * K[0]))},
+           "enstrophy": {"t0": float(E[0]), "end": float(E[-1]), "max": float(E.max())},
+           "mass_rel_drift": float(abs(R[-1, 2] - R[0, 2]) / abs(R[0, 2])),
+           "energy_rel_drift": float(abs(R[-1, 6] - R[0, 6]) / abs(R[0, 6])),
+           "dK_dt_fit_first_200_steps": float(np.polyfit(R[:201, 1], K[:201], 1)[0])}
+    if ref:
+        out["reference"] = ref
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,6 +503,11 @@ def main():
     ap.add_argument("--workload", default="vortex3d_128")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--series", type=int, default=0,
+                    help="run this many steps with the FP64 diagnostics reduced after every step")
+    ap.add_argument("--series-out", default=None, help="CSV file for --series")
+    ap.add_argument("--series-ref", action="store_true",
+                    help="with --series: also run the FP64 synchronous solver and compare the series")
     ap.add_argument("--mlp", action="store_true",
                     help="learned-halo run (Taylor-Green workloads): train, then AT with and without it")
     a = ap.parse_args()
@@ -450,6 +522,9 @@ def main():
         return
     if a.mlp:
         mlp_main(a, torch)
+        return
+    if a.series:
+        series_main(a, torch)
         return
     w = inputs.WORKLOADS[a.workload]
     stages = 4 if w["rk"] == "rk4" else 5

@@ -315,17 +315,19 @@ __global__ void __launch_bounds__(256) mlp_halo_kernel(MlpFeatArgs<T> a, MlpNet 
 #pragma unroll
       for (int v = 0; v < 5; ++v) n2 += W.o[lane * kMlpOut + v] * W.o[lane * kMlpOut + v];
       ok = n2 <= a.tau2;
-      if (ok) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const double d = (double)a.r[v] * (double)W.o[lane * kMlpOut + v];
-          const long long o = rg.dst + (long long)v * rg.npts + pt;
-          for (int e = 0; e < stages; ++e) hbuf[e * halo_stride + o] = (T)((double)hbuf[e * halo_stride + o] + d);
-        }
+    }
+    const unsigned long long okmask = __ballot(valid && ok);
+    n_ok += __popcll(okmask);
+    n_fb += __popcll(__ballot(valid && !ok));
+    // the 16 x 5 (point, variable) corrections spread over all lanes
+    for (int j = lane; j < kMlpChunk * 5; j += 64) {
+      const int p = j % kMlpChunk, v = j / kMlpChunk;
+      if ((okmask >> p) & 1ull) {
+        const double d = (double)a.r[v] * (double)W.o[p * kMlpOut + v];
+        const long long o = rg.dst + (long long)v * rg.npts + ck.start + p;
+        for (int e = 0; e < stages; ++e) hbuf[e * halo_stride + o] = (T)((double)hbuf[e * halo_stride + o] + d);
       }
     }
-    n_ok += __popcll(__ballot(valid && ok));
-    n_fb += __popcll(__ballot(valid && !ok));
     wave_sync();   // the next chunk overwrites this wave's scratch
   }
   if (lane == 0) {
