@@ -130,3 +130,21 @@ def test_batch_instances_are_valid_configs():
         if ctx.value:
             atns.lib().atns_destroy(ctx)
         assert st != -1, atns.lib().atns_last_error(None)
+
+
+def test_bench_byte_accounting_matches_the_per_point_figures():
+    """bench.py's algorithmic bytes per point and RK stage: 80 + 20 C f +
+    20 f / s (whole step) with f the halo points per owned point, and the
+    stage kernel's own 80 + 20 f + 20 f / s.  Pinned to the figures derived
+    by hand for 32^3 Euler blocks (f = 3/8), 16x16x32 Navier-Stokes blocks
+    (H = 4 faces plus 2x2 edges, f = 11/8) and 32^3 Navier-Stokes blocks
+    (f = 51/64)."""
+    import bench
+    from paper_2506_03027_amd import inputs
+    W = inputs.WORKLOADS
+    assert bench.halo_fraction(W["vortex3d_128"]) == 3 / 8
+    assert bench.halo_fraction(W["tgv_256"]) == 11 / 8
+    assert bench.halo_fraction(W["tgv_512"]) == 51 / 64
+    assert bench.algorithmic_bytes_per_point_stage(W["vortex3d_128"], 4, 4)[0] == 80 + 100 * 3 / 8 + 20 * 3 / 8 / 4
+    assert bench.stage_kernel_bytes_per_point(W["tgv_256"], 4, 4) == 80 + 20 * 11 / 8 + 20 * 11 / 8 / 4
+    assert bench.algorithmic_bytes_per_point_stage(dict(W["vortex3d_128"], mode="sa"), 4, 8)[0] == 160
