@@ -84,6 +84,7 @@ struct atns_ctx {
   bool use_graph = true;
   bool nstep_synced = false;
   uint64_t graph_gen = 0;   // bumped whenever captured step parameters go stale
+  unsigned int* d_done = nullptr;   // workgroups done in the last stage of a captured step
   hipEvent_t order_ev = nullptr;
   double* d_partials = nullptr;
   double* d_diag = nullptr;
@@ -456,6 +457,10 @@ StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind) {
   p.halo = kHaloSync;
   p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)e * c->slot_stride : nullptr;
   p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
+  if (e == rk.stages - 1) {   // the last stage also advances the step counter
+    p.step_end = c->d_nstep;
+    p.done = c->d_done;
+  }
   if (!rk.low_storage) {
     T* U = (T*)c->X[0];
     T* Ya = (T*)c->X[1];
@@ -485,10 +490,11 @@ StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind) {
 template <typename T>
 atns_status enqueue_graph_halos(atns_ctx* c, hipStream_t s) {
   if (c->cfg.mode == ATNS_SA) return ATNS_OK;
-  HIP_TRY(c, launch_delays(c->d_delays, nullptr, 0, c->nb, c->cfg.L, c->cfg.seed, c->cfg.algo, s, c->d_nstep));
+  // the halo kernel draws the step's delays itself (no injection here)
+  const DelayDraw dd{1, c->nb, c->cfg.algo == ATNS_SAA ? 1 : 0, (unsigned long long)c->cfg.seed};
   HIP_TRY(c, launch_halo<T>((const T*)c->ring, (T*)c->hbuf, c->d_regions, c->d_work, (int)c->work.size(),
                             c->d_delays, c->d_W, c->slot_stride, c->slot_stride, c->D, 0, c->cfg.L,
-                            c->rk.stages, c->cfg.mode == ATNS_AS, s, c->d_nstep));
+                            c->rk.stages, c->cfg.mode == ATNS_AS, s, c->d_nstep, dd));
   if (c->mlp_on && c->cfg.mode == ATNS_AT) {
     MlpFeatArgs<T> fa = feat_args<T>(c);
     fa.nstep = c->d_nstep;
@@ -499,7 +505,8 @@ atns_status enqueue_graph_halos(atns_ctx* c, hipStream_t s) {
   return ATNS_OK;
 }
 
-// One captured step: halos, s stage kernels, counter increment.
+// One captured step: halos (with the delay draw) and the s stage kernels;
+// the last stage kernel advances the device step counter when it finishes.
 template <typename T>
 atns_status capture_step(atns_ctx* c, hipGraphExec_t* out) {
   hipStream_t s = work_stream(c);
@@ -514,10 +521,6 @@ atns_status capture_step(atns_ctx* c, hipGraphExec_t* out) {
             ? launch_ns_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], s)
             : launch_euler_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], s);
     if (r != hipSuccess) st = fail(c, ATNS_EHIP, std::string("stage launch in capture: ") + hipGetErrorString(r));
-  }
-  if (st == ATNS_OK) {
-    const hipError_t r = launch_step_inc1(c->d_nstep, s);
-    if (r != hipSuccess) st = fail(c, ATNS_EHIP, std::string("counter launch in capture: ") + hipGetErrorString(r));
   }
   const hipError_t ec = hipStreamEndCapture(s, &graph);
   if (st != ATNS_OK) {
@@ -633,6 +636,8 @@ void release(atns_ctx* c) {
   c->order_ev = nullptr;
   if (c->d_nstep) (void)hipFree(c->d_nstep);
   c->d_nstep = nullptr;
+  if (c->d_done) (void)hipFree(c->d_done);
+  c->d_done = nullptr;
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   c->ev_pool.clear();
   for (void*& x : c->X)
@@ -694,7 +699,9 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
     return s;
   };
   if (hipGetDevice(&c->device) != hipSuccess) return fail_free(ATNS_EHIP, "no HIP device");
-  if (hipMalloc((void**)&c->d_nstep, sizeof(long long)) != hipSuccess)
+  if (hipMalloc((void**)&c->d_nstep, sizeof(long long)) != hipSuccess ||
+      hipMalloc((void**)&c->d_done, sizeof(unsigned int)) != hipSuccess ||
+      hipMemset(c->d_done, 0, sizeof(unsigned int)) != hipSuccess)
     return fail_free(ATNS_ENOMEM, "counter allocation failed");
   if (!c->stream && hipStreamCreate(&c->gstream) != hipSuccess)
     return fail_free(ATNS_EHIP, "stream creation failed");

@@ -34,6 +34,23 @@ __device__ __forceinline__ StageParams<T> resolve_step(const StageParams<T>& p) 
   return q;
 }
 
+// End of a captured step: every workgroup of the last stage kernel counts
+// itself done; the last one (all others have finished, so nobody reads the
+// step counter any more in this launch) advances the counter and resets the
+// done count for the next step.  No fence is needed: each workgroup read the
+// counter before counting itself done, and the next kernel sees the new
+// value at the kernel boundary.
+__device__ __forceinline__ void finish_step(long long* step, unsigned int* done) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned int prev = atomicAdd(done, 1u);
+    if (prev == gridDim.x - 1) {
+      *step += 1;
+      *done = 0u;
+    }
+  }
+}
+
 // Copy a block descriptor into LDS (cooperatively, 32-bit words) and wait.
 __device__ __forceinline__ void stage_block(const BlockDev* __restrict__ src, BlockDev* dst) {
   constexpr int nw = (int)(sizeof(BlockDev) / 4);

@@ -181,6 +181,7 @@ template <typename T, int TX, int TY, int KIND>
 __global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T> p) {
   const StageParams<T> q = resolve_step(p);
   euler_tile<T, TX, TY, KIND>(q, p.tiles[blockIdx.x]);
+  if (p.step_end) finish_step(p.step_end, p.done);
 }
 
 // Persistent form for a batch: every workgroup walks the combined tile list

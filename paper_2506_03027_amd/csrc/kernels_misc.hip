@@ -13,24 +13,42 @@ __device__ __forceinline__ unsigned long long sm64(unsigned long long seed, unsi
   return z ^ (z >> 31);
 }
 
-// Delays of step n (n >= C) for every (block, slot): CAA (n - C) mod L,
-// SAA SplitMix64 draw mod L, or the injected value; then the Alg. 3 guard.
+// Alg. 3 guard: delays beyond L-1 or beyond the available history are 0.
+__device__ __forceinline__ int guard_delay(long long k, long long n, int L) {
+  return (k < 0 || k > L - 1 || k > n - kLevels + 1) ? 0 : (int)k;
+}
+
+// Delay of step n (n >= C) for (block, slot) index i = b * 18 + slot:
+// CAA (n - C) mod L, SAA SplitMix64 draw mod L; then the guard.
+// x mod L for a small L (1 <= L <= 16) from 32-bit pieces: with
+// x = hi 2^32 + lo, x mod L = ((hi mod L)(2^32 mod L) + lo mod L) mod L,
+// the same value as the 64-bit remainder, at 32-bit cost.
+__device__ __forceinline__ unsigned mod_small(unsigned long long x, unsigned L) {
+  const unsigned hi = (unsigned)(x >> 32), lo = (unsigned)x;
+  const unsigned p32 = (unsigned)((1ull << 32) % L);
+  return ((hi % L) * p32 + lo % L) % L;
+}
+
+__device__ __forceinline__ int draw_delay(long long n, int i, int nblocks, int L, unsigned long long seed, int algo) {
+  if (n < kLevels) return 0;   // synchronous steps (not drawn)
+  long long k;
+  if (algo == 0) {
+    k = mod_small((unsigned long long)(n - kLevels), (unsigned)L);
+  } else {
+    const unsigned long long draw = (unsigned long long)n * (unsigned long long)nblocks * kNumSlots + i;
+    k = mod_small(sm64(seed, draw), (unsigned)L);
+  }
+  return guard_delay(k, n, L);
+}
+
+// Delays of step n for every (block, slot): the rule above, or the injected
+// value (guarded the same way).
 __global__ void delays_kernel(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
                               unsigned long long seed, int algo, const long long* nstep) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nblocks * kNumSlots) return;
   if (nstep) n = *nstep;
-  long long k;
-  if (inject) {
-    k = inject[i];
-  } else if (algo == 0) {
-    k = (n - kLevels) % L;
-  } else {
-    const unsigned long long draw = (unsigned long long)n * (unsigned long long)nblocks * kNumSlots + i;
-    k = (long long)(sm64(seed, draw) % (unsigned long long)L);
-  }
-  if (k < 0 || k > L - 1 || k > n - kLevels + 1) k = 0;
-  out[i] = (int8_t)k;
+  out[i] = (int8_t)(inject ? guard_delay(inject[i], n, L) : draw_delay(n, i, nblocks, L, seed, algo));
 }
 
 hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
@@ -45,11 +63,6 @@ __global__ void step_set_kernel(long long* nstep, long long value) { *nstep = va
 __global__ void step_inc_kernel(long long* const* counters, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) *counters[i] += 1;
-}
-__global__ void step_inc1_kernel(long long* nstep) { *nstep += 1; }
-hipError_t launch_step_inc1(long long* nstep, hipStream_t s) {
-  step_inc1_kernel<<<1, 1, 0, s>>>(nstep);
-  return hipGetLastError();
 }
 hipError_t launch_step_set(long long* nstep, long long value, hipStream_t s) {
   step_set_kernel<<<1, 1, 0, s>>>(nstep, value);
@@ -70,15 +83,27 @@ hipError_t launch_step_inc(long long* const* counters, int n, hipStream_t s) {
 template <typename T, int S, bool STALE>
 __global__ void __launch_bounds__(kHaloChunk)
     halo_kernel(const T* __restrict__ ring, T* __restrict__ halo, const HaloRegion* __restrict__ regions,
-                const HaloWork* __restrict__ work, const int8_t* __restrict__ delays,
+                const HaloWork* __restrict__ work, int8_t* __restrict__ delays,
                 const double* __restrict__ W, long long slot_stride, long long halo_stride, int D,
-                int slot_now, int L, const long long* nstep) {
-  if (nstep) slot_now = (int)(*nstep % D);
+                int slot_now, int L, const long long* nstep, DelayDraw dd) {
+  long long n = 0;
+  if (nstep) {
+    n = *nstep;
+    slot_now = (int)(n % D);
+  }
   const HaloWork wk = work[blockIdx.x];
   const HaloRegion rg = regions[wk.region];
+  int k;
+  if (dd.draw) {
+    // the step's delay of this region, drawn here (graph-captured steps);
+    // the region's first chunk records it for the learned-halo correction
+    k = draw_delay(n, rg.kidx, dd.nblocks, L, dd.seed, dd.algo);
+    if (wk.start == 0 && threadIdx.x == 0) delays[rg.kidx] = (int8_t)k;
+  } else {
+    k = delays[rg.kidx];
+  }
   const int i = wk.start + threadIdx.x;
   if (i >= rg.npts) return;
-  const int k = delays[rg.kidx];
   int sl[kLevels];
 #pragma unroll
   for (int l = 0; l < kLevels; ++l) {
@@ -110,13 +135,13 @@ __global__ void __launch_bounds__(kHaloChunk)
 
 template <typename T>
 hipError_t launch_halo(const T* ring, T* halo, const HaloRegion* regions, const HaloWork* work, int nwork,
-                       const int8_t* delays, const double* W, long long slot_stride, long long halo_stride,
+                       int8_t* delays, const double* W, long long slot_stride, long long halo_stride,
                        int D, int slot_now, int L, int stages, bool stale, hipStream_t s,
-                       const long long* nstep) {
+                       const long long* nstep, DelayDraw dd) {
   dim3 grid(nwork), block(kHaloChunk);
 #define ATNS_HALO(SS, ST)                                                                               \
   halo_kernel<T, SS, ST><<<grid, block, 0, s>>>(ring, halo, regions, work, delays, W, slot_stride, \
-                                                 halo_stride, D, slot_now, L, nstep)
+                                                 halo_stride, D, slot_now, L, nstep, dd)
   if (stages == 4) {
     if (stale) ATNS_HALO(4, true); else ATNS_HALO(4, false);
   } else {
@@ -125,12 +150,12 @@ hipError_t launch_halo(const T* ring, T* halo, const HaloRegion* regions, const 
 #undef ATNS_HALO
   return hipGetLastError();
 }
-template hipError_t launch_halo<float>(const float*, float*, const HaloRegion*, const HaloWork*, int,
-                                       const int8_t*, const double*, long long, long long, int, int, int,
-                                       int, bool, hipStream_t, const long long*);
-template hipError_t launch_halo<double>(const double*, double*, const HaloRegion*, const HaloWork*, int,
-                                        const int8_t*, const double*, long long, long long, int, int, int,
-                                        int, bool, hipStream_t, const long long*);
+template hipError_t launch_halo<float>(const float*, float*, const HaloRegion*, const HaloWork*, int, int8_t*,
+                                       const double*, long long, long long, int, int, int, int, bool, hipStream_t,
+                                       const long long*, DelayDraw);
+template hipError_t launch_halo<double>(const double*, double*, const HaloRegion*, const HaloWork*, int, int8_t*,
+                                        const double*, long long, long long, int, int, int, int, bool, hipStream_t,
+                                        const long long*, DelayDraw);
 
 // Copy the boundary layers of every block of field U into ring slot `slot`.
 template <typename T>

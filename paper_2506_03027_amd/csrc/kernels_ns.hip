@@ -343,6 +343,7 @@ template <typename T, int TX, int TY, int KIND, int NDIM>
 __global__ void __launch_bounds__((TX + 8) * (TY + 8)) __attribute__((amdgpu_waves_per_eu(5, 8))) ns_stage_kernel(const StageParams<T> p) {
   const StageParams<T> q = resolve_step(p);
   ns_tile<T, TX, TY, KIND, NDIM>(q, p.tiles[blockIdx.x]);
+  if (p.step_end) finish_step(p.step_end, p.done);
 }
 
 // Persistent form for a batch (see the Euler kernel).

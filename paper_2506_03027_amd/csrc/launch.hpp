@@ -19,13 +19,12 @@ hipError_t launch_ns_batch(const StageParams<T>* ps, const BatchTile* tl, int nt
                            int ty, hipStream_t s);
 hipError_t launch_step_set(long long* nstep, long long value, hipStream_t s);
 hipError_t launch_step_inc(long long* const* counters, int n, hipStream_t s);
-hipError_t launch_step_inc1(long long* nstep, hipStream_t s);
 
 template <typename T>
 hipError_t launch_halo(const T* ring, T* halo, const HaloRegion* regions, const HaloWork* work, int nwork,
-                       const int8_t* delays, const double* W, long long slot_stride, long long halo_stride,
+                       int8_t* delays, const double* W, long long slot_stride, long long halo_stride,
                        int D, int slot_now, int L, int stages, bool stale, hipStream_t s,
-                       const long long* nstep = nullptr);
+                       const long long* nstep = nullptr, DelayDraw dd = DelayDraw{0, 0, 0, 0ull});
 template <typename T>
 hipError_t launch_init_case(T* U, const int n[3], const double h[3], const double len[3], int kind, int ndim,
                             double gamma, double mach, double beta, double t, double xc, double yc, hipStream_t s);

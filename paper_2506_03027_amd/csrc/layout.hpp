@@ -74,6 +74,15 @@ struct HaloWork {
   int start;
 };
 
+// Delay rule of a context for halo kernels that draw the step's delays
+// themselves (draw != 0).
+struct DelayDraw {
+  int draw;
+  int nblocks;
+  int algo;
+  unsigned long long seed;
+};
+
 struct TileDev {
   int blk;                  // block id
   short x0, y0, z0;         // tile origin, block-local
@@ -118,6 +127,10 @@ struct StageParams {
   // counter: slot_now = n % D and halo = (n >= C) ? async_halo : kHaloSync.
   const long long* nstep;
   int async_halo;
+  // Set only for the last stage of a captured step: the workgroup that
+  // finishes last (counted in *done) advances *step_end by one.
+  long long* step_end;
+  unsigned int* done;
   int L;
   int H;                 // halo depth (faces)
   int ndim;
