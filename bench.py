@@ -119,7 +119,7 @@ def gpu_run(torch, w, precision, mode, steps, warmup, U0, dt):
     g = make_solver(w, precision, mode)
     g.set_dt(dt)
     g.set_state(torch.from_numpy(U0))
-    tiles = g.autotune(reps=3, cache=TUNE_CACHE)   # tile shape of the stage kernels
+    tiles = g.autotune(reps=10, cache=TUNE_CACHE)   # tile shape of the stage kernels
     g.step(warmup)
     ms = time_steps(torch, g, steps)
     # per-launch durations of the fused stage kernel, from HIP events on the
@@ -260,7 +260,7 @@ def batch_main(a, torch):
     for m, w in zip(b.members, ws):
         start_instance(m, w)
     b.step(C_LEVELS + 1)
-    eu, nst = b.autotune(reps=2)
+    eu, nst = b.autotune(reps=10)
     b.step(a.warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -276,7 +276,7 @@ def batch_main(a, torch):
         s = atns.Solver(**solver_kwargs(w))
         start_instance(s, w)
         s.step(C_LEVELS + 1)
-        s.autotune(reps=2, cache=TUNE_CACHE)
+        s.autotune(reps=10, cache=TUNE_CACHE)
         s.step(a.warmup)
         solo_ms += time_steps(torch, s, a.steps)
         s.close()
@@ -366,7 +366,7 @@ def mlp_main(a, torch):
             g.mlp_set_params(theta)
             g.mlp_set_scales(s, r)
             g.mlp_enable(True, tau)
-        tiles = g.autotune(reps=2, cache=TUNE_CACHE)
+        tiles = g.autotune(reps=10, cache=TUNE_CACHE)
         g.step(C_LEVELS + 1 + a.warmup)
         g.mlp_stats() if use_mlp else None
         ms = time_steps(torch, g, a.steps)
@@ -440,7 +440,7 @@ def series_main(a, torch):
     dt = inputs.cfl_dt(U0, n, w["length"], w["ndim"], 1.4, w["cfl"])
     g.set_dt(dt)
     g.init_case(atns.CASE_TGV if w["physics"] == "ns" else atns.CASE_VORTEX)
-    g.autotune(reps=2, cache=TUNE_CACHE)
+    g.autotune(reps=10, cache=TUNE_CACHE)
     rows = [(0, 0.0) + tuple(g.reduce()[0])]
     torch.cuda.synchronize()
     t0 = time.perf_counter()

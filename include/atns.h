@@ -223,8 +223,11 @@ atns_status atns_get_tiles(const atns_ctx* ctx, int32_t* tx, int32_t* ty, int32_
 
 /* Autotuner of the tile shape.  Times every supported (TX, TY) with column
  * lengths TZ in {4, 8, 16, 32} (Navier-Stokes: 8, 16, 32) on the current
- * state -- reps launches of the stage kernel each, HIP events on the context
- * stream, results into a scratch register so the state is untouched -- and
+ * state -- reps times one step's mix of stage kernels (first, middle and
+ * last RK stage, with the ring write), HIP events on the context stream,
+ * writing only buffers that are dead at a step boundary (stage registers,
+ * accumulator, the ring slot of level n + 1), so the state and the next
+ * step are untouched -- and
  * keeps the fastest.  cache_path (or NULL) names a text file of
  * "key tx ty tz" lines; a configuration found there is applied without
  * timing, a newly tuned one is appended.  best_txyz (or NULL) receives the
@@ -301,9 +304,10 @@ atns_status atns_host_delays(int32_t algo, int64_t n, int32_t nblocks, int32_t L
  * walks the combined tile list of all members of that physics; the Euler and
  * Navier-Stokes members form two independent branches of the graph.  Each
  * physics uses one tile shape for all its members (atns_batch_set_tiles, or
- * atns_batch_autotune, which times every shape with each member's own stage
- * kernel -- right-hand side only, reps launches, into a scratch register, so
- * no state changes -- and applies, per physics, the shape with the least
+ * atns_batch_autotune, which times every shape with the stage kernel of the
+ * largest member of each physics -- one step's stage-kernel mix as for
+ * atns_autotune, so no state changes --
+ * and applies, per physics, the shape with the least
  * total time; best receives int[6] = Euler (tx, ty, tz), Navier-Stokes
  * (tx, ty, tz)).
  * Member results are bit-identical to stepping each member alone.

@@ -1130,18 +1130,53 @@ void cache_store(const char* path, const std::string& key, const int v[3]) {
 
 template <typename T>
 atns_status time_shape(atns_ctx* c, int reps, float* ms_out) {
-  StageParams<T> p = base_params<T>(c);
-  p.halo = kHaloSync;
-  p.slot_now = c->D ? (int)(c->step % c->D) : 0;
-  p.ring_write = 0;
-  p.Y = (const T*)state_ptr(c);
-  p.Yout = (T*)(c->rk.low_storage ? c->X[1 - c->cur] : c->X[1]);   // scratch register
+  // One step's mix of stage kernels on the current state -- first, middle
+  // and last RK stage, the last with its ring write -- writing only what is
+  // dead at a step boundary: the stage registers and the accumulator (RK4),
+  // or Q and the spare buffer (LSERK4); the last stage's output goes to a
+  // stage register instead of the state, and its ring write to slot
+  // (n + 1) mod D, whose level n + 1 - D no stage of step n reads.
+  const RKScheme& rk = c->rk;
+  std::vector<std::pair<StageParams<T>, int>> seq;
+  for (int e = 0; e < rk.stages; ++e) {
+    StageParams<T> p = base_params<T>(c);
+    p.halo = kHaloSync;
+    p.slot_now = c->D ? (int)(c->step % c->D) : 0;
+    p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
+    int kind;
+    if (!rk.low_storage) {
+      T* U = (T*)c->X[0];
+      T* Ya = (T*)c->X[1];
+      T* Yb = (T*)c->X[2];
+      p.U0 = U;
+      p.acc = (T*)c->X[3];
+      const T* ins[4] = {U, Ya, Yb, Ya};
+      T* outs[4] = {Ya, Yb, Ya, Yb};   // the last stage into Yb, not U
+      p.Y = ins[e];
+      p.Yout = outs[e];
+      kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
+      p.cA = rk.b[e];
+      p.cB = e < 3 ? rk.a[e + 1][e] : 0.0;
+    } else {
+      // the state buffer is only ever read; the stages alternate between
+      // the spare buffer and X[2], which low-storage schemes do not use
+      void* spare[2] = {c->X[1 - c->cur], c->X[2]};
+      p.Y = (const T*)(e == 0 ? c->X[c->cur] : spare[(e - 1) & 1]);
+      p.Yout = (T*)spare[e & 1];
+      p.acc = (T*)c->X[3];
+      kind = e == 0 ? kLSFirst : kLSMid;
+      p.cA = rk.A[e];
+      p.cB = rk.B[e];
+    }
+    seq.push_back({p, kind});
+  }
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
-  HIP_TRY(c, launch_stage<T>(c, p, kRhsOnly));   // warm
+  for (auto& q : seq) HIP_TRY(c, launch_stage<T>(c, q.first, q.second));   // warm
   HIP_TRY(c, hipEventRecord(e0, c->stream));
-  for (int r = 0; r < reps; ++r) HIP_TRY(c, launch_stage<T>(c, p, kRhsOnly));
+  for (int r = 0; r < reps; ++r)
+    for (auto& q : seq) HIP_TRY(c, launch_stage<T>(c, q.first, q.second));
   HIP_TRY(c, hipEventRecord(e1, c->stream));
   HIP_TRY(c, hipEventSynchronize(e1));
   float ms = 0.f;
@@ -1698,14 +1733,17 @@ atns_status atns_batch_autotune(atns_batch* b, int32_t reps, int32_t* best) {
   for (atns_ctx* c : b->m)
     if (!c->state_set) return bfail(b, ATNS_ESTATE, "member state not set");
   BHIP(b, hipDeviceSynchronize());
-  // Per physics: every shape is timed with each member's own stage kernel
-  // (right-hand side only, into a scratch register; states are untouched),
-  // and the shape with the least total time over the members is applied to
-  // the whole batch.
+  // Per physics: every shape is timed with the stage kernel of the largest
+  // member (a middle RK stage writing only registers that are dead at a
+  // step boundary; states are untouched) and the fastest is applied to the
+  // whole batch.  The largest member stands for the batch: there the time
+  // is set by throughput, as in the batch kernels, whereas small members
+  // alone are dominated by launch and tail effects that favour small tiles.
   for (int ph = 0; ph < 2; ++ph) {
-    bool any = false;
-    for (atns_ctx* c : b->m) any = any || ((c->cfg.physics == ATNS_NS) == (ph == 1));
-    if (!any) continue;
+    atns_ctx* rep = nullptr;
+    for (atns_ctx* c : b->m)
+      if ((c->cfg.physics == ATNS_NS) == (ph == 1) && (!rep || c->field > rep->field)) rep = c;
+    if (!rep) continue;
     float best_ms = 1e30f;
     int pick[3] = {b->shape[ph][0], b->shape[ph][1], b->shape[ph][2]};
     const int phys = ph ? ATNS_NS : ATNS_EULER;
@@ -1713,16 +1751,11 @@ atns_status atns_batch_autotune(atns_batch* b, int32_t reps, int32_t* best) {
       for (int tz : {4, 8, 16, 32}) {
         if (ph == 1 && tz < 8) continue;
         const int tx = shape_at(phys, i)[0], ty = shape_at(phys, i)[1];
+        atns_status st = atns_set_tiles(rep, tx, ty, tz);
+        if (st != ATNS_OK) return bfail(b, st, rep->err);
         float total = 0.f;
-        for (atns_ctx* c : b->m) {
-          if ((c->cfg.physics == ATNS_NS) != (ph == 1)) continue;
-          atns_status st = atns_set_tiles(c, tx, ty, tz);
-          if (st != ATNS_OK) return bfail(b, st, c->err);
-          float ms = 0.f;
-          st = c->esz == 4 ? time_shape<float>(c, reps, &ms) : time_shape<double>(c, reps, &ms);
-          if (st != ATNS_OK) return bfail(b, st, c->err);
-          total += ms;
-        }
+        st = rep->esz == 4 ? time_shape<float>(rep, reps, &total) : time_shape<double>(rep, reps, &total);
+        if (st != ATNS_OK) return bfail(b, st, rep->err);
         if (total < best_ms) {
           best_ms = total;
           pick[0] = tx;
