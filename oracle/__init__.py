@@ -16,7 +16,7 @@ arXiv 2506.03027 (Arumugam, Goswami, Vadlamani, Aditya):
 * ``delays``  -- delay schedules of the communication-avoiding (Alg. 2) and
                  synchronization-avoiding (Alg. 3) algorithms.
 * ``flow``    -- Euler / Navier-Stokes fluxes (Eq. 1, App. A) and the explicit
-                 CD4 derivative (Eq. 2, App. B).
+                 CD4 and CD2 derivatives (Eq. 2, App. B).
 * ``solver``  -- blocks (processing elements), delayed history, halo filling
                  in SA / AS / AT modes and the RK step (Sec. 3.2, Alg. 1-3).
 * ``diagnostics`` -- conserved totals, kinetic energy and enstrophy (Sec. 5.2).
@@ -30,12 +30,14 @@ What pins it (tests/test_oracle_*.py, all on the CPU):
   k^2 coefficient read as 26), RK4/LSERK order conditions, observed temporal
   order on an ODE, exactness of the extrapolation for polynomials, the
   literal buffer recursion equal to the closed form;
-* flow -- the CD4 modified wavenumber, fourth-order convergence, closed-form
+* flow -- the CD4 and CD2 modified wavenumbers, fourth- and second-order
+  convergence, CD2 exact on quadratics, closed-form
   viscous solutions (shear wave, heat conduction, compression wave),
   rotation covariance, the translating vortex, TGV initial kinetic energy and
   enstrophy in closed form;
 * solver -- decomposed SA equal to one block bit for bit, Table 1 orders for
-  SA/AT/AS, AT with zero delay converging to SA, conservation under SA,
+  SA/AT/AS (cases 4-6 with RK4/LSERK4-CD4-AT4, cases 1-3 with
+  LSERK2-CD2-AT2), AT with zero delay converging to SA, conservation under SA,
   a brute-force pointwise halo rule, the delay patterns of Alg. 2 and
   Alg. 3 and SplitMix64's published outputs;
 * mlp -- central-difference gradients, BF16 rounding, the fallback rule.

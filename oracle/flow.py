@@ -19,9 +19,10 @@ Readings where App. A is garbled or silent (all used consistently):
 * viscous terms are built as repeated first derivatives (gradients first,
   then the divergence of the viscous flux), as in the paper's form.
 
-Derivatives: the explicit member of Eq. (2) (alpha = 0) with the CD4
-parameters of App. B, a = 4/3, b = -1/3:
-    phi'_i = b (phi_{i+2} - phi_{i-2}) / (4 h) + a (phi_{i+1} - phi_{i-1}) / (2 h).
+Derivatives: the explicit member of Eq. (2) (alpha = 0),
+    phi'_i = b (phi_{i+2} - phi_{i-2}) / (4 h) + a (phi_{i+1} - phi_{i-1}) / (2 h),
+with the parameters of App. B: CD4 a = 4/3, b = -1/3 (order 4, the default)
+and CD2 a = 1, b = 0 (order 2, Table 1 cases 1-3).
 
 Arrays are (z, y, x) per variable, conserved state is (5, z, y, x).  The
 "extended" arrays used below carry an apron of depth H around the owned
@@ -33,6 +34,7 @@ import numpy as np
 
 CD4_A = 4.0 / 3.0
 CD4_B = -1.0 / 3.0
+CD2_A = 1.0
 
 EULER, NS = "euler", "ns"
 
@@ -81,6 +83,32 @@ def cd4(f, d, h):
     return out
 
 
+def cd2(f, d, h):
+    """CD2 derivative along direction d; the end point on each side is NaN."""
+    ax = 2 - d
+    n = f.shape[ax]
+    out = np.full(f.shape, np.nan)
+    if n < 3:
+        return out
+
+    def sl(a, b):
+        idx = [slice(None)] * 3
+        idx[ax] = slice(a, b)
+        return tuple(idx)
+
+    out[sl(1, n - 1)] = CD2_A * (f[sl(2, n)] - f[sl(0, n - 2)]) / (2.0 * h)
+    return out
+
+
+def derivative(order):
+    """The central difference of the given order (2 or 4)."""
+    if order == 4:
+        return cd4
+    if order == 2:
+        return cd2
+    raise ValueError("order must be 2 or 4")
+
+
 def primitives(E, gas):
     rho, mx, my, mz, et = E
     u = mx / rho
@@ -102,12 +130,15 @@ def inviscid_fluxes(E, gas):
     return out
 
 
-def rhs_extended(E, H, ndim, h, physics, gas):
+def rhs_extended(E, H, ndim, h, physics, gas, order=4):
     """RHS at the owned points of an extended block.
 
     E: (5, ez, ey, ex) with an apron of H on both sides of every active
     direction (z has no apron when ndim == 2).  Returns (5, bz, by, bx).
+    order: 4 (CD4) or 2 (CD2); the apron depth H is that of CD4 either way,
+    CD2 simply reaches less of it.
     """
+    cd = derivative(order)
     dims = [0, 1] if ndim == 2 else [0, 1, 2]
     own = [slice(None)] * 3            # (z, y, x) slices of the owned region
     for d in dims:
@@ -118,7 +149,7 @@ def rhs_extended(E, H, ndim, h, physics, gas):
     Fs = inviscid_fluxes(E, gas)
     for d in dims:
         for v in range(5):
-            R[v] -= cd4(Fs[d][v], d, h[d])[own]
+            R[v] -= cd(Fs[d][v], d, h[d])[own]
 
     if physics == NS:
         _, u, vv, w, p = primitives(E, gas)
@@ -127,9 +158,9 @@ def rhs_extended(E, H, ndim, h, physics, gas):
         vel = [u, vv, w]
         zero = np.zeros_like(u)
         # gradients du_i/dx_j (i = velocity component, j = direction) and dT/dx_j
-        g = [[cd4(vel[i], j, h[j]) if j in dims else zero for j in range(3)]
+        g = [[cd(vel[i], j, h[j]) if j in dims else zero for j in range(3)]
              for i in range(3)]
-        gT = [cd4(T, j, h[j]) if j in dims else zero for j in range(3)]
+        gT = [cd(T, j, h[j]) if j in dims else zero for j in range(3)]
         div = g[0][0] + g[1][1] + g[2][2]
         mu = gas.mu
         tau = [[mu * (g[i][j] + g[j][i]) - (2.0 / 3.0) * mu * div * (i == j)
@@ -140,7 +171,7 @@ def rhs_extended(E, H, ndim, h, physics, gas):
                   u * tau[d][0] + vv * tau[d][1] + w * tau[d][2]
                   + gas.kappa * gT[d]]
             for v in range(1, 5):
-                R[v] += cd4(Fv[v], d, h[d])[own] / gas.re
+                R[v] += cd(Fv[v], d, h[d])[own] / gas.re
     return R
 
 
@@ -151,7 +182,7 @@ def pad_periodic(U, H, ndim):
     return np.pad(U, pads, mode="wrap")
 
 
-def rhs_global(U, h, ndim, physics, gas):
+def rhs_global(U, h, ndim, physics, gas, order=4):
     """RHS of the whole periodic field as one block (synchronous view)."""
     H = halo_depth(physics)
-    return rhs_extended(pad_periodic(U, H, ndim), H, ndim, h, physics, gas)
+    return rhs_extended(pad_periodic(U, H, ndim), H, ndim, h, physics, gas, order)

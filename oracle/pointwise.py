@@ -6,11 +6,17 @@ Sec. 3, written with scalar loops so that it can be checked against
 check single sampled outputs of large runs.
 
 The CD4 derivative (Eq. 2 with a = 4/3, b = -1/3, alpha = 0) is written here
-in its expanded form  (phi_{i-2} - 8 phi_{i-1} + 8 phi_{i+1} - phi_{i+2}) / (12 h).
+in its expanded form  (phi_{i-2} - 8 phi_{i-1} + 8 phi_{i+1} - phi_{i+2}) / (12 h),
+and CD2 (a = 1, b = 0) as  (phi_{i+1} - phi_{i-1}) / (2 h).
 """
 import math
 
 CD4_W = ((-2, 1.0 / 12.0), (-1, -8.0 / 12.0), (1, 8.0 / 12.0), (2, -1.0 / 12.0))
+CD2_W = ((-1, -0.5), (1, 0.5))
+
+
+def weights(order):
+    return {4: CD4_W, 2: CD2_W}[order]
 
 UNIT = ((1, 0, 0), (0, 1, 0), (0, 0, 1))
 
@@ -37,12 +43,12 @@ def _inviscid(get, d, x, y, z, gas):
     return f
 
 
-def _gradients(get, x, y, z, h, dims, gas):
+def _gradients(get, x, y, z, h, dims, gas, order=4):
     """(du_i/dx_j, dT/dx_j) at one point."""
     gu = [[0.0] * 3 for _ in range(3)]
     gT = [0.0] * 3
     for j in dims:
-        for o, c in CD4_W:
+        for o, c in weights(order):
             e = UNIT[j]
             _, vel, _, T = _prim(get, x + o * e[0], y + o * e[1], z + o * e[2], gas)
             for i in range(3):
@@ -51,8 +57,8 @@ def _gradients(get, x, y, z, h, dims, gas):
     return gu, gT
 
 
-def _viscous(get, d, x, y, z, h, dims, gas):
-    gu, gT = _gradients(get, x, y, z, h, dims, gas)
+def _viscous(get, d, x, y, z, h, dims, gas, order=4):
+    gu, gT = _gradients(get, x, y, z, h, dims, gas, order)
     _, vel, _, _ = _prim(get, x, y, z, gas)
     divu = gu[0][0] + gu[1][1] + gu[2][2]
     tau = [[gas.mu * (gu[i][j] + gu[j][i]) - (2.0 / 3.0) * gas.mu * divu * (1.0 if i == j else 0.0)
@@ -62,22 +68,22 @@ def _viscous(get, d, x, y, z, h, dims, gas):
     return [0.0, tau[d][0], tau[d][1], tau[d][2], energy]
 
 
-def rhs_point(get, h, ndim, physics, gas):
+def rhs_point(get, h, ndim, physics, gas, order=4):
     """RHS (5 values) at local point (0, 0, 0); get(v, x, y, z) returns the
-    conserved variable v at the local offset (x, y, z)."""
+    conserved variable v at the local offset (x, y, z).  order: 4 (CD4) or 2."""
     dims = [0, 1] if ndim == 2 else [0, 1, 2]
     R = [0.0] * 5
     for d in dims:
         e = UNIT[d]
-        for o, c in CD4_W:
+        for o, c in weights(order):
             F = _inviscid(get, d, o * e[0], o * e[1], o * e[2], gas)
             for v in range(5):
                 R[v] -= c * F[v] / h[d]
     if physics == "ns":
         for d in dims:
             e = UNIT[d]
-            for o, c in CD4_W:
-                Fv = _viscous(get, d, o * e[0], o * e[1], o * e[2], h, dims, gas)
+            for o, c in weights(order):
+                Fv = _viscous(get, d, o * e[0], o * e[1], o * e[2], h, dims, gas, order)
                 for v in range(5):
                     R[v] += c * Fv[v] / h[d] / gas.re
     return R
@@ -135,6 +141,10 @@ def block_accessor(Y, history, n, origin, size, point, k=None, W=None, e=0,
     return get
 
 
-def modified_wavenumber(kappa, h):
-    """Exact CD4 response: D sin(kappa x) = kstar cos(kappa x)."""
+def modified_wavenumber(kappa, h, order=4):
+    """Exact response of the central difference: D sin(kappa x) =
+    kstar cos(kappa x), kstar = (8 sin(kappa h) - sin(2 kappa h)) / (6 h) for
+    CD4 and sin(kappa h) / h for CD2."""
+    if order == 2:
+        return math.sin(kappa * h) / h
     return (8.0 * math.sin(kappa * h) - math.sin(2.0 * kappa * h)) / (6.0 * h)

@@ -10,9 +10,11 @@ processing elements, PEs, of Sec. 3).  Every stage of every step:
           data, Table 1 cases 2 and 5);
     AT -- sum_l W[e][k][l] U^{n-k-l}, the AT buffer value of stage e
           (Eqs. 7-15; see ``at.py``);
-* the CD4 right-hand side is evaluated on the extended block
-  (``flow.rhs_extended``), and
-* the RK update of the owned points follows (classical RK4 or LSERK4, Eq. 3).
+* the CD4 (or, for the second-order method of Table 1 cases 1-3, CD2)
+  right-hand side is evaluated on the extended block (``flow.rhs_extended``),
+  and
+* the RK update of the owned points follows (classical RK4, LSERK4 or
+  LSERK2, Eq. 3).
 
 Halo geometry.  Euler needs faces of depth 2.  Navier-Stokes, with viscous
 terms built from repeated first derivatives, needs faces of depth 4 and the
@@ -55,7 +57,7 @@ def even_split(n, nb):
 class Config:
     def __init__(self, n, length, ndim=3, nblk=(1, 1, 1), physics="euler",
                  gamma=1.4, mach=0.1, re=1600.0, pr=0.71, rk="rk4", mode="sa",
-                 algo="caa", L=1, seed=0, C=atmod.AT4_C, dt=None, split=None):
+                 algo="caa", L=1, seed=0, C=atmod.AT4_C, dt=None, split=None, order=4):
         self.n = tuple(n)
         self.length = tuple(length)
         self.ndim = ndim
@@ -68,6 +70,7 @@ class Config:
         self.L = L
         self.seed = seed
         self.C = C
+        self.order = order          # central-difference order, 4 or 2
         self.dt = dt
         self.split = split or [even_split(self.n[d], self.nblk[d]) for d in range(3)]
         self.h = tuple(self.length[d] / self.n[d] for d in range(3))
@@ -260,7 +263,7 @@ class Oracle:
         R = np.empty_like(Y)
         for b in range(len(self.blocks)):
             E = self._extended(b, Y, e, k, bufs)
-            Rb = flow.rhs_extended(E, cfg.H, cfg.ndim, cfg.h, cfg.physics, cfg.gas)
+            Rb = flow.rhs_extended(E, cfg.H, cfg.ndim, cfg.h, cfg.physics, cfg.gas, cfg.order)
             bx, by, bz = self.blocks.sizes[b]
             R[(slice(None),) + self.blocks.global_index(
                 b, [np.arange(bx), np.arange(by), np.arange(bz)])] = Rb

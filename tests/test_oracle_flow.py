@@ -40,6 +40,39 @@ def test_cd4_fourth_order():
     assert min(orders) > 3.8
 
 
+def test_cd2_modified_wavenumber_exact():
+    # CD2 (App. B: a = 1, b = 0) maps sin(kx) to (sin(kh)/h) cos(kx) exactly
+    n, L = 32, 2 * math.pi
+    h = L / n
+    x = np.arange(n) * h
+    for kap in (1, 3, 7):
+        f = np.sin(kap * x)[None, None, :]
+        fp = np.pad(f, ((0, 0), (0, 0), (2, 2)), mode="wrap")
+        d = flow.cd2(fp, 0, h)[:, :, 2:-2]
+        assert np.allclose(d[0, 0], math.sin(kap * h) / h * np.cos(kap * x), atol=1e-13)
+
+
+def test_cd2_second_order_and_exact_for_quadratics():
+    errs = []
+    for n in (32, 64, 128):
+        h = 1.0 / n
+        x = np.arange(n) * h
+        f = np.exp(np.sin(2 * math.pi * x))
+        fp = np.pad(f[None, None, :], ((0, 0), (0, 0), (1, 1)), mode="wrap")
+        d = flow.cd2(fp, 0, h)[0, 0, 1:-1]
+        exact = 2 * math.pi * np.cos(2 * math.pi * x) * f
+        errs.append(np.abs(d - exact).max())
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert 1.9 < min(orders) and max(orders) < 2.1, orders
+    # a quadratic along y (no wrap needed inside the array): exact derivative
+    y = np.linspace(-1.0, 2.0, 9)
+    h = y[1] - y[0]
+    q = (3.0 * y * y - 2.0 * y + 0.5)[None, :, None] * np.ones((2, 1, 3))
+    d = flow.cd2(q, 1, h)[:, 1:-1, :]
+    assert np.allclose(d, (6.0 * y - 2.0)[None, 1:-1, None], atol=1e-12)
+    assert np.isnan(flow.cd2(q, 1, h)[:, 0, :]).all()
+
+
 # ------------------------------------------------------- NS closed forms
 def _rhs(U, n, length, physics, gas, ndim=3):
     h = inputs.spacing(n, length)
@@ -137,17 +170,18 @@ def test_rhs_rotation_covariance():
 
 
 # ------------------------------------------------------ brute force pins
+@pytest.mark.parametrize("order", [4, 2])
 @pytest.mark.parametrize("physics", [flow.EULER, flow.NS])
-def test_vectorized_rhs_matches_pointwise_sync(physics):
+def test_vectorized_rhs_matches_pointwise_sync(physics, order):
     n = (10, 10, 10) if physics == flow.EULER else (12, 12, 12)
     U = inputs.smooth_random_state(n, L3, seed=7)
     h = inputs.spacing(n, L3)
-    R = _rhs(U, n, L3, physics, GAS)
+    R = flow.rhs_global(U, h, 3, physics, GAS, order)
     rng = np.random.default_rng(0)
     pts = rng.integers(0, n[0], size=(25, 3))
     for x, y, z in pts:
         get = pointwise.block_accessor(U, None, 0, (x, y, z), n, (0, 0, 0))
-        r = pointwise.rhs_point(get, h, 3, physics, GAS)
+        r = pointwise.rhs_point(get, h, 3, physics, GAS, order)
         assert np.allclose(r, R[:, z, y, x], rtol=1e-11, atol=1e-11 * np.abs(R).max())
 
 

@@ -7,18 +7,20 @@ import numpy as np
 import pytest
 
 from oracle import at as atmod, delays as dl, diagnostics, flow, pointwise, rk, solver
+from conftest import read_golden
 from paper_2506_03027_amd import inputs
 
 
 def vortex_run(N, mode, nblk=(2, 2, 1), algo="caa", L=4, T=0.5, rkname="rk4",
-               seed=1, split=None, halo="closed", dt_scale=1.0):
+               seed=1, split=None, halo="closed", dt_scale=1.0, order=4, C=5):
     n, length = (N, N, 1), (10.0, 10.0, 1.0)
     U0 = inputs.vortex_state(n, length, 2)
     # dt proportional to h, fixed by the N = 32 value at CFL ~ 0.3
     dt32 = 0.3 * (10.0 / 32) / (0.5 * math.sqrt(1.4) * math.sqrt(2) + math.sqrt(1.4)) / 2
     nsteps = int(round(T / (dt_scale * dt32 * 32 / N)))
     cfg = solver.Config(n, length, ndim=2, nblk=nblk, physics="euler", rk=rkname,
-                        mode=mode, algo=algo, L=L, seed=seed, dt=T / nsteps, split=split)
+                        mode=mode, algo=algo, L=L, seed=seed, dt=T / nsteps, split=split,
+                        order=order, C=C)
     o = solver.Oracle(cfg)
     o.halo = halo
     o.set_state(U0)
@@ -68,6 +70,24 @@ def test_table1_orders_sa_at_as(rkname):
     _, o_saa = _orders("at", rkname=rkname, algo="saa", L=3, seed=7, dt_scale=0.25)
     _, o_as = _orders("as", rkname=rkname, algo="caa", L=4)
     assert o_sa[-1] > 3.7 and o_at[-1] > 3.7 and o_saa[-1] > 3.7, (o_sa, o_at, o_saa)
+    assert 0.7 < o_as[-1] < 1.3, o_as
+
+
+@pytest.mark.slow
+def test_table1_orders_second_order_method():
+    # Table 1 cases 1, 3 and 2: LSERK2 with CD2 in the interior and AT2 (three
+    # delayed levels) at block boundaries keeps second order under CAA and
+    # SAA delays; standard CD2 on stale data (AS) drops to first order.  The
+    # expected orders are those of the golden table.
+    expect = {(r[1], r[2]): int(r[-1]) for r in read_golden("table1_orders.txt")}
+    kw = dict(rkname="lserk2", order=2, C=3, dt_scale=0.5)
+    _, o_sa = _orders("sa", **kw)
+    _, o_at = _orders("at", algo="caa", L=4, **kw)
+    _, o_saa = _orders("at", algo="saa", L=3, seed=7, **kw)
+    _, o_as = _orders("as", algo="caa", L=4, **kw)
+    print("orders SA", o_sa, "CAA-AT", o_at, "SAA-AT", o_saa, "AS", o_as)
+    assert expect[("SA", "lserk2")] == 2 and expect[("AT", "lserk2")] == 2 and expect[("AS", "lserk2")] == 1
+    assert 1.8 < o_sa[-1] < 2.3 and 1.8 < o_at[-1] < 2.3 and 1.8 < o_saa[-1] < 2.3, (o_sa, o_at, o_saa)
     assert 0.7 < o_as[-1] < 1.3, o_as
 
 
@@ -128,14 +148,16 @@ def test_literal_buffer_recursion_equals_closed_form():
 
 
 @pytest.mark.parametrize("physics", ["euler", "ns"])
-@pytest.mark.parametrize("mode", ["at", "as"])
-def test_stage_rhs_matches_pointwise_halo_rule(physics, mode):
+@pytest.mark.parametrize("mode,rkname", [("at", "rk4"), ("as", "rk4"), ("at", "lserk2")])
+def test_stage_rhs_matches_pointwise_halo_rule(physics, mode, rkname):
     # Brute force: classify every stencil point of every owned point into
     # owned / halo slot and evaluate the halo value from the full-field history.
+    # lserk2 runs the second-order method: CD2 and AT2 (three levels).
+    order, C = (2, atmod.AT2_C) if rkname == "lserk2" else (4, atmod.AT4_C)
     n, length = (12, 12, 8), (6.0, 6.0, 4.0)
-    cfg = solver.Config(n, length, 3, (3, 2, 2), physics, mode=mode, algo="saa",
+    cfg = solver.Config(n, length, 3, (3, 2, 2), physics, rk=rkname, mode=mode, algo="saa",
                         L=4, seed=9, re=50.0, mach=0.3, dt=1e-3,
-                        split=[[4, 4, 4], [5, 7], [4, 4]])
+                        split=[[4, 4, 4], [5, 7], [4, 4]], order=order, C=C)
     o = solver.Oracle(cfg)
     nstep = 8
     hist = {}
@@ -147,7 +169,7 @@ def test_stage_rhs_matches_pointwise_halo_rule(physics, mode):
     Y = inputs.smooth_random_state(n, length, seed=1)
     W = o.W if mode == "at" else None
     rng = np.random.default_rng(2)
-    for e in (0, 2):
+    for e in ((0, 1) if rkname == "lserk2" else (0, 2)):
         R = o.rhs(Y, e, k)
         for b in range(len(o.blocks)):
             size = o.blocks.sizes[b]
@@ -158,7 +180,7 @@ def test_stage_rhs_matches_pointwise_halo_rule(physics, mode):
             for p in cand:
                 get = pointwise.block_accessor(Y, hist, nstep, org, size, p, k=k[b],
                                                W=W, e=e, C=cfg.C, mode=mode)
-                r = pointwise.rhs_point(get, cfg.h, 3, physics, cfg.gas)
+                r = pointwise.rhs_point(get, cfg.h, 3, physics, cfg.gas, order)
                 g = [(org[d] + p[d]) % n[d] for d in range(3)]
                 ref = R[:, g[2], g[1], g[0]]
                 assert np.allclose(r, ref, rtol=1e-9, atol=1e-9 * np.abs(R).max()), (e, b, p)
