@@ -5,7 +5,8 @@
  * The library advances the compressible Euler / Navier-Stokes equations
  * (Sec. 2, Eq. 1 and App. A of arXiv 2506.03027) on a uniform periodic
  * Cartesian grid with the explicit fourth-order central difference (Eq. 2,
- * CD4 of App. B).  The grid is split into a tensor product of blocks -- the
+ * CD4 of App. B), or, for the second-order method of Table 1 cases 1-3
+ * (rk = ATNS_LSERK2), with CD2 and the AT2 schemes.  The grid is split into a tensor product of blocks -- the
  * processing elements (PEs) of Sec. 3 -- that all live on one GPU.  Each
  * block reads the points it does not own (its halo, the "buffer points" of
  * Sec. 3) either synchronously (SA, Alg. 1) or from a ring of delayed time
@@ -70,7 +71,7 @@ typedef enum {
 } atns_status;
 
 enum { ATNS_EULER = 0, ATNS_NS = 1 };                 /* physics          */
-enum { ATNS_RK4 = 0, ATNS_LSERK4 = 1 };               /* time integrator  */
+enum { ATNS_RK4 = 0, ATNS_LSERK4 = 1, ATNS_LSERK2 = 2 }; /* time integrator */
 enum { ATNS_SA = 0, ATNS_AS = 1, ATNS_AT = 2 };       /* halo treatment   */
 enum { ATNS_CAA = 0, ATNS_SAA = 1 };                  /* delay algorithm  */
 enum { ATNS_F32 = 0, ATNS_F64 = 1 };                  /* state precision  */
@@ -87,7 +88,14 @@ typedef struct {
   double gamma, mach, re, pr; /* gas: p = (gamma-1)(rho E - rho|u|^2/2),
                               T = gamma M^2 p / rho, mu = 1,
                               kappa = 1/((gamma-1) M^2 Pr); re, pr NS only    */
-  int32_t rk;            /* ATNS_RK4 | ATNS_LSERK4 (Eq. 3, Table 4)           */
+  int32_t rk;            /* ATNS_RK4 | ATNS_LSERK4 (Eq. 3, Table 4): CD4 and
+                            AT4 (C = 5 delayed levels).  ATNS_LSERK2 (App. B,
+                            A = {0, -1/2}, B = {1/2, 1}): the second-order
+                            method of Table 1 cases 1-3, CD2 (App. B, a = 1,
+                            b = 0) in the interior and AT2 (C = 3 levels,
+                            Eq. 14 and App. C) at block boundaries; the halo
+                            depth stays that of CD4 (the outer layer is read
+                            with weight 0).  The learned halo needs C = 5.   */
   int32_t mode;          /* ATNS_SA | ATNS_AS | ATNS_AT                       */
   int32_t algo;          /* ATNS_CAA | ATNS_SAA                               */
   int32_t L;             /* delay bound: delays are 0..L-1 (Alg. 2, 3)        */
@@ -103,7 +111,8 @@ const char* atns_version(void);
  * not summing to n, L < 1 or L > 16, unknown enums, ndim == 2 with nz != 1)
  * before any device call.  stream: a hipStream_t, or NULL.  On success *out
  * owns all device buffers: state and RK registers, the delayed-level ring
- * (C + L levels of each block's boundary layers, C = 5 for AT4) and tables. */
+ * (C + L levels of each block's boundary layers, C = 5 for AT4, 3 for AT2)
+ * and tables. */
 atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out);
 
 /* Free every resource of the context.  NULL is accepted. */
@@ -279,17 +288,19 @@ atns_status atns_hbm_probe(const void* dev_src, void* dev_dst, int64_t bytes, vo
 
 /* ---- host-only helpers (no device needed) -------------------------------
  * The FP64 per-stage halo weight table the kernels use: out[e][k][l] for
- * stages e < s (s = 4 for RK4, 5 for LSERK4), delays k < L and levels
- * l < C (C = 5).  AT: the AT4 buffer extrapolation (stage 0, Eq. 15) and
- * the RK-consistent buffer updates (Eqs. 8-13) in closed form; AS: 1 at
- * l = 0.  out must hold s*L*C doubles. */
+ * stages e < s (s = 4 for RK4, 5 for LSERK4, 2 for LSERK2), delays k < L
+ * and levels l < C (C = 5, or 3 for LSERK2).  AT: the buffer extrapolation
+ * (stage 0, Eqs. 14-15) and the RK-consistent buffer updates (Eqs. 8-13,
+ * App. C) in closed form; AS: 1 at l = 0.  out must hold s*L*C doubles. */
 atns_status atns_host_weights(int32_t rk, int32_t mode, int32_t L, double* out);
 
 /* The delays step n would draw (after the guard), without a device, into
- * out[nblocks][ATNS_NSLOTS]; *synchronous = 1 (and zeros) when n < C.
- * CAA: k = (n - C) mod L everywhere.  SAA: SplitMix64 draw number
- * (n*nblocks + b)*ATNS_NSLOTS + v of stream `seed`, modulo L. */
-atns_status atns_host_delays(int32_t algo, int64_t n, int32_t nblocks, int32_t L,
+ * out[nblocks][ATNS_NSLOTS]; *synchronous = 1 (and zeros) when n < C, C the
+ * level count of scheme rk (5, or 3 for ATNS_LSERK2).  CAA: k = (n - C) mod
+ * L everywhere.  SAA: SplitMix64 draw number (n*nblocks + b)*ATNS_NSLOTS + v
+ * of stream `seed`, modulo L.  Then the guard of Alg. 3: k = 0 where
+ * k > n - C + 1. */
+atns_status atns_host_delays(int32_t algo, int32_t rk, int64_t n, int32_t nblocks, int32_t L,
                              uint64_t seed, int8_t* out, int32_t* synchronous);
 
 /* ---- batches --------------------------------------------------------------

@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libatns.so")
 
 EULER, NS = 0, 1
-RK4, LSERK4 = 0, 1
+RK4, LSERK4, LSERK2 = 0, 1, 2
 SA, AS, AT = 0, 1, 2
 CAA, SAA = 0, 1
 F32, F64 = 0, 1
@@ -22,6 +22,16 @@ CASE_VORTEX, CASE_TGV = 0, 1
 NSLOTS = 18
 NDIAG = 7
 C_LEVELS = 5
+
+
+def levels(rk):
+    """Delayed levels C of the AT scheme paired with integrator rk: 5 (AT4)
+    for RK4 and LSERK4, 3 (AT2) for LSERK2."""
+    return 3 if rk == LSERK2 else 5
+
+
+def stages(rk):
+    return {RK4: 4, LSERK4: 5, LSERK2: 2}[rk]
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE"}
 
@@ -94,7 +104,7 @@ def lib():
             "atns_mlp_enable": ([vp, i32, dbl], i32),
             "atns_mlp_stats": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
             "atns_host_weights": ([i32, i32, i32, vp], i32),
-            "atns_host_delays": ([i32, i64, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(i32)], i32),
+            "atns_host_delays": ([i32, i32, i64, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(i32)], i32),
             "atns_batch_create": ([ctypes.POINTER(Config), i32, vp, ctypes.POINTER(vp)], i32),
             "atns_batch_destroy": ([vp], i32),
             "atns_batch_last_error": ([vp], ctypes.c_char_p),
@@ -127,16 +137,15 @@ def hbm_probe(src, dst, nbytes, stream=None):
 
 
 def host_weights(rk, mode, L):
-    s = 4 if rk == RK4 else 5
-    out = np.zeros((s, L, C_LEVELS), dtype=np.float64)
+    out = np.zeros((stages(rk), L, levels(rk)), dtype=np.float64)
     _check(lib().atns_host_weights(rk, mode, L, out.ctypes.data))
     return out
 
 
-def host_delays(algo, n, nblocks, L, seed):
+def host_delays(algo, n, nblocks, L, seed, rk=RK4):
     out = np.zeros((nblocks, NSLOTS), dtype=np.int8)
     sync = ctypes.c_int32(0)
-    _check(lib().atns_host_delays(algo, n, nblocks, L, ctypes.c_uint64(seed), out.ctypes.data,
+    _check(lib().atns_host_delays(algo, rk, n, nblocks, L, ctypes.c_uint64(seed), out.ctypes.data,
                                   ctypes.byref(sync)))
     return out, bool(sync.value)
 

@@ -25,6 +25,7 @@ struct atns_ctx {
   double h[3] = {1, 1, 1};
   int H = 2;
   RKScheme rk{};
+  int C = 5;                         // delayed levels of the AT scheme
   int nb = 0;
   std::vector<BlockDev> blocks;
   std::vector<TileDev> tiles;
@@ -127,7 +128,8 @@ atns_status validate(const atns_config* cfg, std::vector<int> split[3], atns_ctx
   if (!cfg) return fail(c, ATNS_EINVAL, "null config");
   if (cfg->ndim != 2 && cfg->ndim != 3) return fail(c, ATNS_EINVAL, "ndim must be 2 or 3");
   if (cfg->physics != ATNS_EULER && cfg->physics != ATNS_NS) return fail(c, ATNS_EINVAL, "bad physics");
-  if (cfg->rk != ATNS_RK4 && cfg->rk != ATNS_LSERK4) return fail(c, ATNS_EINVAL, "bad rk");
+  if (cfg->rk != ATNS_RK4 && cfg->rk != ATNS_LSERK4 && cfg->rk != ATNS_LSERK2)
+    return fail(c, ATNS_EINVAL, "bad rk");
   if (cfg->mode != ATNS_SA && cfg->mode != ATNS_AS && cfg->mode != ATNS_AT)
     return fail(c, ATNS_EINVAL, "bad mode");
   if (cfg->algo != ATNS_CAA && cfg->algo != ATNS_SAA) return fail(c, ATNS_EINVAL, "bad algo");
@@ -339,12 +341,14 @@ StageParams<T> base_params(const atns_ctx* c) {
   p.tiles = c->d_tiles;
   for (int d = 0; d < 3; ++d) {
     p.n[d] = c->n[d];
-    p.inv12h[d] = 1.0 / (12.0 * c->h[d]);
+    p.dscale[d] = c->cfg.rk == ATNS_LSERK2 ? 1.0 / (2.0 * c->h[d]) : 1.0 / (12.0 * c->h[d]);
   }
   p.field = c->field;
   p.slot_stride = c->slot_stride;
   p.D = c->D;
   p.L = c->cfg.L;
+  p.C = c->C;
+  p.cd2 = c->cfg.rk == ATNS_LSERK2 ? 1 : 0;
   p.H = c->H;
   p.ndim = c->cfg.ndim;
   p.gamma = c->cfg.gamma;
@@ -384,13 +388,13 @@ hipError_t launch_stage(atns_ctx* c, const StageParams<T>& p, int kind) {
   return r;
 }
 
-bool is_async(const atns_ctx* c, int64_t step) { return c->cfg.mode != ATNS_SA && step >= kC; }
+bool is_async(const atns_ctx* c, int64_t step) { return c->cfg.mode != ATNS_SA && step >= c->C; }
 
 atns_status draw_delays(atns_ctx* c, int64_t step, int8_t* dst) {
   const int8_t* inj = nullptr;
   if (c->inject_n > 0 && step >= c->inject0 && step < c->inject0 + c->inject_n)
     inj = c->d_inject + (size_t)(step - c->inject0) * c->nb * kNumSlots;
-  HIP_TRY(c, launch_delays(dst, inj, step, c->nb, c->cfg.L, c->cfg.seed, c->cfg.algo, c->stream));
+  HIP_TRY(c, launch_delays(dst, inj, step, c->nb, c->cfg.L, c->C, c->cfg.seed, c->cfg.algo, c->stream));
   return ATNS_OK;
 }
 
@@ -683,6 +687,7 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
   c->stream = (hipStream_t)stream;
   c->H = cfg->physics == ATNS_NS ? 4 : 2;
   c->rk = make_rk(cfg->rk);
+  c->C = levels(cfg->rk);
   c->esz = cfg->precision == ATNS_F64 ? 8 : 4;
   c->field = (long long)c->n[0] * c->n[1] * c->n[2];
   build_layout(c);
@@ -690,7 +695,7 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
   build_tiles(c, c->tile[0], c->tile[1], c->tile[2]);
   // SA keeps a delayed-level ring only when L > 1 (history for the learned
   // halo's training samples); the asynchronous modes always do.
-  c->D = (cfg->mode == ATNS_SA && cfg->L <= 1) ? 0 : kC + cfg->L;
+  c->D = (cfg->mode == ATNS_SA && cfg->L <= 1) ? 0 : c->C + cfg->L;
 
   auto fail_free = [&](atns_status s, const std::string& m) {
     release(c);
@@ -718,8 +723,8 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
       return fail_free(ATNS_ENOMEM, "halo buffer allocation failed");
     {
       const std::vector<double> W0 = halo_weights(cfg->rk, ATNS_AT, cfg->L);   // stage 0 = first L*C entries
-      if (hipMalloc((void**)&c->d_W0at, (size_t)cfg->L * kC * sizeof(double)) != hipSuccess ||
-          hipMemcpy(c->d_W0at, W0.data(), (size_t)cfg->L * kC * sizeof(double), hipMemcpyHostToDevice) !=
+      if (hipMalloc((void**)&c->d_W0at, (size_t)cfg->L * c->C * sizeof(double)) != hipSuccess ||
+          hipMemcpy(c->d_W0at, W0.data(), (size_t)cfg->L * c->C * sizeof(double), hipMemcpyHostToDevice) !=
               hipSuccess)
         return fail_free(ATNS_EHIP, "weight table upload failed");
       if (hipMalloc((void**)&c->d_faceinfo, c->faceinfo.size() * sizeof(FaceInfo)) != hipSuccess ||
@@ -1281,7 +1286,8 @@ atns_status mlp_need(atns_ctx* c) {
 atns_status sample_into(atns_ctx* c, int n, uint64_t seed, float* X, float* Y) {
   if (!c->ring) return fail(c, ATNS_ESTATE, "no delayed-level history (SA with L = 1)");
   if (c->face_regions.empty()) return fail(c, ATNS_ESTATE, "no face halos");
-  if (c->step < kC + c->cfg.L - 1) return fail(c, ATNS_ESTATE, "history shorter than C + L - 1 levels");
+  if (c->C != kMaxC) return fail(c, ATNS_EINVAL, "the learned halo works with AT4 (C = 5 levels)");
+  if (c->step < c->C + c->cfg.L - 1) return fail(c, ATNS_ESTATE, "history shorter than C + L - 1 levels");
   if (c->esz == 4) {
     MlpFeatArgs<float> fa = feat_args<float>(c);
     HIP_TRY(c, mlp_sample<float>(fa, c->d_regions, c->d_faceinfo, c->d_face_regions, (int)c->face_regions.size(),
@@ -1391,6 +1397,7 @@ atns_status atns_mlp_enable(atns_ctx* c, int32_t on, double tau) {
   if (!c) return fail(c, ATNS_EINVAL, "null context");
   if (on && !c->mlp_ready) return fail(c, ATNS_ESTATE, "MLP parameters not set");
   if (on && c->cfg.mode != ATNS_AT) return fail(c, ATNS_EINVAL, "the learned halo needs mode ATNS_AT");
+  if (on && c->C != kMaxC) return fail(c, ATNS_EINVAL, "the learned halo works with AT4 (C = 5 levels)");
   if (!(tau >= 0)) return fail(c, ATNS_EINVAL, "tau must be non-negative");
   c->mlp_on = on != 0;
   c->mlp_tau = tau;
@@ -1422,18 +1429,20 @@ atns_status atns_hbm_probe(const void* dev_src, void* dev_dst, int64_t bytes, vo
 }
 
 atns_status atns_host_weights(int32_t rk, int32_t mode, int32_t L, double* out) {
-  if (!out || L < 1 || L > 16 || (rk != ATNS_RK4 && rk != ATNS_LSERK4) || (mode != ATNS_AT && mode != ATNS_AS))
+  if (!out || L < 1 || L > 16 || (rk != ATNS_RK4 && rk != ATNS_LSERK4 && rk != ATNS_LSERK2) ||
+      (mode != ATNS_AT && mode != ATNS_AS))
     return fail(nullptr, ATNS_EINVAL, "bad weight-table request");
   const std::vector<double> W = halo_weights(rk, mode, L);
   std::memcpy(out, W.data(), W.size() * sizeof(double));
   return ATNS_OK;
 }
 
-atns_status atns_host_delays(int32_t algo, int64_t n, int32_t nblocks, int32_t L, uint64_t seed, int8_t* out,
-                             int32_t* synchronous) {
-  if (!out || nblocks < 1 || L < 1 || L > 16 || (algo != ATNS_CAA && algo != ATNS_SAA) || n < 0)
+atns_status atns_host_delays(int32_t algo, int32_t rk, int64_t n, int32_t nblocks, int32_t L, uint64_t seed,
+                             int8_t* out, int32_t* synchronous) {
+  if (!out || nblocks < 1 || L < 1 || L > 16 || (algo != ATNS_CAA && algo != ATNS_SAA) || n < 0 ||
+      (rk != ATNS_RK4 && rk != ATNS_LSERK4 && rk != ATNS_LSERK2))
     return fail(nullptr, ATNS_EINVAL, "bad delay request");
-  const bool async = step_delays(algo, n, nblocks, L, seed, nullptr, out);
+  const bool async = step_delays(algo, n, nblocks, L, levels(rk), seed, nullptr, out);
   if (synchronous) *synchronous = async ? 0 : 1;
   return ATNS_OK;
 }
@@ -1592,7 +1601,7 @@ atns_status batch_steps(atns_batch* b, int nsteps) {
   atns_status st = ATNS_OK;
   for (int it = 0; it < nsteps && st == ATNS_OK; ++it) {
     const int64_t step = b->m[0]->step;
-    bool eager = step < kC;
+    bool eager = step < kMaxC;   // members use RK4 (C = 5)
     for (atns_ctx* c : b->m) {
       if (c->step != step) return bfail(b, ATNS_ESTATE, "members are not at the same step");
       if (!c->state_set || !(c->dt > 0)) return bfail(b, ATNS_ESTATE, "member state or dt not set");

@@ -22,9 +22,19 @@
 
 namespace atns {
 
+int levels(int rk) { return rk == ATNS_LSERK2 ? 3 : 5; }
+
 RKScheme make_rk(int rk) {
   RKScheme s{};
-  if (rk == ATNS_RK4) {
+  if (rk == ATNS_LSERK2) {
+    // Two-stage LSERK2, App. B: A = {0, -1/2}, B = {1/2, 1}
+    s.stages = 2;
+    s.low_storage = true;
+    s.A[0] = 0.0;
+    s.A[1] = -0.5;
+    s.B[0] = 0.5;
+    s.B[1] = 1.0;
+  } else if (rk == ATNS_RK4) {
     s.stages = 4;
     s.low_storage = false;
     s.a[1][0] = 0.5;
@@ -96,12 +106,13 @@ std::vector<Poly> stage_polys(int rk) {
   return out;
 }
 
-// d^j/dtau^j of the Lagrange basis polynomial of level l, at tau = 0.
-long double basis_derivative(int k, int l, int j) {
+// d^j/dtau^j of the Lagrange basis polynomial of level l (of C levels), at
+// tau = 0.
+long double basis_derivative(int k, int l, int j, int C) {
   Poly p{1.0L};
   long double denom = 1.0L;
   const long double tl = -(long double)(k + l);
-  for (int m = 0; m < kC; ++m) {
+  for (int m = 0; m < C; ++m) {
     if (m == l) continue;
     const long double tm = -(long double)(k + m);
     p = mul(p, Poly{-tm, 1.0L});
@@ -117,19 +128,20 @@ long double basis_derivative(int k, int l, int j) {
 
 std::vector<double> halo_weights(int rk, int mode, int L) {
   const int s = make_rk(rk).stages;
-  std::vector<double> W((size_t)s * L * kC, 0.0);
+  const int C = levels(rk);
+  std::vector<double> W((size_t)s * L * C, 0.0);
   const std::vector<Poly> nu = stage_polys(rk);
   for (int e = 0; e < s; ++e)
     for (int k = 0; k < L; ++k)
-      for (int l = 0; l < kC; ++l) {
+      for (int l = 0; l < C; ++l) {
         long double w = 0.0L;
         if (mode == ATNS_AT) {
-          for (int j = 0; j < (int)nu[e].size() && j < kC; ++j)
-            w += nu[e][j] * basis_derivative(k, l, j);
+          for (int j = 0; j < (int)nu[e].size() && j < C; ++j)
+            w += nu[e][j] * basis_derivative(k, l, j, C);
         } else {
           w = (l == 0) ? 1.0L : 0.0L;
         }
-        W[((size_t)e * L + k) * kC + l] = (double)w;
+        W[((size_t)e * L + k) * C + l] = (double)w;
       }
   return W;
 }
@@ -143,10 +155,10 @@ uint64_t splitmix64(uint64_t seed, uint64_t i) {
   return z ^ (z >> 31);
 }
 
-bool step_delays(int algo, int64_t n, int nblocks, int L, uint64_t seed,
+bool step_delays(int algo, int64_t n, int nblocks, int L, int C, uint64_t seed,
                  const int8_t* override_k, int8_t* out) {
   const size_t cnt = (size_t)nblocks * kSlots;
-  if (n < kC) {  // Alg. 2/3: the first C steps are synchronous
+  if (n < C) {  // Alg. 2/3: the first C steps are synchronous
     std::memset(out, 0, cnt);
     return false;
   }
@@ -157,13 +169,13 @@ bool step_delays(int algo, int64_t n, int nblocks, int L, uint64_t seed,
       if (override_k) {
         k = override_k[idx];
       } else if (algo == ATNS_CAA) {
-        k = (n - kC) % L;  // period-L refresh, delay 0 right after it
+        k = (n - C) % L;  // period-L refresh, delay 0 right after it
       } else {
         const uint64_t draw = ((uint64_t)n * (uint64_t)nblocks + (uint64_t)b) * kSlots + v;
         k = (int64_t)(splitmix64(seed, draw) % (uint64_t)L);
       }
       // Alg. 3 guard: too stale, or levels not (yet) available -> wait, k = 0
-      if (k < 0 || k > L - 1 || k > n - kC + 1) k = 0;
+      if (k < 0 || k > L - 1 || k > n - C + 1) k = 0;
       out[idx] = (int8_t)k;
     }
   return true;

@@ -6,8 +6,13 @@
 
 namespace atns {
 
-constexpr int kC = 5;          // AT4: C = 5 delayed levels, (d, q, r) = (1, 4, 1)
+constexpr int kMaxC = 5;       // most delayed levels of any scheme (AT4)
 constexpr int kSlots = 18;     // 6 faces + 12 edges
+
+// Delayed levels C of the AT scheme paired with an integrator: AT4,
+// (d, q, r) = (1, 4, 1), C = 5 with RK4 and LSERK4; AT2, (1, 2, 1), C = 3
+// with LSERK2 (Table 1).
+int levels(int rk);
 
 struct RKScheme {
   int stages;                  // s
@@ -20,17 +25,18 @@ struct RKScheme {
   bool low_storage;
 };
 
-RKScheme make_rk(int rk);      // rk: ATNS_RK4 or ATNS_LSERK4
+RKScheme make_rk(int rk);      // rk: ATNS_RK4, ATNS_LSERK4 or ATNS_LSERK2
 
-// W[e][k][l], e < s, k < L, l < kC.  mode: ATNS_AT or ATNS_AS.
+// W[e][k][l], e < s, k < L, l < C = levels(rk).  mode: ATNS_AT or ATNS_AS.
 std::vector<double> halo_weights(int rk, int mode, int L);
 
 // SplitMix64 draw i of stream `seed`.
 uint64_t splitmix64(uint64_t seed, uint64_t i);
 
-// Delays of step n after the Alg. 3 guard (override may be null).
-// Returns false (and zeros) for a synchronous step (n < kC).
-bool step_delays(int algo, int64_t n, int nblocks, int L, uint64_t seed,
+// Delays of step n after the Alg. 3 guard (override may be null), for a
+// scheme with C delayed levels.  Returns false (and zeros) for a synchronous
+// step (n < C).
+bool step_delays(int algo, int64_t n, int nblocks, int L, int C, uint64_t seed,
                  const int8_t* override_k, int8_t* out);
 
 }  // namespace atns

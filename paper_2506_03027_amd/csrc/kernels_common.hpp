@@ -7,7 +7,7 @@
 
 namespace atns {
 
-constexpr int kLevels = 5;  // AT4: C = 5
+constexpr int kLevels = 5;  // AT4: C = 5 (the learned halo works on AT4)
 
 // Workgroup barrier that orders LDS only: finish this wave's LDS operations,
 // then meet at s_barrier.  Unlike __syncthreads() it does not wait for
@@ -29,7 +29,7 @@ __device__ __forceinline__ StageParams<T> resolve_step(const StageParams<T>& p) 
   if (p.nstep) {
     const long long n = *p.nstep;
     q.slot_now = p.D ? (int)(n % p.D) : 0;
-    q.halo = (n >= kLevels) ? p.async_halo : kHaloSync;
+    q.halo = (n >= p.C) ? p.async_halo : kHaloSync;
   }
   return q;
 }

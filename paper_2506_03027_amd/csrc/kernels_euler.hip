@@ -61,7 +61,9 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
   const int lx = t.x0 + tx, ly = t.y0 + ty;
   const bool three = (p.ndim == 3);
   const T gm1 = (T)(p.gamma - 1.0);
-  const T ihx = (T)p.inv12h[0], ihy = (T)p.inv12h[1], ihz = (T)p.inv12h[2];
+  const T ihx = (T)p.dscale[0], ihy = (T)p.dscale[1], ihz = (T)p.dscale[2];
+  // central-difference weights of the inner and outer neighbour pairs
+  const T w1 = p.cd2 ? T(1) : T(8), w2 = p.cd2 ? T(0) : T(1);
 
   __shared__ T sF[2][5][TY][TX + 4];
   __shared__ T sG[2][5][TY + 4][TX];
@@ -153,10 +155,10 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
       T R[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        const T dx = (T(8) * (sF[buf][v][ty][tx + 3] - sF[buf][v][ty][tx + 1]) -
-                      (sF[buf][v][ty][tx + 4] - sF[buf][v][ty][tx])) * ihx;
-        const T dy = (T(8) * (sG[buf][v][ty + 3][tx] - sG[buf][v][ty + 1][tx]) -
-                      (sG[buf][v][ty + 4][tx] - sG[buf][v][ty][tx])) * ihy;
+        const T dx = (w1 * (sF[buf][v][ty][tx + 3] - sF[buf][v][ty][tx + 1]) -
+                      w2 * (sF[buf][v][ty][tx + 4] - sF[buf][v][ty][tx])) * ihx;
+        const T dy = (w1 * (sG[buf][v][ty + 3][tx] - sG[buf][v][ty + 1][tx]) -
+                      w2 * (sG[buf][v][ty + 4][tx] - sG[buf][v][ty][tx])) * ihy;
         R[v] = -(dx + dy);
       }
       if (three) {
@@ -166,7 +168,7 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
         euler_flux(q[3], 2, gm1, h3);
         euler_flux(q[4], 2, gm1, h4);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) R[v] -= (T(8) * (h3[v] - h1[v]) - (h4[v] - h0[v])) * ihz;
+        for (int v = 0; v < 5; ++v) R[v] -= (w1 * (h3[v] - h1[v]) - w2 * (h4[v] - h0[v])) * ihz;
       }
       const long long g = g0 + iz * gplane;
       T out[5];

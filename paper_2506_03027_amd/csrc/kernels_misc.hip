@@ -14,8 +14,8 @@ __device__ __forceinline__ unsigned long long sm64(unsigned long long seed, unsi
 }
 
 // Alg. 3 guard: delays beyond L-1 or beyond the available history are 0.
-__device__ __forceinline__ int guard_delay(long long k, long long n, int L) {
-  return (k < 0 || k > L - 1 || k > n - kLevels + 1) ? 0 : (int)k;
+__device__ __forceinline__ int guard_delay(long long k, long long n, int L, int C) {
+  return (k < 0 || k > L - 1 || k > n - C + 1) ? 0 : (int)k;
 }
 
 // Delay of step n (n >= C) for (block, slot) index i = b * 18 + slot:
@@ -29,32 +29,33 @@ __device__ __forceinline__ unsigned mod_small(unsigned long long x, unsigned L) 
   return ((hi % L) * p32 + lo % L) % L;
 }
 
-__device__ __forceinline__ int draw_delay(long long n, int i, int nblocks, int L, unsigned long long seed, int algo) {
-  if (n < kLevels) return 0;   // synchronous steps (not drawn)
+__device__ __forceinline__ int draw_delay(long long n, int i, int nblocks, int L, unsigned long long seed, int algo,
+                                          int C) {
+  if (n < C) return 0;   // synchronous steps (not drawn)
   long long k;
   if (algo == 0) {
-    k = mod_small((unsigned long long)(n - kLevels), (unsigned)L);
+    k = mod_small((unsigned long long)(n - C), (unsigned)L);
   } else {
     const unsigned long long draw = (unsigned long long)n * (unsigned long long)nblocks * kNumSlots + i;
     k = mod_small(sm64(seed, draw), (unsigned)L);
   }
-  return guard_delay(k, n, L);
+  return guard_delay(k, n, L, C);
 }
 
 // Delays of step n for every (block, slot): the rule above, or the injected
 // value (guarded the same way).
-__global__ void delays_kernel(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
+__global__ void delays_kernel(int8_t* out, const int8_t* inject, long long n, int nblocks, int L, int C,
                               unsigned long long seed, int algo, const long long* nstep) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nblocks * kNumSlots) return;
   if (nstep) n = *nstep;
-  out[i] = (int8_t)(inject ? guard_delay(inject[i], n, L) : draw_delay(n, i, nblocks, L, seed, algo));
+  out[i] = (int8_t)(inject ? guard_delay(inject[i], n, L, C) : draw_delay(n, i, nblocks, L, seed, algo, C));
 }
 
-hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
+hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nblocks, int L, int C,
                          unsigned long long seed, int algo, hipStream_t s, const long long* nstep) {
   const int cnt = nblocks * kNumSlots;
-  delays_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(out, inject, n, nblocks, L, seed, algo, nstep);
+  delays_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(out, inject, n, nblocks, L, C, seed, algo, nstep);
   return hipGetLastError();
 }
 
@@ -80,7 +81,7 @@ hipError_t launch_step_inc(long long* const* counters, int n, hipStream_t s) {
 // (AT: buffer extrapolation and RK-consistent updates, Eqs. 7-15; AS: the
 // stale level itself).  One thread per point, consecutive threads on
 // consecutive points of a region, so reads and writes are contiguous runs.
-template <typename T, int S, bool STALE>
+template <typename T, int S, int CL, bool STALE>
 __global__ void __launch_bounds__(kHaloChunk)
     halo_kernel(const T* __restrict__ ring, T* __restrict__ halo, const HaloRegion* __restrict__ regions,
                 const HaloWork* __restrict__ work, int8_t* __restrict__ delays,
@@ -97,16 +98,16 @@ __global__ void __launch_bounds__(kHaloChunk)
   if (dd.draw) {
     // the step's delay of this region, drawn here (graph-captured steps);
     // the region's first chunk records it for the learned-halo correction
-    k = draw_delay(n, rg.kidx, dd.nblocks, L, dd.seed, dd.algo);
+    k = draw_delay(n, rg.kidx, dd.nblocks, L, dd.seed, dd.algo, CL);
     if (wk.start == 0 && threadIdx.x == 0) delays[rg.kidx] = (int8_t)k;
   } else {
     k = delays[rg.kidx];
   }
   const int i = wk.start + threadIdx.x;
   if (i >= rg.npts) return;
-  int sl[kLevels];
+  int sl[CL];
 #pragma unroll
-  for (int l = 0; l < kLevels; ++l) {
+  for (int l = 0; l < CL; ++l) {
     int q = slot_now - k - l;
     sl[l] = q + ((q < 0) ? D : 0);
   }
@@ -119,15 +120,15 @@ __global__ void __launch_bounds__(kHaloChunk)
       for (int e = 0; e < S; ++e) halo[e * halo_stride + dof] = x;
       continue;
     }
-    double lev[kLevels];
+    double lev[CL];
 #pragma unroll
-    for (int l = 0; l < kLevels; ++l) lev[l] = (double)ring[(long long)sl[l] * slot_stride + so];
+    for (int l = 0; l < CL; ++l) lev[l] = (double)ring[(long long)sl[l] * slot_stride + so];
 #pragma unroll
     for (int e = 0; e < S; ++e) {
-      const double* w = W + ((long long)e * L + k) * kLevels;
+      const double* w = W + ((long long)e * L + k) * CL;
       double a = 0.0;
 #pragma unroll
-      for (int l = 0; l < kLevels; ++l) a = fma(w[l], lev[l], a);
+      for (int l = 0; l < CL; ++l) a = fma(w[l], lev[l], a);
       halo[e * halo_stride + dof] = (T)a;
     }
   }
@@ -139,13 +140,19 @@ hipError_t launch_halo(const T* ring, T* halo, const HaloRegion* regions, const 
                        int D, int slot_now, int L, int stages, bool stale, hipStream_t s,
                        const long long* nstep, DelayDraw dd) {
   dim3 grid(nwork), block(kHaloChunk);
-#define ATNS_HALO(SS, ST)                                                                               \
-  halo_kernel<T, SS, ST><<<grid, block, 0, s>>>(ring, halo, regions, work, delays, W, slot_stride, \
-                                                 halo_stride, D, slot_now, L, nstep, dd)
+#define ATNS_HALO(SS, CC, ST)                                                                               \
+  halo_kernel<T, SS, CC, ST><<<grid, block, 0, s>>>(ring, halo, regions, work, delays, W, slot_stride, \
+                                                     halo_stride, D, slot_now, L, nstep, dd)
+  // the stage count identifies the scheme: RK4 and LSERK4 pair with AT4
+  // (C = 5), LSERK2 with AT2 (C = 3)
   if (stages == 4) {
-    if (stale) ATNS_HALO(4, true); else ATNS_HALO(4, false);
+    if (stale) ATNS_HALO(4, 5, true); else ATNS_HALO(4, 5, false);
+  } else if (stages == 5) {
+    if (stale) ATNS_HALO(5, 5, true); else ATNS_HALO(5, 5, false);
+  } else if (stages == 2) {
+    if (stale) ATNS_HALO(2, 3, true); else ATNS_HALO(2, 3, false);
   } else {
-    if (stale) ATNS_HALO(5, true); else ATNS_HALO(5, false);
+    return hipErrorInvalidValue;
   }
 #undef ATNS_HALO
   return hipGetLastError();

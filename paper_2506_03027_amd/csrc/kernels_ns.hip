@@ -105,7 +105,9 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
   const T gM2 = (T)p.mach2_gamma;
   const T kap = (T)p.kappa;
   const T ire = (T)p.inv_re;
-  const T ihx = (T)p.inv12h[0], ihy = (T)p.inv12h[1], ihz = (T)p.inv12h[2];
+  const T ihx = (T)p.dscale[0], ihy = (T)p.dscale[1], ihz = (T)p.dscale[2];
+  // central-difference weights of the inner and outer neighbour pairs
+  const T w1 = p.cd2 ? T(1) : T(8), w2 = p.cd2 ? T(0) : T(1);
   const T two3 = (T)(2.0 / 3.0);
 
   __shared__ T sP[2][4][EY][EX];        // u, v, w, T of plane m (double-buffered)
@@ -219,17 +221,17 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
       T g[3][3], gT[3];   // g[i][j] = d u_i / d x_j
       T dz[4] = {T(0), T(0), T(0), T(0)};
       if constexpr (three) {
-        dz[0] = (T(8) * (qu[3] - qu[1]) - (qu[4] - qu[0])) * ihz;
-        dz[1] = (T(8) * (qv[3] - qv[1]) - (qv[4] - qv[0])) * ihz;
-        dz[2] = (T(8) * (qw[3] - qw[1]) - (qw[4] - qw[0])) * ihz;
-        dz[3] = (T(8) * (qT[3] - qT[1]) - (qT[4] - qT[0])) * ihz;
+        dz[0] = (w1 * (qu[3] - qu[1]) - w2 * (qu[4] - qu[0])) * ihz;
+        dz[1] = (w1 * (qv[3] - qv[1]) - w2 * (qv[4] - qv[0])) * ihz;
+        dz[2] = (w1 * (qw[3] - qw[1]) - w2 * (qw[4] - qw[0])) * ihz;
+        dz[3] = (w1 * (qT[3] - qT[1]) - w2 * (qT[4] - qT[0])) * ihz;
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const T ddx = (T(8) * (sP[buf][c][sy][sx + 1] - sP[buf][c][sy][sx - 1]) -
-                       (sP[buf][c][sy][sx + 2] - sP[buf][c][sy][sx - 2])) * ihx;
-        const T ddy = (T(8) * (sP[buf][c][sy + 1][sx] - sP[buf][c][sy - 1][sx]) -
-                       (sP[buf][c][sy + 2][sx] - sP[buf][c][sy - 2][sx])) * ihy;
+        const T ddx = (w1 * (sP[buf][c][sy][sx + 1] - sP[buf][c][sy][sx - 1]) -
+                       w2 * (sP[buf][c][sy][sx + 2] - sP[buf][c][sy][sx - 2])) * ihx;
+        const T ddy = (w1 * (sP[buf][c][sy + 1][sx] - sP[buf][c][sy - 1][sx]) -
+                       w2 * (sP[buf][c][sy + 2][sx] - sP[buf][c][sy - 2][sx])) * ihy;
         if (c < 3) {
           g[c][0] = ddx;
           g[c][1] = ddy;
@@ -281,7 +283,7 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
           const bool zt = mrel - 2 >= 0 && mrel - 2 < nz;
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            if (zt) zd[v] = (T(8) * (sH[s3][v][y][x] - sH[s1][v][y][x]) - (hz[v] - sH[s0][v][y][x])) * ihz;
+            if (zt) zd[v] = (w1 * (sH[s3][v][y][x] - sH[s1][v][y][x]) - w2 * (hz[v] - sH[s0][v][y][x])) * ihz;
             sH[s0][v][y][x] = hz[v];
           }
         }
@@ -296,10 +298,10 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
     const int dbuf = buf ^ 1;
     T xyn[5] = {T(0), T(0), T(0), T(0), T(0)};
     auto xy_div = [&](int v, int px, int py) {
-      const T ddx = (T(8) * (sFX[dbuf][v][py][px + 3] - sFX[dbuf][v][py][px + 1]) -
-                     (sFX[dbuf][v][py][px + 4] - sFX[dbuf][v][py][px])) * ihx;
-      const T ddy = (T(8) * (sFY[dbuf][v][py + 3][px] - sFY[dbuf][v][py + 1][px]) -
-                     (sFY[dbuf][v][py + 4][px] - sFY[dbuf][v][py][px])) * ihy;
+      const T ddx = (w1 * (sFX[dbuf][v][py][px + 3] - sFX[dbuf][v][py][px + 1]) -
+                     w2 * (sFX[dbuf][v][py][px + 4] - sFX[dbuf][v][py][px])) * ihx;
+      const T ddy = (w1 * (sFY[dbuf][v][py + 3][px] - sFY[dbuf][v][py + 1][px]) -
+                     w2 * (sFY[dbuf][v][py + 4][px] - sFY[dbuf][v][py][px])) * ihy;
       return ddx + ddy;
     };
     if constexpr (three) {

@@ -29,7 +29,7 @@ template <typename T>
 hipError_t launch_init_case(T* U, const int n[3], const double h[3], const double len[3], int kind, int ndim,
                             double gamma, double mach, double beta, double t, double xc, double yc, hipStream_t s);
 hipError_t launch_copy_probe(const void* src, void* dst, long long bytes, hipStream_t s);
-hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nblocks, int L,
+hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nblocks, int L, int C,
                          unsigned long long seed, int algo, hipStream_t s, const long long* nstep = nullptr);
 template <typename T>
 hipError_t launch_ring_fill(const StageParams<T>& p, const T* U, int slot, int nblocks, hipStream_t s);

@@ -132,9 +132,14 @@ struct StageParams {
   long long* step_end;
   unsigned int* done;
   int L;
+  int C;                 // delayed levels of the AT scheme (5 AT4, 3 AT2)
   int H;                 // halo depth (faces)
   int ndim;
-  double inv12h[3];      // 1 / (12 h_d)
+  // Central difference of Eq. 2 from d1 = f(+1) - f(-1), d2 = f(+2) - f(-2):
+  // (w1 d1 - w2 d2) * dscale, with w1 = 8, w2 = 1, dscale = 1/(12 h_d) for
+  // CD4 and w1 = 1, w2 = 0, dscale = 1/(2 h_d) for CD2 (cd2 != 0).
+  int cd2;
+  double dscale[3];
   double gamma;
   double mach2_gamma;    // gamma * M^2          (T = gamma M^2 p / rho)
   double kappa;          // 1/((gamma-1) M^2 Pr)

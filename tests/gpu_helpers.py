@@ -10,7 +10,7 @@ from oracle import solver
 from paper_2506_03027_amd import atns
 
 PHYS = {"euler": atns.EULER, "ns": atns.NS}
-RK = {"rk4": atns.RK4, "lserk4": atns.LSERK4}
+RK = {"rk4": atns.RK4, "lserk4": atns.LSERK4, "lserk2": atns.LSERK2}
 MODE = {"sa": atns.SA, "as": atns.AS, "at": atns.AT}
 ALGO = {"caa": atns.CAA, "saa": atns.SAA}
 EPS32 = 2.0 ** -24
@@ -30,13 +30,15 @@ def announce(*what):
 
 def pair(spec, precision="f64", dt=None):
     """(oracle, gpu solver) for a spec dict with keys n, length, ndim, nblk,
-    physics, rk, mode, algo, L, seed, re, mach, split."""
+    physics, rk, mode, algo, L, seed, re, mach, split.  rk "lserk2" is the
+    second-order method (CD2, AT2 with three levels) on both sides."""
     s = dict(ndim=3, nblk=(1, 1, 1), physics="euler", rk="rk4", mode="sa", algo="caa", L=1,
              seed=0, re=1600.0, mach=0.1, gamma=1.4, pr=0.71, split=None)
     s.update(spec)
     cfg = solver.Config(s["n"], s["length"], s["ndim"], s["nblk"], s["physics"], gamma=s["gamma"],
                         mach=s["mach"], re=s["re"], pr=s["pr"], rk=s["rk"], mode=s["mode"],
-                        algo=s["algo"], L=s["L"], seed=s["seed"], dt=dt, split=s["split"])
+                        algo=s["algo"], L=s["L"], seed=s["seed"], dt=dt, split=s["split"],
+                        order=2 if s["rk"] == "lserk2" else 4, C=3 if s["rk"] == "lserk2" else 5)
     o = solver.Oracle(cfg)
     g = atns.Solver(n=s["n"], length=s["length"], ndim=s["ndim"], nblk=s["nblk"],
                     physics=PHYS[s["physics"]], gamma=s["gamma"], mach=s["mach"], re=s["re"],

@@ -38,6 +38,8 @@ def _case(physics, rk, mode, algo, L):
     (atns.EULER, atns.RK4, atns.SA, atns.CAA, 1),
     (atns.NS, atns.RK4, atns.AT, atns.CAA, 3),
     (atns.NS, atns.LSERK4, atns.AT, atns.SAA, 2),
+    (atns.EULER, atns.LSERK2, atns.AT, atns.SAA, 3),
+    (atns.NS, atns.LSERK2, atns.AT, atns.CAA, 2),
 ])
 def test_graph_steps_match_eager_bitwise(physics, rk, mode, algo, L):
     torch = need_gpu()

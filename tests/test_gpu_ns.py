@@ -21,14 +21,15 @@ def ns_tol(U, h, precision, re, wnorm=1.0):
     return rhs_tol(U, h, precision, wnorm) * (1.0 + 1.0 / (re * min(h)))
 
 
+@pytest.mark.parametrize("rk", ["rk4", "lserk2"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("split", [None, ([10, 8, 6], [12, 8], [9, 7])])
-def test_ns_rhs_synchronous(precision, split):
+def test_ns_rhs_synchronous(precision, split, rk):
     need_gpu()
     announce("ns rhs sync", precision, split)
     n = (24, 20, 16)
     nblk = (3, 2, 2) if split else (2, 2, 2)
-    o, g = pair(dict(n=n, length=BOX, nblk=nblk, split=split, **NSKW), precision)
+    o, g = pair(dict(n=n, length=BOX, nblk=nblk, split=split, rk=rk, **NSKW), precision)
     U = inputs.smooth_random_state(n, BOX, seed=8)
     if precision == "f32":
         U = f32(U)
@@ -40,15 +41,15 @@ def test_ns_rhs_synchronous(precision, split):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("mode, algo, nstep", [("at", "saa", 13), ("at", "caa", 16),
-                                               ("as", "saa", 13)])
-def test_ns_rhs_delayed_halos(precision, mode, algo, nstep):
+@pytest.mark.parametrize("mode, algo, nstep, rk", [("at", "saa", 13, "rk4"), ("at", "caa", 16, "rk4"),
+                                                   ("as", "saa", 13, "rk4"), ("at", "saa", 13, "lserk2")])
+def test_ns_rhs_delayed_halos(precision, mode, algo, nstep, rk):
     need_gpu()
-    announce("ns rhs delayed", precision, mode, algo)
+    announce("ns rhs delayed", precision, mode, algo, rk)
     n = (32, 24, 20)
     split = ([12, 12, 8], [14, 10], [10, 10])
     o, g = pair(dict(n=n, length=BOX, nblk=(3, 2, 2), split=split, mode=mode, algo=algo, L=4,
-                     seed=23, **NSKW), precision)
+                     seed=23, rk=rk, **NSKW), precision)
     D = g.ring_depth
     hist = smooth_history(n, list(range(nstep - D + 1, nstep + 1)))
     for m, U in sorted(hist.items()):
@@ -62,7 +63,7 @@ def test_ns_rhs_delayed_halos(precision, mode, algo, nstep):
     assert np.abs(R - ref).max() < tol, (np.abs(R - ref).max(), tol)
 
 
-@pytest.mark.parametrize("rk", ["rk4", "lserk4"])
+@pytest.mark.parametrize("rk", ["rk4", "lserk4", "lserk2"])
 @pytest.mark.parametrize("mode, algo, L", [("sa", "caa", 1), ("at", "caa", 4), ("at", "saa", 3),
                                            ("as", "saa", 2)])
 def test_ns_steps_fp64_match_oracle(rk, mode, algo, L):

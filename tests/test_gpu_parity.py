@@ -30,14 +30,15 @@ def rhs_tol(U, h, precision, wnorm=1.0):
 
 
 # ------------------------------------------------------------- RHS parity
+@pytest.mark.parametrize("rk", ["rk4", "lserk2"])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("split", [None, ([10, 8, 6], [12, 8], [9, 7])])
-def test_rhs_synchronous(precision, split):
+def test_rhs_synchronous(precision, split, rk):
     need_gpu()
     announce("rhs sync", precision, split)
     n = (24, 20, 16)
     nblk = (3, 2, 2) if split else (2, 2, 2)
-    o, g = pair(dict(n=n, length=BOX, nblk=nblk, split=split), precision)
+    o, g = pair(dict(n=n, length=BOX, nblk=nblk, split=split, rk=rk), precision)
     U = inputs.smooth_random_state(n, BOX, seed=4)
     if precision == "f32":
         U = f32(U)
@@ -57,15 +58,16 @@ def smooth_history(n, steps, tau=0.05, ndim=3, seed=3):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("mode, algo, nstep", [("at", "saa", 13), ("at", "caa", 16),
-                                               ("as", "saa", 13)])
-def test_rhs_delayed_halos(precision, mode, algo, nstep):
+@pytest.mark.parametrize("mode, algo, nstep, rk", [("at", "saa", 13, "rk4"), ("at", "caa", 16, "rk4"),
+                                                   ("as", "saa", 13, "rk4"), ("at", "saa", 13, "lserk2"),
+                                                   ("at", "caa", 18, "lserk2")])
+def test_rhs_delayed_halos(precision, mode, algo, nstep, rk):
     need_gpu()
-    announce("rhs delayed", precision, mode, algo)
+    announce("rhs delayed", precision, mode, algo, rk)
     n = (32, 24, 20)
     split = ([12, 12, 8], [14, 10], [10, 10])
     o, g = pair(dict(n=n, length=BOX, nblk=(3, 2, 2), split=split, mode=mode, algo=algo, L=4,
-                     seed=21), precision)
+                     seed=21, rk=rk), precision)
     D = g.ring_depth
     hist = smooth_history(n, list(range(nstep - D + 1, nstep + 1)))
     for m, U in sorted(hist.items()):
@@ -80,12 +82,13 @@ def test_rhs_delayed_halos(precision, mode, algo, nstep):
 
 
 # ----------------------------------------------------------------- delays
+@pytest.mark.parametrize("rk", ["rk4", "lserk2"])
 @pytest.mark.parametrize("algo", ["caa", "saa"])
-def test_device_delays_match_oracle(algo):
+def test_device_delays_match_oracle(algo, rk):
     need_gpu()
-    announce("delays", algo)
+    announce("delays", algo, rk)
     n = (32, 32, 32)
-    o, g = pair(dict(n=n, length=BOX, nblk=(4, 2, 2), mode="at", algo=algo, L=4, seed=77))
+    o, g = pair(dict(n=n, length=BOX, nblk=(4, 2, 2), mode="at", algo=algo, L=4, seed=77, rk=rk))
     for step in list(range(0, 12)) + [999, 123456]:
         k = g.get_delays(step)
         ref = o.delays(step)
@@ -121,7 +124,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("rk", ["rk4", "lserk4"])
+@pytest.mark.parametrize("rk", ["rk4", "lserk4", "lserk2"])
 @pytest.mark.parametrize("mode, algo, L", CASES)
 def test_steps_fp64_match_oracle(rk, mode, algo, L):
     need_gpu()

@@ -27,23 +27,26 @@ def test_library_exports_every_declared_symbol():
     assert set(syms) == set(atns.EXPORTS)
 
 
-@pytest.mark.parametrize("rk, orc", [(atns.RK4, "rk4"), (atns.LSERK4, "lserk4")])
+@pytest.mark.parametrize("rk, orc, C", [(atns.RK4, "rk4", 5), (atns.LSERK4, "lserk4", 5),
+                                        (atns.LSERK2, "lserk2", 3)])
 @pytest.mark.parametrize("L", [1, 4, 5])
-def test_host_weight_table_matches_oracle(rk, orc, L):
+def test_host_weight_table_matches_oracle(rk, orc, C, L):
     W = atns.host_weights(rk, atns.AT, L)
-    ref = oat.halo_table(orc, "at", 5, L - 1)
+    ref = oat.halo_table(orc, "at", C, L - 1)
+    assert W.shape == ref.shape
     scale = np.abs(ref).max()
     assert np.abs(W - ref).max() < 1e-14 * scale
     Was = atns.host_weights(rk, atns.AS, L)
-    assert np.array_equal(Was, oat.halo_table(orc, "as", 5, L - 1))
+    assert np.array_equal(Was, oat.halo_table(orc, "as", C, L - 1))
 
 
+@pytest.mark.parametrize("rk, C", [(atns.RK4, 5), (atns.LSERK2, 3)])
 @pytest.mark.parametrize("algo, oalgo", [(atns.CAA, "caa"), (atns.SAA, "saa")])
-def test_host_delays_match_oracle_bitwise(algo, oalgo):
-    for n in (0, 4, 5, 6, 7, 20, 1234):
+def test_host_delays_match_oracle_bitwise(algo, oalgo, rk, C):
+    for n in (0, 2, 3, 4, 5, 6, 7, 20, 1234):
         for nb, L, seed in ((8, 4, 1), (64, 4, 99), (5, 5, 2 ** 63 + 17)):
-            k, sync = atns.host_delays(algo, n, nb, L, seed)
-            ref = odl.delays(oalgo, n, nb, L, 5, seed)
+            k, sync = atns.host_delays(algo, n, nb, L, seed, rk)
+            ref = odl.delays(oalgo, n, nb, L, C, seed)
             if ref is None:
                 assert sync and not k.any()
             else:
@@ -82,7 +85,8 @@ def test_host_helpers_reject_bad_arguments():
     assert atns.lib().atns_host_weights(atns.RK4, atns.AT, 0, out.ctypes.data) == -1
     assert atns.lib().atns_host_weights(9, atns.AT, 4, out.ctypes.data) == -1
     k = np.zeros(18, dtype=np.int8)
-    assert atns.lib().atns_host_delays(atns.SAA, -1, 1, 4, 0, k.ctypes.data, None) == -1
+    assert atns.lib().atns_host_delays(atns.SAA, atns.RK4, -1, 1, 4, 0, k.ctypes.data, None) == -1
+    assert atns.lib().atns_host_delays(atns.SAA, 7, 5, 1, 4, 0, k.ctypes.data, None) == -1
 
 
 def test_batch_create_rejects_bad_members_without_device():
