@@ -31,7 +31,17 @@ sys.path.insert(0, ROOT)
 from paper_2506_03027_amd import atns, inputs  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E
-C_LEVELS = 5
+C_LEVELS = 5              # delayed levels of AT4 (RK4, LSERK4)
+RK_ID = {"rk4": atns.RK4, "lserk4": atns.LSERK4, "lserk2": atns.LSERK2}
+
+
+def n_stages(w):
+    return atns.stages(RK_ID[w["rk"]])
+
+
+def n_levels(w):
+    """Delayed levels C of the workload's AT scheme (5 for AT4, 3 for AT2)."""
+    return atns.levels(RK_ID[w["rk"]])
 
 
 def halo_fraction(w):
@@ -69,7 +79,7 @@ def algorithmic_bytes_per_point_stage(w, stages, esz):
     scale = esz / 4.0
     if w["mode"] == "sa":
         return 80.0 * scale, f
-    levels = C_LEVELS if w["mode"] == "at" else 1
+    levels = n_levels(w) if w["mode"] == "at" else 1
     return (80.0 + 20.0 * levels * f + 20.0 * f / stages) * scale, f
 
 
@@ -92,7 +102,7 @@ def make_solver(w, precision, mode=None):
     algo = atns.SAA if w.get("algo", "saa") == "saa" else atns.CAA
     return atns.Solver(n=w["n"], length=w["length"], ndim=w["ndim"], nblk=w["nblk"], physics=phys,
                        mach=w.get("mach", 0.1), re=w.get("re", 1600.0),
-                       rk=atns.RK4 if w["rk"] == "rk4" else atns.LSERK4, mode=m, algo=algo,
+                       rk=RK_ID[w["rk"]], mode=m, algo=algo,
                        L=w["L"], seed=w.get("seed", 1), precision=precision)
 
 
@@ -188,15 +198,16 @@ def cpu_baseline(torch, w, budget_s=15.0):
     nblk = tuple(n[d] // blk[d] for d in range(3))
     s = dict(w, n=n, nblk=nblk)
     length = w["length"]
-    stages = 4 if w["rk"] == "rk4" else 5
+    stages = n_stages(w)
     cfg = solver.Config(n, length, w["ndim"], nblk, w["physics"], mach=w.get("mach", 0.1),
                         re=w.get("re", 1600.0), rk=w["rk"], mode=w["mode"], algo=w.get("algo", "saa"),
-                        L=w["L"], seed=w.get("seed", 1))
+                        L=w["L"], seed=w.get("seed", 1), C=n_levels(w),
+                        order=2 if w["rk"] == "lserk2" else 4)
     U0 = initial_state(s)
     dt = inputs.cfl_dt(U0, n, length, w["ndim"], 1.4, w["cfl"])
     cfg.dt = dt
     o = solver.Oracle(cfg)
-    D = C_LEVELS + w["L"]
+    D = n_levels(w) + w["L"]
     n0 = 2 * D
     hist = {}
     for m in range(n0 - D + 1, n0 + 1):
@@ -527,11 +538,11 @@ def main():
         series_main(a, torch)
         return
     w = inputs.WORKLOADS[a.workload]
-    stages = 4 if w["rk"] == "rk4" else 5
+    stages = n_stages(w)
     npts = w["n"][0] * w["n"][1] * w["n"][2]
     U0 = initial_state(w)
     dt = inputs.cfl_dt(U0, w["n"], w["length"], w["ndim"], 1.4, w["cfl"])
-    warmup = max(a.warmup, C_LEVELS + 1)   # the first C steps are synchronous
+    warmup = max(a.warmup, n_levels(w) + 1)   # the first C steps are synchronous
 
     ms, launches, kms, finite, tiles = gpu_run(torch, w, atns.F32, None, a.steps, warmup, U0, dt)
     value = npts * stages * a.steps / (ms * 1e-3)
@@ -554,8 +565,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": a.workload, "grid": list(w["n"]), "blocks": list(w["nblk"]),
-                   "physics": w["physics"], "scheme": "CD4 + %s halos, %s" % (w["mode"].upper(),
-                                                                             w["rk"].upper()),
+                   "physics": w["physics"],
+                   "scheme": "%s + %s halos, %s" % ("CD2" if w["rk"] == "lserk2" else "CD4", w["mode"].upper(),
+                                                    w["rk"].upper()),
                    "algo": w.get("algo", "saa").upper(), "L": w["L"], "cfl": w["cfl"],
                    "tiles": list(tiles)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

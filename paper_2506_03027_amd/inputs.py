@@ -133,6 +133,10 @@ WORKLOADS = {
     "vortex3d_128": dict(n=(128, 128, 128), length=(10.0, 10.0, 10.0), ndim=3,
                          nblk=(4, 4, 4), physics="euler", rk="rk4", mode="at",
                          algo="saa", L=4, cfl=0.02, precision="f32"),
+    # the second-order method of Table 1 cases 1-3 on the same grid and blocks
+    "vortex3d_128_lserk2": dict(n=(128, 128, 128), length=(10.0, 10.0, 10.0), ndim=3,
+                                nblk=(4, 4, 4), physics="euler", rk="lserk2", mode="at",
+                                algo="saa", L=4, cfl=0.02, precision="f32"),
     "tgv_256": dict(n=(256, 256, 256), length=(2 * math.pi,) * 3, ndim=3,
                     nblk=(16, 16, 8), physics="ns", rk="rk4", mode="at",
                     algo="saa", L=4, re=1600.0, mach=0.1, cfl=0.02,

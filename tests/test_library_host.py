@@ -152,3 +152,7 @@ def test_bench_byte_accounting_matches_the_per_point_figures():
     assert bench.algorithmic_bytes_per_point_stage(W["vortex3d_128"], 4, 4)[0] == 80 + 100 * 3 / 8 + 20 * 3 / 8 / 4
     assert bench.stage_kernel_bytes_per_point(W["tgv_256"], 4, 4) == 80 + 20 * 11 / 8 + 20 * 11 / 8 / 4
     assert bench.algorithmic_bytes_per_point_stage(dict(W["vortex3d_128"], mode="sa"), 4, 8)[0] == 160
+    # the second-order method: AT2 reads C = 3 levels, LSERK2 has 2 stages
+    w2 = W["vortex3d_128_lserk2"]
+    assert bench.n_levels(w2) == 3 and bench.n_stages(w2) == 2
+    assert bench.algorithmic_bytes_per_point_stage(w2, 2, 4)[0] == 80 + 60 * 3 / 8 + 20 * 3 / 8 / 2
