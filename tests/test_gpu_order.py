@@ -85,3 +85,52 @@ def test_second_order_method_delay_error(mode, lo, hi):
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     print("lserk2 mode", mode, "delay errors", errs, "orders", orders)
     assert lo < orders[-1] < hi, (errs, orders)
+
+
+def _u_2d(N, T, mode, P, L):
+    """u-velocity after time T of the second-order method on the 2-D vortex
+    (FP64), CAA with delay bound L on P blocks along x."""
+    torch = need_gpu()
+    n, length = (N, N, 1), (10.0, 10.0, 1.0)
+    U0 = inputs.vortex_state(n, length, 2)
+    dt = inputs.cfl_dt(U0, n, length, 2, 1.4, 0.05)
+    steps = int(math.ceil(T / dt))
+    g = atns.Solver(n=n, length=length, ndim=2, nblk=(P, 1, 1), rk=atns.LSERK2, mode=mode, algo=atns.CAA,
+                    L=L, seed=1, precision=atns.F64)
+    g.set_dt(T / steps)
+    g.set_state(torch.from_numpy(U0))
+    g.step(steps)
+    U = g.get_state().double().cpu().numpy()
+    g.close()
+    return U[1] / U[0]
+
+
+def test_delay_error_scaling_in_L_and_P():
+    # Sec. 5.1 error scaling for Table 1 case 3 (CAA-AT, LSERK2-CD2-AT2): the
+    # error the delays add (RMS u-velocity difference to the synchronous run)
+    # is a cubic polynomial in L (C = 3 delayed levels) and grows linearly
+    # with the number of blocks P (cut along x).
+    need_gpu()
+    N, T = 256, 1.0
+    ref = _u_2d(N, T, atns.SA, 1, 1)
+
+    def err(P, L):
+        announce("delay error scaling", P, L)
+        d = _u_2d(N, T, atns.AT, P, L) - ref
+        return float(np.sqrt(np.mean(d * d)))
+
+    Ls = np.arange(1, 9)
+    EL = np.array([err(16, int(L)) for L in Ls])
+    rel = {}
+    for deg in (2, 3):
+        c = np.polyfit(Ls, EL, deg)
+        rel[deg] = float(np.max(np.abs(np.polyval(c, Ls) - EL) / EL))
+    Ps = np.array([4, 8, 16, 32])
+    EP = np.array([err(int(P), 4) for P in Ps])
+    c = np.polyfit(Ps, EP, 1)
+    r2 = 1.0 - np.sum((np.polyval(c, Ps) - EP) ** 2) / np.sum((EP - EP.mean()) ** 2)
+    print("E(L), P = 16:", EL.tolist(), "relative residual quadratic / cubic fit:", rel)
+    print("E(P), L = 4:", EP.tolist(), "linear fit", c.tolist(), "R^2", r2)
+    assert np.all(np.diff(EL) > 0), EL
+    assert rel[3] < 0.05 and rel[2] > 5 * rel[3], rel
+    assert c[0] > 0 and r2 > 0.99, (EP, r2)

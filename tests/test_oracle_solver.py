@@ -91,6 +91,57 @@ def test_table1_orders_second_order_method():
     assert 0.7 < o_as[-1] < 1.3, o_as
 
 
+_U_CACHE = {}
+
+
+def _u_2d(N, T, mode, P, L):
+    """u-velocity after time T of the second-order method (Table 1 cases
+    1-3: LSERK2, CD2, AT2) on the 2-D vortex, CAA with delay bound L on P
+    blocks along x."""
+    key = (N, T, mode, P, L)
+    if key not in _U_CACHE:
+        n, length = (N, N, 1), (10.0, 10.0, 1.0)
+        U0 = inputs.vortex_state(n, length, 2)
+        dt = inputs.cfl_dt(U0, n, length, 2, 1.4, 0.05)
+        steps = int(math.ceil(T / dt))
+        cfg = solver.Config(n, length, ndim=2, nblk=(P, 1, 1), physics="euler", rk="lserk2", mode=mode,
+                            algo="caa", L=L, seed=1, dt=T / steps, order=2, C=atmod.AT2_C)
+        o = solver.Oracle(cfg)
+        o.set_state(U0)
+        o.step(steps)
+        _U_CACHE[key] = o.U[1] / o.U[0]
+    return _U_CACHE[key]
+
+
+def _delay_error_2d(N, T, P, L):
+    """RMS u-velocity difference between CAA-AT and the synchronous run."""
+    d = _u_2d(N, T, "at", P, L) - _u_2d(N, T, "sa", 1, 1)
+    return float(np.sqrt(np.mean(d * d)))
+
+
+@pytest.mark.slow
+def test_delay_error_cubic_in_L_and_linear_in_P():
+    # Sec. 5.1 error scaling: the error that delays add grows with the
+    # moments of the delay up to order C (a cubic polynomial in L for AT2,
+    # C = 3) and with the share of points next to block boundaries (linear
+    # in the number of blocks P when they are cut along one axis).
+    Ls = np.arange(1, 9)
+    EL = np.array([_delay_error_2d(64, 0.5, 8, int(L)) for L in Ls])
+    assert np.all(np.diff(EL) > 0), EL
+    rel = {}
+    for deg in (2, 3):
+        c = np.polyfit(Ls, EL, deg)
+        rel[deg] = float(np.max(np.abs(np.polyval(c, Ls) - EL) / EL))
+    print("E(L)", EL, "max relative residual of the quadratic / cubic fit", rel)
+    assert rel[3] < 0.05 and rel[2] > 5 * rel[3], rel
+    Ps = np.array([4, 8, 16])
+    EP = np.array([_delay_error_2d(64, 0.5, int(P), 4) for P in Ps])
+    c = np.polyfit(Ps, EP, 1)
+    r2 = 1.0 - np.sum((np.polyval(c, Ps) - EP) ** 2) / np.sum((EP - EP.mean()) ** 2)
+    print("E(P)", EP, "linear fit", c, "R^2", r2)
+    assert c[0] > 0 and r2 > 0.99, (EP, r2)
+
+
 def test_at_with_zero_delay_converges_to_sa():
     # AT with every delay 0 differs from SA only through the temporal
     # extrapolation of later stages, an O(h^4) effect.
