@@ -18,6 +18,16 @@ Analytic cases
   It is an exact Euler solution on the infinite plane; on the periodic box the
   tail of the perturbation (about 2.4e-5 in velocity at r = 5) sets a floor
   on the error against the translated initial field.
+* The paper's own vortex (Sec. 5.1, its Gaussian vortex after Visbal) on
+  [-8, 8]^2, Mach 0.1 freestream U_inf = 1 along x, strength
+  beta / (U_inf R) = 0.02:  u = U_inf - beta (y-yc)/R^2 exp(-W^2/2),
+  v = beta (x-xc)/R^2 exp(-W^2/2),  p_inf - p = rho beta^2/(2 R^2) exp(-W^2),
+  W^2 = r^2 / R^2.  The paper leaves R and the density open; R = 1 and a
+  uniform rho = 1 are used, with p_inf = 1/(gamma M^2) (so that the sound
+  speed is U_inf / M).  With uniform density this field is an exact
+  solution of the Euler equations that translates with U_inf: the pressure
+  balances the centripetal acceleration and is constant along the
+  streamlines of the moving frame.  Grid index 0 sits at x = -8.
 * Taylor-Green vortex (Sec. 5.2, Eq. 16) with rho0 = U0 = L0 = 1 on
   [0, 2pi]^3.  The printed v has the sign that makes the field divergent; the
   divergence-free form v = -U0 cos x sin y cos z is used.  The initial
@@ -70,6 +80,29 @@ def vortex_state(n, length, ndim, t=0.0, gamma=1.4, beta=5.0,
     rho = T ** (1.0 / (gamma - 1.0))
     p = rho * T
     return to_conserved(rho, u, v, w, p, gamma)
+
+
+VISBAL_BOX = (16.0, 16.0, 1.0)
+
+
+def visbal_vortex_state(n, t=0.0, gamma=1.4, mach=0.1, strength=0.02, radius=1.0):
+    """Conserved field (5, 1, ny, nx) of the paper's Gaussian vortex on
+    [-8, 8]^2 (grid index 0 at -8), centred at the origin at t = 0 and
+    carried by U_inf = 1 along x (periodic images by minimum distance)."""
+    xs, ys, _ = grid_axes((n[0], n[1], 1), VISBAL_BOX)
+    Y, X = np.meshgrid(ys - 8.0, xs - 8.0, indexing="ij")
+    uinf = 1.0
+    beta = strength * uinf * radius
+    dx = (X - uinf * t + 8.0) % 16.0 - 8.0
+    dy = (Y + 8.0) % 16.0 - 8.0
+    om2 = (dx * dx + dy * dy) / radius ** 2
+    g = np.exp(-0.5 * om2)
+    rho = np.ones_like(X)
+    u = uinf - beta * dy / radius ** 2 * g
+    v = beta * dx / radius ** 2 * g
+    w = np.zeros_like(X)
+    p = 1.0 / (gamma * mach ** 2) - rho * beta ** 2 / (2.0 * radius ** 2) * g * g
+    return to_conserved(rho[None], u[None], v[None], w[None], p[None], gamma)
 
 
 def tgv_state(n, mach=0.1, gamma=1.4):

@@ -206,6 +206,26 @@ def test_vortex_rhs_is_translation_to_fourth_order():
     assert min(orders) > 3.7, (errs, orders)
 
 
+def test_visbal_vortex_is_a_translating_solution():
+    # The paper's Gaussian vortex (Sec. 5.1) with uniform density: the Euler
+    # RHS equals -U_inf dU/dx (the field moves rigidly), to fourth order.
+    errs = []
+    for N in (64, 128, 256):
+        n = (N, N, 1)
+        U = inputs.visbal_vortex_state(n)
+        h = inputs.spacing(n, inputs.VISBAL_BOX)
+        R = flow.rhs_global(U, h, 2, flow.EULER, GAS)
+        dt = 1e-6
+        dUdt = (inputs.visbal_vortex_state(n, t=dt) - inputs.visbal_vortex_state(n, t=-dt)) / (2 * dt)
+        errs.append(np.abs(R - dUdt).max() / np.abs(dUdt).max())
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) > 3.7 and errs[-1] < 1e-3, (errs, orders)
+    # uniform density, divergence-free velocity, pressure from the balance
+    U = inputs.visbal_vortex_state((64, 64, 1))
+    assert np.all(U[0] == 1.0)
+    assert abs(U[1].mean() - 1.0) < 1e-12
+
+
 # ---------------------------------------------------------- TGV + diag
 def test_tgv_initial_invariants():
     n = (16, 16, 16)
