@@ -111,8 +111,8 @@ const char* atns_version(void);
  * not summing to n, L < 1 or L > 16, unknown enums, ndim == 2 with nz != 1)
  * before any device call.  stream: a hipStream_t, or NULL.  On success *out
  * owns all device buffers: state and RK registers, the delayed-level ring
- * (C + L levels of each block's boundary layers, C = 5 for AT4, 3 for AT2)
- * and tables. */
+ * (C + 2L - 1 levels of each block's boundary layers in modes AT and AS,
+ * C + L in SA with L > 1; C = 5 for AT4, 3 for AT2) and tables. */
 atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out);
 
 /* Free every resource of the context.  NULL is accepted. */
@@ -193,6 +193,27 @@ atns_status atns_rhs(atns_ctx* ctx, void* dev_R);
  * the ring with the FP64 weights W[e][k][:]), and the ring write of U^{n+1}
  * in the last stage. */
 atns_status atns_rk_step(atns_ctx* ctx, int32_t nsteps);
+
+/* Advance nsteps free-running asynchronous steps: the synchronization-
+ * avoiding algorithm (Alg. 3) with delays that arise from the run itself
+ * instead of a schedule.  One persistent workgroup per block advances its
+ * block without grid-wide barriers; after each step it publishes the ring
+ * level it has written.  At step n the delay from neighbour q is
+ * k = max(0, n - m), m the newest level q has published, and the block
+ * waits while k > L - 1 (with the guard of Alg. 3 this keeps k <= L - 1).
+ * Euler contexts in mode ATNS_AT or ATNS_AS with ATNS_RK4 or ATNS_LSERK2;
+ * the learned halo must be off; the history must hold C + L - 1 levels
+ * (ESTATE otherwise).  The ring keeps C + 2L - 1 levels so that a neighbour
+ * running L - 1 steps ahead never overwrites a level still needed.
+ * dev_log: caller-owned device int8 array [nsteps][nblocks][ATNS_NSLOTS]
+ * that receives the realized delays (-1 for slots the physics does not use);
+ * replaying them through atns_set_delays and atns_rk_step reproduces the
+ * run.  spin_limit: polls (each a short sleep) a workgroup waits for a
+ * neighbour before the run is abandoned; every workgroup then leaves, the
+ * call returns ATNS_ESTATE and the state must be set again.  EINVAL when
+ * the blocks outnumber the workgroups that fit on the device at once (all
+ * must be resident).  Synchronizes with the context stream. */
+atns_status atns_step_async(atns_ctx* ctx, int32_t nsteps, int64_t spin_limit, int8_t* dev_log);
 
 /* FP64 diagnostics of the current state (Sec. 5.2), into host_out[7]:
  * the five conserved totals sum U_v dV, the volume-averaged kinetic energy

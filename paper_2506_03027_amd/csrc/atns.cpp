@@ -93,6 +93,15 @@ struct atns_ctx {
   double dt = 0.0;
   int64_t step = 0;
   bool state_set = false;
+  // free-running asynchronous steps: progress counters, abort flag, the
+  // block-major tile list (for tiles async_tiles) and per-block ranges
+  int* d_prog = nullptr;
+  int* d_abort = nullptr;
+  TileDev* d_btiles = nullptr;
+  int* d_tile_begin = nullptr;
+  int* d_reg_begin = nullptr;
+  void* d_async_ps = nullptr;
+  int async_tiles[3] = {0, 0, 0};
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;   // reusable events
   size_t ev_used = 0;                // events recorded since the last read
@@ -653,7 +662,8 @@ void release(atns_ctx* c) {
                   c->d_partials, c->d_diag, c->hbuf, c->d_regions, c->d_work, c->d_faceinfo,
                   c->d_face_regions, c->d_face_chunks, c->d_W0at, c->net.params, c->net.w1, c->net.w2,
                   c->net.w3, c->d_adam_m, c->d_adam_v, c->d_grad, c->d_part, c->d_loss_part, c->d_loss,
-                  c->d_X, c->d_Y, c->d_counters};
+                  c->d_X, c->d_Y, c->d_counters, c->d_prog, c->d_abort, c->d_btiles, c->d_tile_begin,
+                  c->d_reg_begin, c->d_async_ps};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   c->ring = nullptr;
@@ -695,7 +705,11 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
   build_tiles(c, c->tile[0], c->tile[1], c->tile[2]);
   // SA keeps a delayed-level ring only when L > 1 (history for the learned
   // halo's training samples); the asynchronous modes always do.
-  c->D = (cfg->mode == ATNS_SA && cfg->L <= 1) ? 0 : c->C + cfg->L;
+  // SA keeps C + L levels (training history); the asynchronous modes keep
+  // C + 2L - 1, so that free-running steps (atns_step_async), where a
+  // neighbour may run L - 1 steps ahead of a reader, never overwrite a level
+  // the reader still needs.  Scheduled delays need only C + L.
+  c->D = cfg->mode == ATNS_SA ? (cfg->L <= 1 ? 0 : c->C + cfg->L) : c->C + 2 * cfg->L - 1;
 
   auto fail_free = [&](atns_status s, const std::string& m) {
     release(c);
@@ -1014,6 +1028,141 @@ atns_status atns_rk_step(atns_ctx* c, int32_t nsteps) {
   if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
   if (!(c->dt > 0)) return fail(c, ATNS_ESTATE, "dt not set");
   return c->esz == 4 ? do_steps<float>(c, nsteps) : do_steps<double>(c, nsteps);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device tables of the free-running kernel for the current tile shape.
+atns_status async_tables(atns_ctx* c) {
+  if (c->d_btiles && c->async_tiles[0] == c->tile[0] && c->async_tiles[1] == c->tile[1] &&
+      c->async_tiles[2] == c->tile[2])
+    return ATNS_OK;
+  std::vector<TileDev> bt;
+  std::vector<int> tb(1, 0), rb(1, 0);
+  for (int b = 0; b < c->nb; ++b) {
+    const BlockDev& B = c->blocks[b];
+    for (int z0 = 0; z0 < B.s[2]; z0 += c->tile[2])
+      for (int y0 = 0; y0 < B.s[1]; y0 += c->tile[1])
+        for (int x0 = 0; x0 < B.s[0]; x0 += c->tile[0]) {
+          TileDev t;
+          t.blk = b;
+          t.x0 = (short)x0;
+          t.y0 = (short)y0;
+          t.z0 = (short)z0;
+          t.nx = (short)std::min(c->tile[0], B.s[0] - x0);
+          t.ny = (short)std::min(c->tile[1], B.s[1] - y0);
+          t.nz = (short)std::min(c->tile[2], B.s[2] - z0);
+          bt.push_back(t);
+        }
+    tb.push_back((int)bt.size());
+  }
+  // regions are stored block by block (build_layout)
+  int r = 0;
+  for (int b = 0; b < c->nb; ++b) {
+    while (r < (int)c->regions.size() && c->regions[r].kidx / kNumSlots == b) ++r;
+    rb.push_back(r);
+  }
+  void* ptrs[] = {c->d_btiles, c->d_tile_begin, c->d_reg_begin};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  c->d_btiles = nullptr;
+  c->d_tile_begin = c->d_reg_begin = nullptr;
+  if (hipMalloc((void**)&c->d_btiles, bt.size() * sizeof(TileDev)) != hipSuccess ||
+      hipMalloc((void**)&c->d_tile_begin, tb.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc((void**)&c->d_reg_begin, rb.size() * sizeof(int)) != hipSuccess)
+    return fail(c, ATNS_ENOMEM, "free-running tables allocation failed");
+  HIP_TRY(c, hipMemcpy(c->d_btiles, bt.data(), bt.size() * sizeof(TileDev), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_tile_begin, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(c->d_reg_begin, rb.data(), rb.size() * sizeof(int), hipMemcpyHostToDevice));
+  for (int d = 0; d < 3; ++d) c->async_tiles[d] = c->tile[d];
+  return ATNS_OK;
+}
+
+template <typename T>
+atns_status step_async_impl(atns_ctx* c, int nsteps, long long spin_limit, int8_t* dev_log) {
+  const int stages = c->rk.stages;
+  AsyncArgs a{};
+  int per_cu = 0, cus = 0;
+  HIP_TRY(c, launch_euler_async<T>(nullptr, a, stages, c->tile[0], c->tile[1], c->stream, &per_cu));
+  HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  if ((long long)per_cu * cus < c->nb)
+    return fail(c, ATNS_EINVAL, "more blocks than workgroups that fit on the device at once (" +
+                                    std::to_string((long long)per_cu * cus) + ")");
+  atns_status st = async_tables(c);
+  if (st != ATNS_OK) return st;
+  if (!c->d_prog) {
+    if (hipMalloc((void**)&c->d_prog, c->nb * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&c->d_abort, sizeof(int)) != hipSuccess ||
+        hipMalloc(&c->d_async_ps, 4 * sizeof(StageParams<T>)) != hipSuccess)
+      return fail(c, ATNS_ENOMEM, "free-running state allocation failed");
+  }
+  std::vector<StageParams<T>> ps(stages);
+  for (int e = 0; e < stages; ++e) {
+    int kind = 0;
+    ps[e] = graph_stage_params<T>(c, e, &kind);
+    ps[e].nstep = nullptr;
+    ps[e].step_end = nullptr;
+    ps[e].done = nullptr;
+    ps[e].halo = c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT;
+  }
+  const std::vector<int> prog(c->nb, (int)c->step);
+  const int zero = 0;
+  HIP_TRY(c, hipMemcpyAsync(c->d_async_ps, ps.data(), stages * sizeof(StageParams<T>), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_prog, prog.data(), c->nb * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->d_abort, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  a.prog = c->d_prog;
+  a.abort = c->d_abort;
+  a.log = dev_log;
+  a.regions = c->d_regions;
+  a.reg_begin = c->d_reg_begin;
+  a.tiles = c->d_btiles;
+  a.tile_begin = c->d_tile_begin;
+  a.W = c->d_W;
+  a.n0 = c->step;
+  a.nsteps = nsteps;
+  a.nb = c->nb;
+  a.D = c->D;
+  a.L = c->cfg.L;
+  a.stale = c->cfg.mode == ATNS_AS ? 1 : 0;
+  a.slot_stride = c->slot_stride;
+  a.spin_limit = spin_limit;
+  HIP_TRY(c, launch_euler_async<T>((const StageParams<T>*)c->d_async_ps, a, stages, c->tile[0], c->tile[1],
+                                   c->stream, nullptr));
+  int aborted = 0;
+  HIP_TRY(c, hipMemcpyAsync(&aborted, c->d_abort, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->nstep_synced = false;
+  if (aborted) {
+    c->state_set = false;
+    return fail(c, ATNS_ESTATE, "a wait for a neighbour exceeded spin_limit polls; the blocks stopped at "
+                                "different steps, so the state must be set again");
+  }
+  c->step += nsteps;
+  return ATNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+atns_status atns_step_async(atns_ctx* c, int32_t nsteps, int64_t spin_limit, int8_t* dev_log) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  if (nsteps < 0 || (nsteps > 0 && !dev_log) || spin_limit < 1)
+    return fail(c, ATNS_EINVAL, "need nsteps >= 0, a delay log for nsteps > 0 and spin_limit >= 1");
+  if (c->cfg.physics != ATNS_EULER) return fail(c, ATNS_EINVAL, "free-running steps are built for Euler contexts");
+  if (c->cfg.mode == ATNS_SA) return fail(c, ATNS_EINVAL, "free-running steps need mode ATNS_AT or ATNS_AS");
+  if (c->rk.stages != 4 && c->rk.stages != 2)
+    return fail(c, ATNS_EINVAL, "free-running steps need ATNS_RK4 or ATNS_LSERK2");
+  if (c->mlp_on) return fail(c, ATNS_EINVAL, "the learned halo is not applied in free-running steps");
+  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+  if (!(c->dt > 0)) return fail(c, ATNS_ESTATE, "dt not set");
+  if (c->step < c->C + c->cfg.L - 1) return fail(c, ATNS_ESTATE, "history shorter than C + L - 1 levels");
+  if (nsteps == 0) return ATNS_OK;
+  return c->esz == 4 ? step_async_impl<float>(c, nsteps, spin_limit, dev_log)
+                     : step_async_impl<double>(c, nsteps, spin_limit, dev_log);
 }
 
 atns_status atns_reduce(atns_ctx* c, double* host_out) {

@@ -21,6 +21,45 @@ __device__ __forceinline__ int wrap(int g, int n) {
   return g;
 }
 
+// Stage halos of one halo point i of region rg for delay k (Eq. 7 with
+// Eqs. 8-15): read the C delayed levels U^{n-k-l} of the neighbour's layer
+// from the ring (slots slot_now - k - l mod D) and write the S stage values
+//   Uhat^(e) = sum_l W[e][k][l] U^{n-k-l}   (FP64 arithmetic; AT)
+// or the stale level itself (AS, STALE).
+template <typename T, int S, int CL, bool STALE>
+__device__ __forceinline__ void assemble_halo_point(const T* __restrict__ ring, T* __restrict__ halo,
+                                                    const HaloRegion& rg, int i, int k, int slot_now, int D,
+                                                    const double* __restrict__ W, int L, long long slot_stride,
+                                                    long long halo_stride) {
+  int sl[CL];
+#pragma unroll
+  for (int l = 0; l < CL; ++l) {
+    int q = slot_now - k - l;
+    sl[l] = q + ((q < 0) ? D : 0);
+  }
+  for (int v = 0; v < 5; ++v) {
+    const long long so = rg.src + (long long)v * rg.npts + i;
+    const long long dof = rg.dst + (long long)v * rg.npts + i;
+    if (STALE) {
+      const T x = ring[(long long)sl[0] * slot_stride + so];
+#pragma unroll
+      for (int e = 0; e < S; ++e) halo[e * halo_stride + dof] = x;
+      continue;
+    }
+    double lev[CL];
+#pragma unroll
+    for (int l = 0; l < CL; ++l) lev[l] = (double)ring[(long long)sl[l] * slot_stride + so];
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+      const double* w = W + ((long long)e * L + k) * CL;
+      double a = 0.0;
+#pragma unroll
+      for (int l = 0; l < CL; ++l) a = fma(w[l], lev[l], a);
+      halo[e * halo_stride + dof] = (T)a;
+    }
+  }
+}
+
 // Stage parameters with the step-dependent fields resolved from the device
 // step counter when present.
 template <typename T>

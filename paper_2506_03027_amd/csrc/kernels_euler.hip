@@ -44,6 +44,20 @@ __device__ __forceinline__ void euler_flux(const T u[5], int d, T gm1, T f[5]) {
   f[4] = (u[4] + p) * vel;
 }
 
+// LDS of a tile: the block descriptor and the x/y flux planes.  One object
+// per (T, TX, TY), shared by every stage kind a kernel instantiates.
+template <typename T, int TX, int TY>
+struct EulerLds {
+  BlockDev B;
+  T F[2][5][TY][TX + 4];
+  T G[2][5][TY + 4][TX];
+};
+template <typename T, int TX, int TY>
+__device__ __forceinline__ EulerLds<T, TX, TY>& euler_lds() {
+  __shared__ EulerLds<T, TX, TY> s;
+  return s;
+}
+
 template <typename T, int TX, int TY, int KIND>
 __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDev t) {
   // every apron point (4 per tile row and column) has a thread of its own
@@ -52,9 +66,9 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
   // The block descriptor lives in LDS for the whole kernel: re-reading it from
   // global memory inside the plane loop would make every such load wait for
   // all outstanding (prefetch) loads.
-  __shared__ BlockDev sB;
-  stage_block(p.blocks + t.blk, &sB);
-  const BlockDev* __restrict__ B = &sB;
+  EulerLds<T, TX, TY>& lds = euler_lds<T, TX, TY>();
+  stage_block(p.blocks + t.blk, &lds.B);
+  const BlockDev* __restrict__ B = &lds.B;
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
   const bool act = (tx < t.nx) && (ty < t.ny);
@@ -65,8 +79,8 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
   // central-difference weights of the inner and outer neighbour pairs
   const T w1 = p.cd2 ? T(1) : T(8), w2 = p.cd2 ? T(0) : T(1);
 
-  __shared__ T sF[2][5][TY][TX + 4];
-  __shared__ T sG[2][5][TY + 4][TX];
+  auto& sF = lds.F;
+  auto& sG = lds.G;
 
   // Apron role: x-apron columns {-2,-1,nx,nx+1} x ny rows, then the y-apron.
   const int nxa = 4 * t.ny, nya = 4 * t.nx;
@@ -201,6 +215,141 @@ __global__ void __launch_bounds__(TX* TY)
     euler_tile<T, TX, TY, KIND>(sp, bt.t);
   }
 }
+
+// Free-running asynchronous steps: workgroup b owns block b for the whole
+// run and advances it without any grid-wide barrier.  Per step n:
+//  1. the delay from each neighbour is what that neighbour has published:
+//     k = max(0, n - prog[q]); while k > L - 1 the workgroup waits (bounded
+//     by spin_limit polls; past it, *abort is set and every workgroup
+//     leaves).  This is the synchronization-avoiding rule of Alg. 3 with
+//     delays that come from the run itself instead of a schedule;
+//  2. the block's stage halos are assembled from the ring with those delays;
+//  3. the s stages run over the block's tiles, the last one writing ring
+//     level n+1 of the block's boundary layers;
+//  4. the block publishes prog[b] = n + 1.
+// Ordering across workgroups: every thread fences at agent scope (release)
+// before the publishing store; a reader polls with relaxed loads and fences
+// (acquire) once the level it needs is published, before the workgroup
+// barrier behind which all its threads read the ring, so ring data written
+// on another XCD is seen.  A neighbour can
+// run at most L - 1 steps ahead of a reader, so a ring of C + 2L - 1 levels
+// keeps every level a reader may still need.
+template <typename T, int TX, int TY, int S, int CL>
+__global__ void __launch_bounds__(TX* TY)
+    euler_async_kernel(const StageParams<T>* __restrict__ ps, const AsyncArgs a) {
+  __shared__ StageParams<T> sp;
+  __shared__ int sk[kNumSlots];
+  __shared__ int sabort;
+  const int b = blockIdx.x;
+  const BlockDev* __restrict__ Bg = ps[0].blocks + b;
+  for (int it = 0; it < a.nsteps; ++it) {
+    const long long n = a.n0 + it;
+    // 1. delays from the neighbours' published levels
+    if (threadIdx.x == 0) sabort = 0;
+    __syncthreads();
+    if (threadIdx.x < kNumSlots) {
+      const int s = threadIdx.x;
+      int k = -1;
+      if (Bg->hoff[s] >= 0) {
+        const int q = Bg->nbr[s];
+        for (long long poll = 0;; ++poll) {
+          const int m = __hip_atomic_load(a.prog + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const long long kk = n - m;
+          if (kk <= a.L - 1) {
+            k = kk < 0 ? 0 : (int)kk;
+            // pairs with the neighbour's release: its ring level m is visible
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            break;
+          }
+          if (poll >= a.spin_limit || __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicOr(&sabort, 1);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      sk[s] = k;
+      a.log[((long long)it * a.nb + b) * kNumSlots + s] = (int8_t)k;
+    }
+    __syncthreads();
+    if (sabort) return;
+    // 2. the block's stage halos of step n
+    const int slot_now = (int)(n % a.D);
+    for (int r = a.reg_begin[b]; r < a.reg_begin[b + 1]; ++r) {
+      const HaloRegion rg = a.regions[r];
+      const int k = sk[rg.kidx - b * kNumSlots];
+      for (int i = threadIdx.x; i < rg.npts; i += blockDim.x) {
+        if (a.stale)
+          assemble_halo_point<T, S, CL, true>(ps[0].ring, (T*)ps[0].hbuf, rg, i, k, slot_now, a.D, a.W, a.L,
+                                             a.slot_stride, a.slot_stride);
+        else
+          assemble_halo_point<T, S, CL, false>(ps[0].ring, (T*)ps[0].hbuf, rg, i, k, slot_now, a.D, a.W, a.L,
+                                              a.slot_stride, a.slot_stride);
+      }
+    }
+    __syncthreads();
+    // 3. the stages over the block's tiles
+    for (int e = 0; e < S; ++e) {
+      stage_struct(ps + e, &sp);
+      if (threadIdx.x == 0) sp.slot_now = slot_now;
+      __syncthreads();
+      for (int t = a.tile_begin[b]; t < a.tile_begin[b + 1]; ++t) {
+        const TileDev td = a.tiles[t];
+        if constexpr (S == 2) {
+          if (e == 0)
+            euler_tile<T, TX, TY, kLSFirst>(sp, td);
+          else
+            euler_tile<T, TX, TY, kLSMid>(sp, td);
+        } else {
+          if (e == 0)
+            euler_tile<T, TX, TY, kRK4First>(sp, td);
+          else if (e == S - 1)
+            euler_tile<T, TX, TY, kRK4Last>(sp, td);
+          else
+            euler_tile<T, TX, TY, kRK4Mid>(sp, td);
+        }
+        __syncthreads();
+      }
+    }
+    // 4. publish ring level n + 1
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(a.prog + b, (int)(n + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename T, int TX, int TY>
+hipError_t launch_euler_async_shape(const StageParams<T>* ps, const AsyncArgs& a, int stages, hipStream_t s,
+                                    int* resident) {
+  const void* fn = stages == 2 ? (const void*)euler_async_kernel<T, TX, TY, 2, 3>
+                               : (const void*)euler_async_kernel<T, TX, TY, 4, 5>;
+  if (resident) return hipOccupancyMaxActiveBlocksPerMultiprocessor(resident, fn, TX * TY, 0);
+  dim3 g(a.nb), b(TX * TY);
+  if (stages == 2)
+    euler_async_kernel<T, TX, TY, 2, 3><<<g, b, 0, s>>>(ps, a);
+  else
+    euler_async_kernel<T, TX, TY, 4, 5><<<g, b, 0, s>>>(ps, a);
+  return hipGetLastError();
+}
+
+// With resident != nullptr: only report how many workgroups of the kernel
+// fit on one CU (nothing is launched).
+template <typename T>
+hipError_t launch_euler_async(const StageParams<T>* ps, const AsyncArgs& a, int stages, int tx, int ty,
+                              hipStream_t s, int* resident) {
+  if (stages != 2 && stages != 4) return hipErrorInvalidValue;
+  if (tx == 16 && ty == 16) return launch_euler_async_shape<T, 16, 16>(ps, a, stages, s, resident);
+  if (tx == 32 && ty == 8) return launch_euler_async_shape<T, 32, 8>(ps, a, stages, s, resident);
+  if (tx == 16 && ty == 8) return launch_euler_async_shape<T, 16, 8>(ps, a, stages, s, resident);
+  if (tx == 64 && ty == 8) return launch_euler_async_shape<T, 64, 8>(ps, a, stages, s, resident);
+  if (tx == 32 && ty == 16) return launch_euler_async_shape<T, 32, 16>(ps, a, stages, s, resident);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_euler_async<float>(const StageParams<float>*, const AsyncArgs&, int, int, int, hipStream_t,
+                                              int*);
+template hipError_t launch_euler_async<double>(const StageParams<double>*, const AsyncArgs&, int, int, int,
+                                               hipStream_t, int*);
 
 template <typename T, int TX, int TY>
 hipError_t launch_euler_batch_shape(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind,

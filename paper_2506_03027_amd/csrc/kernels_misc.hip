@@ -105,33 +105,7 @@ __global__ void __launch_bounds__(kHaloChunk)
   }
   const int i = wk.start + threadIdx.x;
   if (i >= rg.npts) return;
-  int sl[CL];
-#pragma unroll
-  for (int l = 0; l < CL; ++l) {
-    int q = slot_now - k - l;
-    sl[l] = q + ((q < 0) ? D : 0);
-  }
-  for (int v = 0; v < 5; ++v) {
-    const long long so = rg.src + (long long)v * rg.npts + i;
-    const long long dof = rg.dst + (long long)v * rg.npts + i;
-    if (STALE) {
-      const T x = ring[(long long)sl[0] * slot_stride + so];
-#pragma unroll
-      for (int e = 0; e < S; ++e) halo[e * halo_stride + dof] = x;
-      continue;
-    }
-    double lev[CL];
-#pragma unroll
-    for (int l = 0; l < CL; ++l) lev[l] = (double)ring[(long long)sl[l] * slot_stride + so];
-#pragma unroll
-    for (int e = 0; e < S; ++e) {
-      const double* w = W + ((long long)e * L + k) * CL;
-      double a = 0.0;
-#pragma unroll
-      for (int l = 0; l < CL; ++l) a = fma(w[l], lev[l], a);
-      halo[e * halo_stride + dof] = (T)a;
-    }
-  }
+  assemble_halo_point<T, S, CL, STALE>(ring, halo, rg, i, k, slot_now, D, W, L, slot_stride, halo_stride);
 }
 
 template <typename T>

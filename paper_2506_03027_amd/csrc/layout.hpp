@@ -89,6 +89,32 @@ struct TileDev {
   short nx, ny, nz;         // tile extent (nx == 0: padding tile, no work)
 };
 
+// Free-running asynchronous steps (one persistent workgroup per block).
+// Block b publishes prog[b] = m once ring level m of its boundary layers is
+// written; a reader at step n takes from neighbour q the newest published
+// level m = prog[q], i.e. the delay k = max(0, n - m), and waits while
+// k > L - 1.  A wait longer than spin_limit polls sets *abort, and every
+// workgroup then leaves.  log receives the realized delays,
+// [step][block][slot] (-1 for unused slots).
+struct AsyncArgs {
+  int* prog;
+  int* abort;
+  int8_t* log;
+  const HaloRegion* regions;
+  const int* reg_begin;     // [nb + 1]: block b owns regions reg_begin[b] ..
+  const TileDev* tiles;     // block-major tile list
+  const int* tile_begin;    // [nb + 1]: block b owns tiles tile_begin[b] ..
+  const double* W;          // halo weights [s][L][C]
+  long long n0;             // step of the state at entry
+  int nsteps;
+  int nb;
+  int D;
+  int L;
+  int stale;                // AS: the stale level instead of the AT sum
+  long long slot_stride;
+  long long spin_limit;
+};
+
 // A tile of one member of a batch.
 struct BatchTile {
   int inst;      // member index
