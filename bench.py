@@ -439,6 +439,93 @@ def mlp_main(a, torch):
     print(json.dumps(out))
 
 
+def free_running_main(a, torch):
+    """Free-running asynchronous steps (delays realized by the run) against
+    the scheduled SAA steps of the same workload and tiles, both FP32 from
+    the same warm state; the free-running run is then replayed on the
+    scheduled path with its logged delays, and the two results compared."""
+    w = inputs.WORKLOADS[a.workload]
+    stages = n_stages(w)
+    npts = w["n"][0] * w["n"][1] * w["n"][2]
+    U0 = initial_state(w)
+    dt = inputs.cfl_dt(U0, w["n"], w["length"], w["ndim"], 1.4, w["cfl"])
+    warmup = max(a.warmup, n_levels(w) + w["L"])
+
+    def start():
+        g = make_solver(w, atns.F32)
+        g.set_dt(dt)
+        g.set_state(torch.from_numpy(U0))
+        tiles = g.autotune(reps=10, cache=TUNE_CACHE)
+        g.step(warmup)
+        return g, tiles
+
+    g, tiles = start()
+    ms_sched = time_steps(torch, g, a.steps)
+    g.close()
+    # tile shape of the free-running kernel: one workgroup walks all tiles of
+    # its block, so the best shape differs from the scheduled one; the
+    # fastest of a few over 5 steps
+    bx = w["n"][0] // w["nblk"][0]
+    best = None
+    for sh in ((32, 16, 32), (32, 16, 16), (16, 16, 16), (16, 16, 8)):
+        if sh[0] > bx:
+            continue
+        g, _ = start()
+        g.set_tiles(*sh)
+        g.step_async(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step_async(5)
+        el = time.perf_counter() - t0
+        g.close()
+        if best is None or el < best[0]:
+            best = (el, sh)
+    free_tiles = best[1]
+    g, _ = start()
+    g.set_tiles(*free_tiles)
+    log0 = g.step_async(2)               # first launch (code load) outside the timing
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    log = g.step_async(a.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_free = e0.elapsed_time(e1)
+    A = g.get_state().double()
+    g.close()
+    r, _ = start()
+    r.set_tiles(*free_tiles)
+    r.set_delays(warmup, np.concatenate([log0, log]))
+    r.step(2 + a.steps)
+    B = r.get_state().double()
+    r.close()
+    used = log[log >= 0]
+    hist = np.bincount(used.ravel(), minlength=w["L"]).tolist()
+    out = {
+        "metric": "grid-point-stage updates/s (FP32, free-running asynchronous steps)",
+        "value": npts * stages * a.steps / (ms_free * 1e-3),
+        "unit": "grid-point-stage/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": warmup + 2,
+        "ms_per_step": ms_free / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "grid": list(w["n"]), "blocks": list(w["nblk"]),
+                   "physics": w["physics"], "rk": w["rk"], "mode": w["mode"], "L": w["L"],
+                   "tiles": list(free_tiles), "scheduled_tiles": list(tiles),
+                   "workgroups": int(np.prod(w["nblk"]))},
+        "scheduled_saa": {"value": npts * stages * a.steps / (ms_sched * 1e-3), "ms_per_step": ms_sched / a.steps},
+        "realized_delays": {"histogram": hist, "mean": float(used.mean())},
+        "replay_rel_max": float((A - B).abs().max() / B.abs().max()),
+        "kernel_hash": kernel_source_hash(),
+    }
+    print(json.dumps(out))
+
+
 def series_main(a, torch):
     """The workload run for a.series steps with the FP64 diagnostics (conserved
     totals, kinetic energy, enstrophy) reduced on the GPU after every step."""
@@ -519,6 +606,9 @@ def main():
     ap.add_argument("--series-out", default=None, help="CSV file for --series")
     ap.add_argument("--series-ref", action="store_true",
                     help="with --series: also run the FP64 synchronous solver and compare the series")
+    ap.add_argument("--free-running", action="store_true",
+                    help="free-running asynchronous steps (one persistent workgroup per block) next to the "
+                         "scheduled graph-captured steps on the same workload")
     ap.add_argument("--mlp", action="store_true",
                     help="learned-halo run (Taylor-Green workloads): train, then AT with and without it")
     a = ap.parse_args()
@@ -533,6 +623,9 @@ def main():
         return
     if a.mlp:
         mlp_main(a, torch)
+        return
+    if a.free_running:
+        free_running_main(a, torch)
         return
     if a.series:
         series_main(a, torch)

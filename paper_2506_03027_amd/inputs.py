@@ -170,6 +170,11 @@ WORKLOADS = {
     "vortex3d_128_lserk2": dict(n=(128, 128, 128), length=(10.0, 10.0, 10.0), ndim=3,
                                 nblk=(4, 4, 4), physics="euler", rk="lserk2", mode="at",
                                 algo="saa", L=4, cfl=0.02, precision="f32"),
+    # the vortex grid in 8 x 8 x 8 blocks of 16^3 (free-running steps: one
+    # resident workgroup per block)
+    "vortex3d_128_b16": dict(n=(128, 128, 128), length=(10.0, 10.0, 10.0), ndim=3,
+                             nblk=(8, 8, 8), physics="euler", rk="rk4", mode="at",
+                             algo="saa", L=4, cfl=0.02, precision="f32"),
     "tgv_256": dict(n=(256, 256, 256), length=(2 * math.pi,) * 3, ndim=3,
                     nblk=(16, 16, 8), physics="ns", rk="rk4", mode="at",
                     algo="saa", L=4, re=1600.0, mach=0.1, cfl=0.02,
