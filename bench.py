@@ -467,7 +467,9 @@ def free_running_main(a, torch):
     # fastest of a few over 5 steps
     bx = w["n"][0] // w["nblk"][0]
     best = None
-    for sh in ((32, 16, 32), (32, 16, 16), (16, 16, 16), (16, 16, 8)):
+    cands = (((16, 16, 32), (16, 8, 32), (32, 8, 32), (16, 16, 16)) if w["physics"] == "ns"
+             else ((32, 16, 32), (32, 16, 16), (16, 16, 16), (16, 16, 8)))
+    for sh in cands:
         if sh[0] > bx:
             continue
         g, _ = start()

@@ -201,7 +201,8 @@ atns_status atns_rk_step(atns_ctx* ctx, int32_t nsteps);
  * level it has written.  At step n the delay from neighbour q is
  * k = max(0, n - m), m the newest level q has published, and the block
  * waits while k > L - 1 (with the guard of Alg. 3 this keeps k <= L - 1).
- * Euler contexts in mode ATNS_AT or ATNS_AS with ATNS_RK4 or ATNS_LSERK2;
+ * Euler or 3-D Navier-Stokes contexts in mode ATNS_AT or ATNS_AS with
+ * ATNS_RK4 or ATNS_LSERK2;
  * the learned halo must be off; the history must hold C + L - 1 levels
  * (ESTATE otherwise).  The ring keeps C + 2L - 1 levels so that a neighbour
  * running L - 1 steps ahead never overwrites a level still needed.

@@ -1085,7 +1085,9 @@ atns_status step_async_impl(atns_ctx* c, int nsteps, long long spin_limit, int8_
   const int stages = c->rk.stages;
   AsyncArgs a{};
   int per_cu = 0, cus = 0;
-  HIP_TRY(c, launch_euler_async<T>(nullptr, a, stages, c->tile[0], c->tile[1], c->stream, &per_cu));
+  const bool ns = c->cfg.physics == ATNS_NS;
+  HIP_TRY(c, ns ? launch_ns_async<T>(nullptr, a, stages, c->tile[0], c->tile[1], c->stream, &per_cu)
+                : launch_euler_async<T>(nullptr, a, stages, c->tile[0], c->tile[1], c->stream, &per_cu));
   HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
   if ((long long)per_cu * cus < c->nb)
     return fail(c, ATNS_EINVAL, "more blocks than workgroups that fit on the device at once (" +
@@ -1129,8 +1131,9 @@ atns_status step_async_impl(atns_ctx* c, int nsteps, long long spin_limit, int8_
   a.stale = c->cfg.mode == ATNS_AS ? 1 : 0;
   a.slot_stride = c->slot_stride;
   a.spin_limit = spin_limit;
-  HIP_TRY(c, launch_euler_async<T>((const StageParams<T>*)c->d_async_ps, a, stages, c->tile[0], c->tile[1],
-                                   c->stream, nullptr));
+  const StageParams<T>* dps = (const StageParams<T>*)c->d_async_ps;
+  HIP_TRY(c, ns ? launch_ns_async<T>(dps, a, stages, c->tile[0], c->tile[1], c->stream, nullptr)
+                : launch_euler_async<T>(dps, a, stages, c->tile[0], c->tile[1], c->stream, nullptr));
   int aborted = 0;
   HIP_TRY(c, hipMemcpyAsync(&aborted, c->d_abort, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1152,7 +1155,8 @@ atns_status atns_step_async(atns_ctx* c, int32_t nsteps, int64_t spin_limit, int
   if (!c) return fail(c, ATNS_EINVAL, "null context");
   if (nsteps < 0 || (nsteps > 0 && !dev_log) || spin_limit < 1)
     return fail(c, ATNS_EINVAL, "need nsteps >= 0, a delay log for nsteps > 0 and spin_limit >= 1");
-  if (c->cfg.physics != ATNS_EULER) return fail(c, ATNS_EINVAL, "free-running steps are built for Euler contexts");
+  if (c->cfg.physics == ATNS_NS && c->cfg.ndim != 3)
+    return fail(c, ATNS_EINVAL, "free-running Navier-Stokes steps are built for 3-D contexts");
   if (c->cfg.mode == ATNS_SA) return fail(c, ATNS_EINVAL, "free-running steps need mode ATNS_AT or ATNS_AS");
   if (c->rk.stages != 4 && c->rk.stages != 2)
     return fail(c, ATNS_EINVAL, "free-running steps need ATNS_RK4 or ATNS_LSERK2");

@@ -350,4 +350,94 @@ __device__ __forceinline__ void epilogue(const StageParams<T>& p, long long g, c
   }
 }
 
+// Free-running asynchronous steps (the body shared by the Euler and
+// Navier-Stokes kernels): workgroup b owns block b for the whole
+// run and advances it without any grid-wide barrier.  Per step n:
+//  1. the delay from each neighbour is what that neighbour has published:
+//     k = max(0, n - prog[q]); while k > L - 1 the workgroup waits (bounded
+//     by spin_limit polls; past it, *abort is set and every workgroup
+//     leaves).  This is the synchronization-avoiding rule of Alg. 3 with
+//     delays that come from the run itself instead of a schedule;
+//  2. the block's stage halos are assembled from the ring with those delays;
+//  3. the s stages run over the block's tiles, the last one writing ring
+//     level n+1 of the block's boundary layers;
+//  4. the block publishes prog[b] = n + 1.
+// Ordering across workgroups: every thread fences at agent scope (release)
+// before the publishing store; a reader polls with relaxed loads and fences
+// (acquire) once the level it needs is published, before the workgroup
+// barrier behind which all its threads read the ring, so ring data written
+// on another XCD is seen.  A neighbour can run at most L - 1 steps ahead of
+// a reader, so a ring of C + 2L - 1 levels keeps every level a reader may
+// still need.
+template <typename T, int S, int CL, typename TileFn>
+__device__ __forceinline__ void async_run(const StageParams<T>* __restrict__ ps, const AsyncArgs& a,
+                                          StageParams<T>& sp, TileFn&& tile) {
+  __shared__ int sk[kNumSlots];
+  __shared__ int sabort;
+  const int b = blockIdx.x;
+  const BlockDev* __restrict__ Bg = ps[0].blocks + b;
+  for (int it = 0; it < a.nsteps; ++it) {
+    const long long n = a.n0 + it;
+    // 1. delays from the neighbours' published levels
+    if (threadIdx.x == 0) sabort = 0;
+    __syncthreads();
+    if (threadIdx.x < kNumSlots) {
+      const int s = threadIdx.x;
+      int k = -1;
+      if (Bg->hoff[s] >= 0) {
+        const int q = Bg->nbr[s];
+        for (long long poll = 0;; ++poll) {
+          const int m = __hip_atomic_load(a.prog + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const long long kk = n - m;
+          if (kk <= a.L - 1) {
+            k = kk < 0 ? 0 : (int)kk;
+            // pairs with the neighbour's release: its ring level m is visible
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            break;
+          }
+          if (poll >= a.spin_limit || __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicOr(&sabort, 1);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      sk[s] = k;
+      a.log[((long long)it * a.nb + b) * kNumSlots + s] = (int8_t)k;
+    }
+    __syncthreads();
+    if (sabort) return;
+    // 2. the block's stage halos of step n
+    const int slot_now = (int)(n % a.D);
+    for (int r = a.reg_begin[b]; r < a.reg_begin[b + 1]; ++r) {
+      const HaloRegion rg = a.regions[r];
+      const int k = sk[rg.kidx - b * kNumSlots];
+      for (int i = threadIdx.x; i < rg.npts; i += blockDim.x) {
+        if (a.stale)
+          assemble_halo_point<T, S, CL, true>(ps[0].ring, (T*)ps[0].hbuf, rg, i, k, slot_now, a.D, a.W, a.L,
+                                             a.slot_stride, a.slot_stride);
+        else
+          assemble_halo_point<T, S, CL, false>(ps[0].ring, (T*)ps[0].hbuf, rg, i, k, slot_now, a.D, a.W, a.L,
+                                              a.slot_stride, a.slot_stride);
+      }
+    }
+    __syncthreads();
+    // 3. the stages over the block's tiles
+    for (int e = 0; e < S; ++e) {
+      stage_struct(ps + e, &sp);
+      if (threadIdx.x == 0) sp.slot_now = slot_now;
+      __syncthreads();
+      for (int t = a.tile_begin[b]; t < a.tile_begin[b + 1]; ++t) {
+        tile(sp, a.tiles[t], e);
+        __syncthreads();
+      }
+    }
+    // 4. publish ring level n + 1
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(a.prog + b, (int)(n + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 }  // namespace atns

@@ -31,6 +31,24 @@
 
 namespace atns {
 
+// LDS of a tile: the block descriptor, primitive planes, x/y flux planes,
+// the z-flux ring and the x/y divergence planes.  One object per (T, TX, TY),
+// shared by every stage kind a kernel instantiates.
+template <typename T, int TX, int TY>
+struct NsLds {
+  BlockDev B;
+  T P[2][4][TY + 8][TX + 8];   // u, v, w, T of plane m (double-buffered)
+  T FX[2][5][TY][TX + 4];      // F - Fv_x/Re on the x-cross of plane m
+  T FY[2][5][TY + 4][TX];      // G - Fv_y/Re on the y-cross of plane m
+  T H[4][5][TY][TX];           // z-fluxes of the last four gradient planes
+  T XY[2][5][TY][TX];          // x/y divergence of the tile's points
+};
+template <typename T, int TX, int TY>
+__device__ __forceinline__ NsLds<T, TX, TY>& ns_lds() {
+  __shared__ NsLds<T, TX, TY> s;
+  return s;
+}
+
 template <typename T, int TX, int TY, int KIND, int NDIM>
 __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t) {
   constexpr int EX = TX + 8, EY = TY + 8;
@@ -39,9 +57,9 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
   // The block descriptor lives in LDS for the whole kernel: re-reading it from
   // global memory inside the plane loop would make every such load wait for
   // all outstanding (prefetch) loads.
-  __shared__ BlockDev sB;
-  stage_block(p.blocks + t.blk, &sB);
-  const BlockDev* __restrict__ B = &sB;
+  NsLds<T, TX, TY>& lds = ns_lds<T, TX, TY>();
+  stage_block(p.blocks + t.blk, &lds.B);
+  const BlockDev* __restrict__ B = &lds.B;
   const int tid = threadIdx.x;
   // Thread -> footprint point, grouped so that whole waves share a role: the
   // TX x TY tile first, then the 2-point cross apron, then the outer apron
@@ -110,14 +128,14 @@ __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t
   const T w1 = p.cd2 ? T(1) : T(8), w2 = p.cd2 ? T(0) : T(1);
   const T two3 = (T)(2.0 / 3.0);
 
-  __shared__ T sP[2][4][EY][EX];        // u, v, w, T of plane m (double-buffered)
-  __shared__ T sFX[2][5][TY][TX + 4];   // F - Fv_x/Re on the x-cross of plane m
-  __shared__ T sFY[2][5][TY + 4][TX];   // G - Fv_y/Re on the y-cross of plane m
+  auto& sP = lds.P;     // u, v, w, T of plane m (double-buffered)
+  auto& sFX = lds.FX;   // F - Fv_x/Re on the x-cross of plane m
+  auto& sFY = lds.FY;   // G - Fv_y/Re on the y-cross of plane m
   // z-fluxes of the last four gradient planes at the tile, plane q in slot
   // q mod 4; each thread reads only its own cells (no barrier needed)
-  __shared__ T sH[4][5][TY][TX];
+  auto& sH = lds.H;
   // x/y divergence of the tile's points, by plane parity (3D)
-  __shared__ T sXY[2][5][TY][TX];
+  auto& sXY = lds.XY;
 
   // queues: q*[j] holds plane f-4+j; rr[j] holds the density of plane f-2+j
   // (pressure and energy at the gradient plane are rebuilt from rho, T and u)
@@ -362,6 +380,59 @@ __global__ void __launch_bounds__((TX + 8) * (TY + 8))
     ns_tile<T, TX, TY, KIND, 3>(sp, bt.t);
   }
 }
+
+// Free-running asynchronous steps of a 3-D Navier-Stokes context (see
+// async_run).
+template <typename T, int TX, int TY, int S, int CL>
+__global__ void __launch_bounds__((TX + 8) * (TY + 8))
+    ns_async_kernel(const StageParams<T>* __restrict__ ps, const AsyncArgs a) {
+  __shared__ StageParams<T> sp;
+  async_run<T, S, CL>(ps, a, sp, [](const StageParams<T>& q, const TileDev& td, int e) {
+    if constexpr (S == 2) {
+      if (e == 0)
+        ns_tile<T, TX, TY, kLSFirst, 3>(q, td);
+      else
+        ns_tile<T, TX, TY, kLSMid, 3>(q, td);
+    } else {
+      if (e == 0)
+        ns_tile<T, TX, TY, kRK4First, 3>(q, td);
+      else if (e == S - 1)
+        ns_tile<T, TX, TY, kRK4Last, 3>(q, td);
+      else
+        ns_tile<T, TX, TY, kRK4Mid, 3>(q, td);
+    }
+  });
+}
+
+template <typename T, int TX, int TY>
+hipError_t launch_ns_async_shape(const StageParams<T>* ps, const AsyncArgs& a, int stages, hipStream_t s,
+                                 int* resident) {
+  const void* fn = stages == 2 ? (const void*)ns_async_kernel<T, TX, TY, 2, 3>
+                               : (const void*)ns_async_kernel<T, TX, TY, 4, 5>;
+  if (resident) return hipOccupancyMaxActiveBlocksPerMultiprocessor(resident, fn, (TX + 8) * (TY + 8), 0);
+  dim3 g(a.nb), b((TX + 8) * (TY + 8));
+  if (stages == 2)
+    ns_async_kernel<T, TX, TY, 2, 3><<<g, b, 0, s>>>(ps, a);
+  else
+    ns_async_kernel<T, TX, TY, 4, 5><<<g, b, 0, s>>>(ps, a);
+  return hipGetLastError();
+}
+
+// With resident != nullptr: only report how many workgroups of the kernel
+// fit on one CU (nothing is launched).
+template <typename T>
+hipError_t launch_ns_async(const StageParams<T>* ps, const AsyncArgs& a, int stages, int tx, int ty, hipStream_t s,
+                           int* resident) {
+  if (stages != 2 && stages != 4) return hipErrorInvalidValue;
+  if (tx == 16 && ty == 16) return launch_ns_async_shape<T, 16, 16>(ps, a, stages, s, resident);
+  if (tx == 32 && ty == 8) return launch_ns_async_shape<T, 32, 8>(ps, a, stages, s, resident);
+  if (tx == 16 && ty == 8) return launch_ns_async_shape<T, 16, 8>(ps, a, stages, s, resident);
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_ns_async<float>(const StageParams<float>*, const AsyncArgs&, int, int, int, hipStream_t,
+                                           int*);
+template hipError_t launch_ns_async<double>(const StageParams<double>*, const AsyncArgs&, int, int, int, hipStream_t,
+                                            int*);
 
 template <typename T, int TX, int TY>
 hipError_t launch_ns_batch_shape(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind,

@@ -6,9 +6,12 @@
 
 namespace atns {
 
-// Free-running asynchronous steps of an Euler context (one persistent
-// workgroup per block); with resident set, only the number of workgroups
-// that fit on one CU is returned.
+// Free-running asynchronous steps (one persistent workgroup per block) of a
+// 3-D Navier-Stokes or an Euler context; with resident set, only the number
+// of workgroups that fit on one CU is returned.
+template <typename T>
+hipError_t launch_ns_async(const StageParams<T>* ps, const AsyncArgs& a, int stages, int tx, int ty, hipStream_t s,
+                           int* resident = nullptr);
 template <typename T>
 hipError_t launch_euler_async(const StageParams<T>* ps, const AsyncArgs& a, int stages, int tx, int ty,
                               hipStream_t s, int* resident = nullptr);

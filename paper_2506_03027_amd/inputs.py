@@ -179,6 +179,12 @@ WORKLOADS = {
                     nblk=(16, 16, 8), physics="ns", rk="rk4", mode="at",
                     algo="saa", L=4, re=1600.0, mach=0.1, cfl=0.02,
                     steps=2000, precision="f32"),
+    # the Taylor-Green blocks of tgv_256 (16 x 16 x 32) on a 128^3 grid:
+    # 256 blocks, few enough for one resident workgroup each
+    "tgv_128": dict(n=(128, 128, 128), length=(2 * math.pi,) * 3, ndim=3,
+                    nblk=(8, 8, 4), physics="ns", rk="rk4", mode="at",
+                    algo="saa", L=4, re=1600.0, mach=0.1, cfl=0.02,
+                    precision="f32"),
     "tgv_512": dict(n=(512, 512, 512), length=(2 * math.pi,) * 3, ndim=3,
                     nblk=(16, 16, 16), physics="ns", rk="rk4", mode="at",
                     algo="saa", L=5, re=1600.0, mach=0.1, cfl=0.01,

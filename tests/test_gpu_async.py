@@ -1,5 +1,5 @@
-"""Free-running asynchronous steps (atns_step_async): one persistent
-workgroup per block, delays that arise from the run itself (the
+"""Free-running asynchronous steps (atns_step_async), Euler and 3-D
+Navier-Stokes: one persistent workgroup per block, delays that arise from the run itself (the
 synchronization-avoiding rule of Alg. 3 without a schedule).  Parity: the
 realized delays are logged, and replaying them through the scheduled path
 (atns_set_delays) and through the oracle reproduces the run."""
@@ -22,14 +22,17 @@ def _start(o, g, n, dt, warm):
     o.step(warm)
 
 
-@pytest.mark.parametrize("rk, mode, L", [("rk4", "at", 3), ("lserk2", "as", 2), ("lserk2", "at", 4)])
-def test_free_running_steps_replay_exactly(rk, mode, L):
+@pytest.mark.parametrize("physics, rk, mode, L", [("euler", "rk4", "at", 3), ("euler", "lserk2", "as", 2),
+                                                  ("euler", "lserk2", "at", 4), ("ns", "rk4", "at", 3),
+                                                  ("ns", "lserk2", "at", 2)])
+def test_free_running_steps_replay_exactly(physics, rk, mode, L):
     torch = need_gpu()
-    announce("free-running", rk, mode, L)
-    n = (32, 24, 16)
+    announce("free-running", physics, rk, mode, L)
+    n = (32, 24, 16) if physics == "euler" else (24, 16, 16)
     U0 = inputs.vortex_state(n, BOX, 3)
     dt = inputs.cfl_dt(U0, n, BOX, 3, 1.4, 0.05)
-    spec = dict(n=n, length=BOX, nblk=(2, 2, 2), rk=rk, mode=mode, algo="saa", L=L, seed=3)
+    spec = dict(n=n, length=BOX, nblk=(2, 2, 2), physics=physics, rk=rk, mode=mode, algo="saa", L=L, seed=3,
+                re=200.0, mach=0.3)
     o, g = pair(spec, "f64", dt=dt)
     C = 3 if rk == "lserk2" else 5
     warm = C + L
@@ -41,7 +44,10 @@ def test_free_running_steps_replay_exactly(rk, mode, L):
     assert log.shape == (nsteps, 8, 18)
     assert used.any() and np.all(log[used] <= L - 1)
     # slots the physics does not use (Euler: the 12 edges) stay -1
-    assert np.all(log[:, :, 6:] == -1) and np.all(log[:, :, :6] >= 0)
+    if physics == "euler":
+        assert np.all(log[:, :, 6:] == -1) and np.all(log[:, :, :6] >= 0)
+    else:
+        assert np.all(log >= 0)
     A = to_np(g.get_state())
     # replay on the scheduled path
     _, r = pair(spec, "f64", dt=dt)
@@ -97,10 +103,11 @@ def test_free_running_rejects_unsupported_contexts():
     n = (32, 32, 32)
     base = dict(n=n, length=BOX, ndim=3, nblk=(2, 2, 2), mode=atns.AT, algo=atns.SAA, L=2, seed=1)
     U0 = inputs.vortex_state(n, BOX, 3)
-    for kw in (dict(base, physics=atns.NS), dict(base, mode=atns.SA), dict(base, rk=atns.LSERK4)):
+    base2d = dict(base, n=(32, 32, 1), ndim=2, nblk=(2, 2, 1), length=(10.0, 10.0, 1.0))
+    for kw in (dict(base2d, physics=atns.NS), dict(base, mode=atns.SA), dict(base, rk=atns.LSERK4)):
         g = atns.Solver(**kw)
         g.set_dt(1e-3)
-        g.set_state(torch.from_numpy(U0))
+        g.set_state(torch.from_numpy(U0 if kw["ndim"] == 3 else inputs.vortex_state(kw["n"], kw["length"], 2)))
         g.step(8)
         with pytest.raises(atns.AtnsError):
             g.step_async(2)
