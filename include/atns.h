@@ -194,6 +194,19 @@ atns_status atns_rhs(atns_ctx* ctx, void* dev_R);
  * in the last stage. */
 atns_status atns_rk_step(atns_ctx* ctx, int32_t nsteps);
 
+/* Fused RK4 stage pairs (on != 0): 3-D Euler contexts with classical RK4 in
+ * single precision run stages 1-2 and stages 3-4 as two kernels instead of
+ * four.  Stage A of a pair is evaluated on the tile and a 2-point apron and
+ * stage B follows in the same pass, so the intermediate stage field and the
+ * first RK register update never go through HBM; this is possible because
+ * asynchronous halos of every stage come from the delayed levels, not from
+ * the neighbours' current stage (and under synchronous halos the apron is
+ * computed from the global field).  Results are the same bits as the
+ * separate stage kernels.  Other contexts, and tile shapes the pair kernel
+ * is not built for (it takes (16,16), (32,8), (16,8), (32,16)), keep the
+ * separate kernels.  Default off. */
+atns_status atns_set_fusion(atns_ctx* ctx, int32_t on);
+
 /* Advance nsteps free-running asynchronous steps: the synchronization-
  * avoiding algorithm (Alg. 3) with delays that arise from the run itself
  * instead of a schedule.  One persistent workgroup per block advances its

@@ -33,8 +33,10 @@ struct atns_ctx {
   std::vector<HaloWork> work;
   size_t esz = 4;
   long long field = 0;
-  // RK registers: RK4 uses X[0] = U, X[1] = Ya, X[2] = Yb, X[3] = acc.
-  // LSERK uses X[cur] = U, X[1-cur] = the other stage buffer, X[3] = Q.
+  // RK registers: RK4 uses X[cur] = U, X[1-cur] = Ya, X[2] = Yb,
+  // X[3] = acc (cur changes only with fused stage pairs, whose last stage
+  // writes the new state to X[1-cur]); LSERK uses X[cur] = U, X[1-cur] =
+  // the other stage buffer, X[3] = Q.
   void* X[4] = {nullptr, nullptr, nullptr, nullptr};
   int cur = 0;
   void* ring = nullptr;
@@ -93,6 +95,7 @@ struct atns_ctx {
   double dt = 0.0;
   int64_t step = 0;
   bool state_set = false;
+  bool fuse = false;                 // classical RK4 stages 1-2 and 3-4 fused in pairs
   // free-running asynchronous steps: progress counters, abort flag, the
   // block-major tile list (for tiles async_tiles) and per-block ranges
   int* d_prog = nullptr;
@@ -397,6 +400,30 @@ hipError_t launch_stage(atns_ctx* c, const StageParams<T>& p, int kind) {
   return r;
 }
 
+// Whether the RK4 stages run as two fused pairs: 3-D Euler, classical RK4,
+// single precision, and a tile shape the pair kernel is built for.
+bool pairs_apply(const atns_ctx* c) {
+  if (!c->fuse || c->cfg.physics != ATNS_EULER || c->cfg.ndim != 3 || c->cfg.rk != ATNS_RK4 || c->esz != 4)
+    return false;
+  const int tx = c->tile[0], ty = c->tile[1];
+  return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 16 && ty == 8) || (tx == 32 && ty == 16);
+}
+
+template <typename T>
+hipError_t launch_pair(atns_ctx* c, const StageParams<T>& pA, const StageParams<T>& pB, int pair, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profiling) {
+    hipError_t r = next_event(c, &e0);
+    if (r == hipSuccess) r = next_event(c, &e1);
+    if (r == hipSuccess) r = hipEventRecord(e0, s);
+    if (r != hipSuccess) return r;
+  }
+  hipError_t r = launch_euler_pair<float>(*(const StageParams<float>*)&pA, *(const StageParams<float>*)&pB,
+                                          (int)c->tiles.size(), pair, c->tile[0], c->tile[1], s);
+  if (r == hipSuccess && c->profiling) r = hipEventRecord(e1, s);
+  return r;
+}
+
 bool is_async(const atns_ctx* c, int64_t step) { return c->cfg.mode != ATNS_SA && step >= c->C; }
 
 atns_status draw_delays(atns_ctx* c, int64_t step, int8_t* dst) {
@@ -461,8 +488,10 @@ void drop_graphs(atns_ctx* c) {
 
 // Stage parameters of stage e of an asynchronous step whose step number is
 // read on the device (graph-captured steps).
+// fused: the parameters for the fused stage pairs, where the last stage
+// writes the new state to X[1-cur] (the pair kernels never touch Ya).
 template <typename T>
-StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind) {
+StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind, bool fused) {
   const RKScheme& rk = c->rk;
   StageParams<T> p = base_params<T>(c);
   p.nstep = c->d_nstep;
@@ -475,13 +504,13 @@ StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind) {
     p.done = c->d_done;
   }
   if (!rk.low_storage) {
-    T* U = (T*)c->X[0];
-    T* Ya = (T*)c->X[1];
+    T* U = (T*)c->X[c->cur];
+    T* Ya = (T*)c->X[1 - c->cur];
     T* Yb = (T*)c->X[2];
     p.U0 = U;
     p.acc = (T*)c->X[3];
     const T* ins[4] = {U, Ya, Yb, Ya};
-    T* outs[4] = {Ya, Yb, Ya, U};
+    T* outs[4] = {Ya, Yb, Ya, fused ? Ya : U};
     p.Y = ins[e];
     p.Yout = outs[e];
     *kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
@@ -526,13 +555,22 @@ atns_status capture_step(atns_ctx* c, hipGraphExec_t* out) {
   hipGraph_t graph = nullptr;
   HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   atns_status st = enqueue_graph_halos<T>(c, s);
+  const bool pairs = pairs_apply(c);
+  StageParams<T> ps[4];
   for (int e = 0; st == ATNS_OK && e < c->rk.stages; ++e) {
     int kind = 0;
-    const StageParams<T> p = graph_stage_params<T>(c, e, &kind);
-    const hipError_t r =
-        (c->cfg.physics == ATNS_NS)
-            ? launch_ns_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], s)
-            : launch_euler_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], s);
+    const StageParams<T> p = graph_stage_params<T>(c, e, &kind, pairs);
+    hipError_t r = hipSuccess;
+    if (pairs) {
+      ps[e] = p;
+      if (e == 1 || e == 3)
+        r = launch_euler_pair<float>(*(const StageParams<float>*)&ps[e - 1], *(const StageParams<float>*)&ps[e],
+                                     (int)c->tiles.size(), e / 2, c->tile[0], c->tile[1], s);
+    } else {
+      r = (c->cfg.physics == ATNS_NS)
+              ? launch_ns_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], s)
+              : launch_euler_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], s);
+    }
     if (r != hipSuccess) st = fail(c, ATNS_EHIP, std::string("stage launch in capture: ") + hipGetErrorString(r));
   }
   const hipError_t ec = hipStreamEndCapture(s, &graph);
@@ -563,7 +601,7 @@ atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
     const bool graphable = async && c->use_graph && !c->profiling && c->inject_n == 0;
     hipStream_t s = work_stream(c);
     if (graphable) {
-      const int par = rk.low_storage ? c->cur : 0;
+      const int par = c->cur;
       if (!c->gexec[par]) {
         atns_status st = capture_step<T>(c, &c->gexec[par]);
         if (st != ATNS_OK) return st;
@@ -578,7 +616,7 @@ atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
         c->nstep_synced = true;
       }
       HIP_TRY(c, hipGraphLaunch(c->gexec[par], s));
-      if (rk.low_storage && (rk.stages & 1)) c->cur = 1 - c->cur;
+      if ((rk.low_storage && (rk.stages & 1)) || pairs_apply(c)) c->cur = 1 - c->cur;
       c->step += 1;
       continue;
     }
@@ -595,18 +633,20 @@ atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
     StageParams<T> p = base_params<T>(c);
     p.halo = !async ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
     p.slot_now = c->D ? (int)(c->step % c->D) : 0;
+    const bool pairs = pairs_apply(c);
+    StageParams<T> ps[4];
     for (int e = 0; e < rk.stages; ++e) {
       p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)e * c->slot_stride : nullptr;
       p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
       int kind;
       if (!rk.low_storage) {
-        T* U = (T*)c->X[0];
-        T* Ya = (T*)c->X[1];
+        T* U = (T*)c->X[c->cur];
+        T* Ya = (T*)c->X[1 - c->cur];
         T* Yb = (T*)c->X[2];
         p.U0 = U;
         p.acc = (T*)c->X[3];
         const T* ins[4] = {U, Ya, Yb, Ya};
-        T* outs[4] = {Ya, Yb, Ya, U};
+        T* outs[4] = {Ya, Yb, Ya, pairs ? Ya : U};
         p.Y = ins[e];
         p.Yout = outs[e];
         kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
@@ -620,9 +660,15 @@ atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
         p.cA = rk.A[e];
         p.cB = rk.B[e];
       }
-      HIP_TRY(c, launch_stage<T>(c, p, kind));
+      if (pairs) {
+        ps[e] = p;
+        if (e == 1 || e == 3) HIP_TRY(c, launch_pair<T>(c, ps[e - 1], ps[e], e / 2, c->stream));
+      } else {
+        HIP_TRY(c, launch_stage<T>(c, p, kind));
+      }
       if (rk.low_storage) c->cur = 1 - c->cur;
     }
+    if (pairs) c->cur = 1 - c->cur;   // the new state went to X[1 - cur]
     c->step += 1;
   }
   return ATNS_OK;
@@ -639,7 +685,7 @@ atns_status do_steps(atns_ctx* c, int nsteps) {
   return st;
 }
 
-void* state_ptr(const atns_ctx* c) { return c->rk.low_storage ? c->X[c->cur] : c->X[0]; }
+void* state_ptr(const atns_ctx* c) { return c->X[c->cur]; }
 
 void release(atns_ctx* c) {
   drop_graphs(c);
@@ -1022,6 +1068,13 @@ atns_status atns_rhs(atns_ctx* c, void* dev_R) {
   return c->esz == 4 ? go(float{}) : go(double{});
 }
 
+atns_status atns_set_fusion(atns_ctx* c, int32_t on) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  c->fuse = on != 0;
+  drop_graphs(c);
+  return ATNS_OK;
+}
+
 atns_status atns_rk_step(atns_ctx* c, int32_t nsteps) {
   if (!c) return fail(c, ATNS_EINVAL, "null context");
   if (nsteps < 0) return fail(c, ATNS_EINVAL, "negative step count");
@@ -1103,7 +1156,7 @@ atns_status step_async_impl(atns_ctx* c, int nsteps, long long spin_limit, int8_
   std::vector<StageParams<T>> ps(stages);
   for (int e = 0; e < stages; ++e) {
     int kind = 0;
-    ps[e] = graph_stage_params<T>(c, e, &kind);
+    ps[e] = graph_stage_params<T>(c, e, &kind, false);
     ps[e].nstep = nullptr;
     ps[e].step_end = nullptr;
     ps[e].done = nullptr;
@@ -1303,8 +1356,8 @@ atns_status time_shape(atns_ctx* c, int reps, float* ms_out) {
     p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
     int kind;
     if (!rk.low_storage) {
-      T* U = (T*)c->X[0];
-      T* Ya = (T*)c->X[1];
+      T* U = (T*)c->X[c->cur];
+      T* Ya = (T*)c->X[1 - c->cur];
       T* Yb = (T*)c->X[2];
       p.U0 = U;
       p.acc = (T*)c->X[3];
@@ -1683,7 +1736,7 @@ atns_status batch_params(atns_batch* b) {
   for (int e = 0; e < b->stages; ++e)
     for (int i = 0; i < n; ++i) {
       int kind = 0;
-      ps[(size_t)e * n + i] = graph_stage_params<T>(b->m[i], e, &kind);
+      ps[(size_t)e * n + i] = graph_stage_params<T>(b->m[i], e, &kind, false);
     }
   if (!b->d_ps && hipMalloc(&b->d_ps, ps.size() * sizeof(StageParams<T>)) != hipSuccess)
     return bfail(b, ATNS_ENOMEM, "batch parameter allocation failed");

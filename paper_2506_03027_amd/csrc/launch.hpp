@@ -9,6 +9,12 @@ namespace atns {
 // Free-running asynchronous steps (one persistent workgroup per block) of a
 // 3-D Navier-Stokes or an Euler context; with resident set, only the number
 // of workgroups that fit on one CU is returned.
+// Two consecutive classical RK4 stages of a 3-D Euler context in one pass
+// (pair 0: stages 1-2 with the parameters of stages 0 and 1; pair 1: stages
+// 3-4), single precision.
+template <typename T>
+hipError_t launch_euler_pair(const StageParams<T>& pA, const StageParams<T>& pB, int ntiles, int pair, int tx,
+                             int ty, hipStream_t s);
 template <typename T>
 hipError_t launch_ns_async(const StageParams<T>* ps, const AsyncArgs& a, int stages, int tx, int ty, hipStream_t s,
                            int* resident = nullptr);
