@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "kernels_common.hpp"
+
 namespace atns {
 
 // The fluxes of a point are computed by its own thread or, at a tile edge, by
@@ -12,7 +14,7 @@ namespace atns {
 template <typename T>
 __device__ __forceinline__ void euler_prims(const T u[5], T gm1, T& iv_rho, T& p) {
 #pragma clang fp contract(off)
-  iv_rho = T(1) / u[0];
+  iv_rho = recip(u[0]);   // FP32: reciprocal estimate and one Newton step
   const T m2 = fma(u[1], u[1], fma(u[2], u[2], u[3] * u[3]));
   p = gm1 * fma(T(-0.5) * m2, iv_rho, u[4]);
 }

@@ -8,8 +8,9 @@
 // boundary layers into the delayed-level ring.
 //
 // Work decomposition (2.5D): a workgroup owns a TX x TY column tile of one
-// block and walks it along z.  Each thread keeps the five z-levels
-// z-2..z+2 of its column in registers; the x- and y-fluxes of the current
+// block and walks it along z.  Each thread keeps the state of planes
+// z..z+2 of its column and the z-fluxes of planes z-2..z+2 (each computed
+// once, when its plane arrives) in registers; the x- and y-fluxes of the current
 // plane (tile plus a 2-point apron) are staged in LDS, double-buffered so one
 // barrier per plane suffices.  Points outside the block -- the apron at a
 // block face and the z-levels beyond it -- come from fetch(), which applies
@@ -79,11 +80,23 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
   if (act) colq = column_source(p, B, lx, ly);
   if (arole) cola = column_source(p, B, t.x0 + ax, t.y0 + ay);
 
-  T q[5][5];
+  // z-queues of the own column: the state of planes lz..lz+2 (the centre
+  // and the two planes behind it) and the z-fluxes of planes lz-2..lz+2, each
+  // computed once, when its plane arrives
+  T uq[3][5], hq[5][5];
   T nq[5], na[5];   // prefetched: own column at z+2 and the apron point at z
   if (act && three) {
+    T u[5];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) fetch_col(p, B, colq, t.blk, lx, ly, t.z0 - 2 + j, q[j + 1]);
+    for (int j = 0; j < 2; ++j) {
+      fetch_col(p, B, colq, t.blk, lx, ly, t.z0 - 2 + j, u);
+      euler_flux(u, 2, gm1, hq[j + 1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      fetch_col(p, B, colq, t.blk, lx, ly, t.z0 + j, uq[j + 1]);
+      euler_flux(uq[j + 1], 2, gm1, hq[j + 3]);
+    }
     fetch_col(p, B, colq, t.blk, lx, ly, t.z0 + 2, nq);
   }
   if (arole) fetch_col(p, B, cola, t.blk, t.x0 + ax, t.y0 + ay, t.z0, na);
@@ -109,19 +122,24 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-          for (int v = 0; v < 5; ++v) q[j][v] = q[j + 1][v];
+          for (int v = 0; v < 5; ++v) hq[j][v] = hq[j + 1][v];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) q[4][v] = nq[v];
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int v = 0; v < 5; ++v) uq[j][v] = uq[j + 1][v];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) uq[2][v] = nq[v];
+        euler_flux(uq[2], 2, gm1, hq[4]);
         // next plane's column value: in flight while this plane is computed
         if (iz + 1 < t.nz) fetch_col(p, B, colq, t.blk, lx, ly, lz + 3, nq);
       } else {
-        fetch_col(p, B, colq, t.blk, lx, ly, lz, q[2]);
+        fetch_col(p, B, colq, t.blk, lx, ly, lz, uq[0]);
       }
       T f[5];
-      euler_flux(q[2], 0, gm1, f);
+      euler_flux(uq[0], 0, gm1, f);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sF[buf][v][ty][tx + 2] = f[v];
-      euler_flux(q[2], 1, gm1, f);
+      euler_flux(uq[0], 1, gm1, f);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sG[buf][v][ty + 2][tx] = f[v];
     }
@@ -152,17 +170,13 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
         R[v] = -(dx + dy);
       }
       if (three) {
-        T h0[5], h1[5], h3[5], h4[5];
-        euler_flux(q[0], 2, gm1, h0);
-        euler_flux(q[1], 2, gm1, h1);
-        euler_flux(q[3], 2, gm1, h3);
-        euler_flux(q[4], 2, gm1, h4);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) R[v] -= (w1 * (h3[v] - h1[v]) - w2 * (h4[v] - h0[v])) * ihz;
+        for (int v = 0; v < 5; ++v)
+          R[v] -= (w1 * (hq[3][v] - hq[1][v]) - w2 * (hq[4][v] - hq[0][v])) * ihz;
       }
       const long long g = g0 + iz * gplane;
       T out[5];
-      epilogue_pre<T, KIND>(p, g, q[2], R, accv, u0v, out);
+      epilogue_pre<T, KIND>(p, g, uq[0], R, accv, u0v, out);
       if (iz + 1 < t.nz) epilogue_load<T, KIND>(p, g + gplane, accv, u0v);
       if (ring_slot) ring_store(p, B, rmask, lx, ly, lz, out, ring_slot);
     }
