@@ -165,12 +165,13 @@ def hbm_probe(torch, reps=10):
 
 
 def kernel_source_hash():
-    """Hash of the kernel sources: stored counter results apply only to it."""
+    """Hash of the device-code sources (.hip files and the headers they
+    include): stored counter results apply only to it."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2506_03027_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
+        if name.endswith((".hip", ".hpp")):
             h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "coeffs.hpp"
@@ -418,8 +419,9 @@ hipError_t launch_pair(atns_ctx* c, const StageParams<T>& pA, const StageParams<
     if (r == hipSuccess) r = hipEventRecord(e0, s);
     if (r != hipSuccess) return r;
   }
-  hipError_t r = launch_euler_pair<float>(*(const StageParams<float>*)&pA, *(const StageParams<float>*)&pB,
-                                          (int)c->tiles.size(), pair, c->tile[0], c->tile[1], s);
+  hipError_t r = hipErrorInvalidValue;
+  if constexpr (std::is_same<T, float>::value)
+    r = launch_euler_pair<float>(pA, pB, (int)c->tiles.size(), pair, c->tile[0], c->tile[1], s);
   if (r == hipSuccess && c->profiling) r = hipEventRecord(e1, s);
   return r;
 }
@@ -563,9 +565,10 @@ atns_status capture_step(atns_ctx* c, hipGraphExec_t* out) {
     hipError_t r = hipSuccess;
     if (pairs) {
       ps[e] = p;
-      if (e == 1 || e == 3)
-        r = launch_euler_pair<float>(*(const StageParams<float>*)&ps[e - 1], *(const StageParams<float>*)&ps[e],
-                                     (int)c->tiles.size(), e / 2, c->tile[0], c->tile[1], s);
+      if constexpr (std::is_same<T, float>::value) {
+        if (e == 1 || e == 3)
+          r = launch_euler_pair<float>(ps[e - 1], ps[e], (int)c->tiles.size(), e / 2, c->tile[0], c->tile[1], s);
+      }
     } else {
       r = (c->cfg.physics == ATNS_NS)
               ? launch_ns_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], s)
