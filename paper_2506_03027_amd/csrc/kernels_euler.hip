@@ -84,7 +84,7 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
   // and the two planes behind it) and the z-fluxes of planes lz-2..lz+2, each
   // computed once, when its plane arrives
   T uq[3][5], hq[5][5];
-  T nq[5], na[5];   // prefetched: own column at z+2 and the apron point at z
+  T nq[5], nq2[5], na[5];   // prefetched: own column at z+2, z+3 and the apron point at z
   if (act && three) {
     T u[5];
 #pragma unroll
@@ -98,6 +98,7 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
       euler_flux(uq[j + 1], 2, gm1, hq[j + 3]);
     }
     fetch_col(p, B, colq, t.blk, lx, ly, t.z0 + 2, nq);
+    if (t.nz > 1) fetch_col(p, B, colq, t.blk, lx, ly, t.z0 + 3, nq2);
   }
   if (arole) fetch_col(p, B, cola, t.blk, t.x0 + ax, t.y0 + ay, t.z0, na);
 
@@ -128,10 +129,13 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
 #pragma unroll
           for (int v = 0; v < 5; ++v) uq[j][v] = uq[j + 1][v];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) uq[2][v] = nq[v];
+        for (int v = 0; v < 5; ++v) {
+          uq[2][v] = nq[v];
+          nq[v] = nq2[v];
+        }
         euler_flux(uq[2], 2, gm1, hq[4]);
         // next plane's column value: in flight while this plane is computed
-        if (iz + 1 < t.nz) fetch_col(p, B, colq, t.blk, lx, ly, lz + 3, nq);
+        if (iz + 2 < t.nz) fetch_col(p, B, colq, t.blk, lx, ly, lz + 4, nq2);
       } else {
         fetch_col(p, B, colq, t.blk, lx, ly, lz, uq[0]);
       }
