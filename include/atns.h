@@ -350,12 +350,14 @@ atns_status atns_host_delays(int32_t algo, int32_t rk, int64_t n, int32_t nblock
  * walks the combined tile list of all members of that physics; the Euler and
  * Navier-Stokes members form two independent branches of the graph.  Each
  * physics uses one tile shape for all its members (atns_batch_set_tiles, or
- * atns_batch_autotune, which times every shape with the stage kernel of the
- * largest member of each physics -- one step's stage-kernel mix as for
- * atns_autotune, so no state changes --
- * and applies, per physics, the shape with the least
- * total time; best receives int[6] = Euler (tx, ty, tz), Navier-Stokes
- * (tx, ty, tz)).
+ * atns_batch_autotune, which times every shape with the batch kernels
+ * themselves over all members of each physics -- one step's stage-kernel mix
+ * writing only stage registers, as for atns_autotune, so no state changes --
+ * then times the three fastest shapes of each physics in pairs, the two
+ * physics running concurrently as in a batch step, and applies the fastest
+ * pair; best receives int[6] = Euler (tx, ty, tz), Navier-Stokes
+ * (tx, ty, tz)).  The persistent grid of each physics is as many workgroups
+ * as the device holds at once for that kernel and shape.
  * Member results are bit-identical to stepping each member alone.
  * Ownership: the batch owns its member contexts; never pass a member to
  * atns_destroy (atns_batch_destroy releases them).  Member calls that change

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1342,46 +1344,55 @@ void cache_store(const char* path, const std::string& key, const int v[3]) {
   std::fclose(f);
 }
 
+// Parameters of RK stage e of a timing probe on the current state, writing
+// only what is dead at a step boundary: the stage registers and the
+// accumulator (RK4), or Q and the spare buffer (LSERK4).  The last stage's
+// output goes to a stage register instead of the state, and its ring write to
+// slot (n + 1) mod D, whose level n + 1 - D no stage of step n reads.
+template <typename T>
+StageParams<T> probe_stage(atns_ctx* c, int e, int* kind_out) {
+  const RKScheme& rk = c->rk;
+  StageParams<T> p = base_params<T>(c);
+  p.halo = kHaloSync;
+  p.slot_now = c->D ? (int)(c->step % c->D) : 0;
+  p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
+  int kind;
+  if (!rk.low_storage) {
+    T* U = (T*)c->X[c->cur];
+    T* Ya = (T*)c->X[1 - c->cur];
+    T* Yb = (T*)c->X[2];
+    p.U0 = U;
+    p.acc = (T*)c->X[3];
+    const T* ins[4] = {U, Ya, Yb, Ya};
+    T* outs[4] = {Ya, Yb, Ya, Yb};   // the last stage into Yb, not U
+    p.Y = ins[e];
+    p.Yout = outs[e];
+    kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
+    p.cA = rk.b[e];
+    p.cB = e < 3 ? rk.a[e + 1][e] : 0.0;
+  } else {
+    // the state buffer is only ever read; the stages alternate between
+    // the spare buffer and X[2], which low-storage schemes do not use
+    void* spare[2] = {c->X[1 - c->cur], c->X[2]};
+    p.Y = (const T*)(e == 0 ? c->X[c->cur] : spare[(e - 1) & 1]);
+    p.Yout = (T*)spare[e & 1];
+    p.acc = (T*)c->X[3];
+    kind = e == 0 ? kLSFirst : kLSMid;
+    p.cA = rk.A[e];
+    p.cB = rk.B[e];
+  }
+  *kind_out = kind;
+  return p;
+}
+
 template <typename T>
 atns_status time_shape(atns_ctx* c, int reps, float* ms_out) {
-  // One step's mix of stage kernels on the current state -- first, middle
-  // and last RK stage, the last with its ring write -- writing only what is
-  // dead at a step boundary: the stage registers and the accumulator (RK4),
-  // or Q and the spare buffer (LSERK4); the last stage's output goes to a
-  // stage register instead of the state, and its ring write to slot
-  // (n + 1) mod D, whose level n + 1 - D no stage of step n reads.
-  const RKScheme& rk = c->rk;
+  // One step's mix of stage kernels -- first, middle and last RK stage, the
+  // last with its ring write -- as timing probes.
   std::vector<std::pair<StageParams<T>, int>> seq;
-  for (int e = 0; e < rk.stages; ++e) {
-    StageParams<T> p = base_params<T>(c);
-    p.halo = kHaloSync;
-    p.slot_now = c->D ? (int)(c->step % c->D) : 0;
-    p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
+  for (int e = 0; e < c->rk.stages; ++e) {
     int kind;
-    if (!rk.low_storage) {
-      T* U = (T*)c->X[c->cur];
-      T* Ya = (T*)c->X[1 - c->cur];
-      T* Yb = (T*)c->X[2];
-      p.U0 = U;
-      p.acc = (T*)c->X[3];
-      const T* ins[4] = {U, Ya, Yb, Ya};
-      T* outs[4] = {Ya, Yb, Ya, Yb};   // the last stage into Yb, not U
-      p.Y = ins[e];
-      p.Yout = outs[e];
-      kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
-      p.cA = rk.b[e];
-      p.cB = e < 3 ? rk.a[e + 1][e] : 0.0;
-    } else {
-      // the state buffer is only ever read; the stages alternate between
-      // the spare buffer and X[2], which low-storage schemes do not use
-      void* spare[2] = {c->X[1 - c->cur], c->X[2]};
-      p.Y = (const T*)(e == 0 ? c->X[c->cur] : spare[(e - 1) & 1]);
-      p.Yout = (T*)spare[e & 1];
-      p.acc = (T*)c->X[3];
-      kind = e == 0 ? kLSFirst : kLSMid;
-      p.cA = rk.A[e];
-      p.cB = rk.B[e];
-    }
+    StageParams<T> p = probe_stage<T>(c, e, &kind);
     seq.push_back({p, kind});
   }
   hipEvent_t e0, e1;
@@ -1727,7 +1738,18 @@ atns_status batch_tiles(atns_batch* b, int ph) {
   }
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->m[0]->device);
-  const int per_cu = ph == 0 ? 4 : 2;   // resident workgroups per CU of the two kernels
+  // as many persistent workgroups as fit on the device at once (occupancy of
+  // the batch kernel of this shape and precision)
+  int per_cu = 0;
+  const int tx = b->shape[ph][0], ty = b->shape[ph][1];
+  hipError_t e;
+  if (b->esz == 4)
+    e = ph == 1 ? launch_ns_batch<float>(nullptr, nullptr, 0, 0, 0, tx, ty, nullptr, &per_cu)
+                : launch_euler_batch<float>(nullptr, nullptr, 0, 0, 0, tx, ty, nullptr, &per_cu);
+  else
+    e = ph == 1 ? launch_ns_batch<double>(nullptr, nullptr, 0, 0, 0, tx, ty, nullptr, &per_cu)
+                : launch_euler_batch<double>(nullptr, nullptr, 0, 0, 0, tx, ty, nullptr, &per_cu);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
   b->grid[ph] = (int)std::min<size_t>(b->tl[ph].size(), (size_t)cus * per_cu);
   return ATNS_OK;
 }
@@ -1946,42 +1968,128 @@ atns_status atns_batch_step(atns_batch* b, int32_t nsteps) {
   return b->esz == 4 ? batch_steps<float>(b, nsteps) : batch_steps<double>(b, nsteps);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Average time of one step's batch stage kernels (first, middle and last RK
+// stage over the combined tile lists, with the current tiles and grids) of
+// the physics in `mask` (bit 0 Euler, bit 1 Navier-Stokes; both: the two run
+// concurrently on their own streams, as in a batch step), as timing probes
+// that leave every member's state intact.
+template <typename T>
+atns_status batch_time(atns_batch* b, int mask, int reps, float* ms_out) {
+  const int n = (int)b->m.size();
+  std::vector<StageParams<T>> ps((size_t)b->stages * n);
+  std::vector<int> kinds(b->stages);
+  for (int e = 0; e < b->stages; ++e)
+    for (int i = 0; i < n; ++i) ps[(size_t)e * n + i] = probe_stage<T>(b->m[i], e, &kinds[e]);
+  StageParams<T>* d = nullptr;
+  BHIP(b, hipMalloc(&d, ps.size() * sizeof(StageParams<T>)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto run = [&]() -> atns_status {
+    BHIP(b, hipMemcpy(d, ps.data(), ps.size() * sizeof(StageParams<T>), hipMemcpyHostToDevice));
+    BHIP(b, hipEventCreate(&e0));
+    BHIP(b, hipEventCreate(&e1));
+    auto pass = [&](int ph) -> hipError_t {
+      for (int e = 0; e < b->stages; ++e) {
+        const StageParams<T>* pe = d + (size_t)e * n;
+        const hipError_t r =
+            ph == 0 ? launch_euler_batch<T>(pe, b->d_tl[0], (int)b->tl[0].size(), b->grid[0], kinds[e],
+                                           b->shape[0][0], b->shape[0][1], b->s[0])
+                    : launch_ns_batch<T>(pe, b->d_tl[1], (int)b->tl[1].size(), b->grid[1], kinds[e],
+                                        b->shape[1][0], b->shape[1][1], b->s[1]);
+        if (r != hipSuccess) return r;
+      }
+      return hipSuccess;
+    };
+    auto passes = [&](int count) -> atns_status {
+      BHIP(b, hipEventRecord(b->fork, b->s[0]));
+      BHIP(b, hipStreamWaitEvent(b->s[1], b->fork, 0));
+      for (int ph = 0; ph < 2; ++ph)
+        if ((mask >> ph & 1) && !b->tl[ph].empty())
+          for (int r = 0; r < count; ++r) BHIP(b, pass(ph));
+      BHIP(b, hipEventRecord(b->join, b->s[1]));
+      BHIP(b, hipStreamWaitEvent(b->s[0], b->join, 0));
+      return ATNS_OK;
+    };
+    atns_status st = passes(1);   // warm
+    if (st != ATNS_OK) return st;
+    BHIP(b, hipEventRecord(e0, b->s[0]));
+    if ((st = passes(reps)) != ATNS_OK) return st;
+    BHIP(b, hipEventRecord(e1, b->s[0]));
+    BHIP(b, hipEventSynchronize(e1));
+    float ms = 0.f;
+    BHIP(b, hipEventElapsedTime(&ms, e0, e1));
+    *ms_out = ms / reps;
+    return ATNS_OK;
+  };
+  const atns_status st = run();
+  (void)hipDeviceSynchronize();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(d);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
 atns_status atns_batch_autotune(atns_batch* b, int32_t reps, int32_t* best) {
   if (!b || reps < 1) return bfail(b, ATNS_EINVAL, "bad arguments");
   for (atns_ctx* c : b->m)
     if (!c->state_set) return bfail(b, ATNS_ESTATE, "member state not set");
   BHIP(b, hipDeviceSynchronize());
-  // Per physics: every shape is timed with the stage kernel of the largest
-  // member (a middle RK stage writing only registers that are dead at a
-  // step boundary; states are untouched) and the fastest is applied to the
-  // whole batch.  The largest member stands for the batch: there the time
-  // is set by throughput, as in the batch kernels, whereas small members
-  // alone are dominated by launch and tail effects that favour small tiles.
+  // Every shape of each physics is timed with the batch kernels themselves
+  // over the combined tile list of all members of that physics (timing
+  // probes on the current states, which stay untouched).  The two physics
+  // share the device during a batch step, so the three fastest shapes of
+  // each are then timed in pairs, running concurrently, and the fastest pair
+  // is kept.
+  constexpr int kTop = 3;
+  std::vector<std::array<int, 3>> top[2];
+  auto timer = [&](int mask, float* ms) {
+    return b->esz == 4 ? batch_time<float>(b, mask, reps, ms) : batch_time<double>(b, mask, reps, ms);
+  };
   for (int ph = 0; ph < 2; ++ph) {
-    atns_ctx* rep = nullptr;
-    for (atns_ctx* c : b->m)
-      if ((c->cfg.physics == ATNS_NS) == (ph == 1) && (!rep || c->field > rep->field)) rep = c;
-    if (!rep) continue;
-    float best_ms = 1e30f;
-    int pick[3] = {b->shape[ph][0], b->shape[ph][1], b->shape[ph][2]};
     const int phys = ph ? ATNS_NS : ATNS_EULER;
+    if (b->tl[ph].empty()) {
+      top[ph].push_back({b->shape[ph][0], b->shape[ph][1], b->shape[ph][2]});
+      continue;
+    }
+    std::vector<std::pair<float, std::array<int, 3>>> timed;
     for (int i = 0; i < num_shapes(phys); ++i)
       for (int tz : {4, 8, 16, 32}) {
         if (ph == 1 && tz < 8) continue;
         const int tx = shape_at(phys, i)[0], ty = shape_at(phys, i)[1];
-        atns_status st = atns_set_tiles(rep, tx, ty, tz);
-        if (st != ATNS_OK) return bfail(b, st, rep->err);
-        float total = 0.f;
-        st = rep->esz == 4 ? time_shape<float>(rep, reps, &total) : time_shape<double>(rep, reps, &total);
-        if (st != ATNS_OK) return bfail(b, st, rep->err);
-        if (total < best_ms) {
-          best_ms = total;
-          pick[0] = tx;
-          pick[1] = ty;
-          pick[2] = tz;
-        }
+        atns_status st = atns_batch_set_tiles(b, phys, tx, ty, tz);
+        if (st != ATNS_OK) return st;
+        float ms = 0.f;
+        if ((st = timer(1 << ph, &ms)) != ATNS_OK) return st;
+        timed.push_back({ms, {tx, ty, tz}});
       }
-    atns_status st = atns_batch_set_tiles(b, ph ? ATNS_NS : ATNS_EULER, pick[0], pick[1], pick[2]);
+    std::stable_sort(timed.begin(), timed.end(),
+                     [](const auto& x, const auto& y) { return x.first < y.first; });
+    for (int i = 0; i < kTop && i < (int)timed.size(); ++i) top[ph].push_back(timed[i].second);
+  }
+  float best_ms = 1e30f;
+  std::array<int, 3> pick[2] = {top[0][0], top[1][0]};
+  for (const auto& eu : top[0])
+    for (const auto& ns : top[1]) {
+      atns_status st = atns_batch_set_tiles(b, ATNS_EULER, eu[0], eu[1], eu[2]);
+      if (st == ATNS_OK) st = atns_batch_set_tiles(b, ATNS_NS, ns[0], ns[1], ns[2]);
+      if (st != ATNS_OK) return st;
+      float ms = 0.f;
+      if ((st = timer(3, &ms)) != ATNS_OK) return st;
+      if (ms < best_ms) {
+        best_ms = ms;
+        pick[0] = eu;
+        pick[1] = ns;
+      }
+    }
+  for (int ph = 0; ph < 2; ++ph) {
+    const atns_status st = atns_batch_set_tiles(b, ph ? ATNS_NS : ATNS_EULER, pick[ph][0], pick[ph][1], pick[ph][2]);
     if (st != ATNS_OK) return st;
   }
   if (best)

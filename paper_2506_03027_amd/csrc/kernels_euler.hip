@@ -266,7 +266,10 @@ template hipError_t launch_euler_async<double>(const StageParams<double>*, const
 
 template <typename T, int TX, int TY>
 hipError_t launch_euler_batch_shape(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind,
-                                    hipStream_t s) {
+                                    hipStream_t s, int* resident) {
+  if (resident)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(resident, (const void*)euler_batch_kernel<T, TX, TY, kRK4Mid>,
+                                                        TX * TY, 0);
   dim3 g(grid), b(TX * TY);
   switch (kind) {
     case kRK4First: euler_batch_kernel<T, TX, TY, kRK4First><<<g, b, 0, s>>>(ps, tl, ntiles); break;
@@ -277,20 +280,22 @@ hipError_t launch_euler_batch_shape(const StageParams<T>* ps, const BatchTile* t
   return hipGetLastError();
 }
 
+// With resident != nullptr: only report how many workgroups of the (middle
+// stage) kernel fit on one CU.
 template <typename T>
 hipError_t launch_euler_batch(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind, int tx,
-                              int ty, hipStream_t s) {
-  if (tx == 16 && ty == 16) return launch_euler_batch_shape<T, 16, 16>(ps, tl, ntiles, grid, kind, s);
-  if (tx == 32 && ty == 8) return launch_euler_batch_shape<T, 32, 8>(ps, tl, ntiles, grid, kind, s);
-  if (tx == 16 && ty == 8) return launch_euler_batch_shape<T, 16, 8>(ps, tl, ntiles, grid, kind, s);
-  if (tx == 64 && ty == 8) return launch_euler_batch_shape<T, 64, 8>(ps, tl, ntiles, grid, kind, s);
-  if (tx == 32 && ty == 16) return launch_euler_batch_shape<T, 32, 16>(ps, tl, ntiles, grid, kind, s);
+                              int ty, hipStream_t s, int* resident) {
+  if (tx == 16 && ty == 16) return launch_euler_batch_shape<T, 16, 16>(ps, tl, ntiles, grid, kind, s, resident);
+  if (tx == 32 && ty == 8) return launch_euler_batch_shape<T, 32, 8>(ps, tl, ntiles, grid, kind, s, resident);
+  if (tx == 16 && ty == 8) return launch_euler_batch_shape<T, 16, 8>(ps, tl, ntiles, grid, kind, s, resident);
+  if (tx == 64 && ty == 8) return launch_euler_batch_shape<T, 64, 8>(ps, tl, ntiles, grid, kind, s, resident);
+  if (tx == 32 && ty == 16) return launch_euler_batch_shape<T, 32, 16>(ps, tl, ntiles, grid, kind, s, resident);
   return hipErrorInvalidValue;
 }
 template hipError_t launch_euler_batch<float>(const StageParams<float>*, const BatchTile*, int, int, int, int, int,
-                                              hipStream_t);
+                                              hipStream_t, int*);
 template hipError_t launch_euler_batch<double>(const StageParams<double>*, const BatchTile*, int, int, int, int, int,
-                                               hipStream_t);
+                                               hipStream_t, int*);
 
 template <typename T, int TX, int TY>
 hipError_t launch_euler_shape(const StageParams<T>& p, int ntiles, int kind, hipStream_t s) {

@@ -436,7 +436,10 @@ template hipError_t launch_ns_async<double>(const StageParams<double>*, const As
 
 template <typename T, int TX, int TY>
 hipError_t launch_ns_batch_shape(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind,
-                                 hipStream_t s) {
+                                 hipStream_t s, int* resident) {
+  if (resident)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(resident, (const void*)ns_batch_kernel<T, TX, TY, kRK4Mid>,
+                                                        (TX + 8) * (TY + 8), 0);
   dim3 g(grid), b((TX + 8) * (TY + 8));
   switch (kind) {
     case kRK4First: ns_batch_kernel<T, TX, TY, kRK4First><<<g, b, 0, s>>>(ps, tl, ntiles); break;
@@ -447,18 +450,20 @@ hipError_t launch_ns_batch_shape(const StageParams<T>* ps, const BatchTile* tl, 
   return hipGetLastError();
 }
 
+// With resident != nullptr: only report how many workgroups of the (middle
+// stage) kernel fit on one CU.
 template <typename T>
 hipError_t launch_ns_batch(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind, int tx,
-                           int ty, hipStream_t s) {
-  if (tx == 16 && ty == 16) return launch_ns_batch_shape<T, 16, 16>(ps, tl, ntiles, grid, kind, s);
-  if (tx == 32 && ty == 8) return launch_ns_batch_shape<T, 32, 8>(ps, tl, ntiles, grid, kind, s);
-  if (tx == 16 && ty == 8) return launch_ns_batch_shape<T, 16, 8>(ps, tl, ntiles, grid, kind, s);
+                           int ty, hipStream_t s, int* resident) {
+  if (tx == 16 && ty == 16) return launch_ns_batch_shape<T, 16, 16>(ps, tl, ntiles, grid, kind, s, resident);
+  if (tx == 32 && ty == 8) return launch_ns_batch_shape<T, 32, 8>(ps, tl, ntiles, grid, kind, s, resident);
+  if (tx == 16 && ty == 8) return launch_ns_batch_shape<T, 16, 8>(ps, tl, ntiles, grid, kind, s, resident);
   return hipErrorInvalidValue;
 }
 template hipError_t launch_ns_batch<float>(const StageParams<float>*, const BatchTile*, int, int, int, int, int,
-                                           hipStream_t);
+                                           hipStream_t, int*);
 template hipError_t launch_ns_batch<double>(const StageParams<double>*, const BatchTile*, int, int, int, int, int,
-                                            hipStream_t);
+                                            hipStream_t, int*);
 
 template <typename T, int KIND, int TX, int TY>
 hipError_t launch_ns_kind(const StageParams<T>& p, int ntiles, hipStream_t s) {

@@ -28,10 +28,10 @@ hipError_t launch_ns_stage(const StageParams<T>& p, int ntiles, int kind, int tx
 
 template <typename T>
 hipError_t launch_euler_batch(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind, int tx,
-                              int ty, hipStream_t s);
+                              int ty, hipStream_t s, int* resident = nullptr);
 template <typename T>
 hipError_t launch_ns_batch(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind, int tx,
-                           int ty, hipStream_t s);
+                           int ty, hipStream_t s, int* resident = nullptr);
 hipError_t launch_step_set(long long* nstep, long long value, hipStream_t s);
 hipError_t launch_step_inc(long long* const* counters, int n, hipStream_t s);
 

@@ -171,7 +171,7 @@ def test_batch_matches_individual_bitwise():
 
 @pytest.mark.skip(reason="aborted (SIGABRT inside the former batch autotuner, which re-captured the batch "
                          "graph for every tile shape) with no GPU fault and no cause found by reading; that "
-                         "autotuner is switched off (the batch now tunes with each member's stage kernel) and "
+                         "autotuner is removed (the batch now times its stage kernels directly, without any graph capture) and "
                          "this case stays off the GPU")
 def test_batch_autotune_and_errors():
     torch = need_gpu()
