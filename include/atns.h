@@ -251,10 +251,13 @@ atns_status atns_get_layout(const atns_ctx* ctx, int32_t* nblocks, int32_t* ring
 atns_status atns_set_graphs(atns_ctx* ctx, int32_t on);
 
 /* Per-kernel timing of the fused stage kernels.  While enabled (on != 0),
- * every stage-kernel launch of atns_rk_step is bracketed by a pair of HIP
- * events recorded on the context stream.  atns_profile_read synchronizes,
- * returns the number of timed launches and their summed duration in ms, and
- * clears the record.  Disabling also clears it. */
+ * the stage-kernel launches of each atns_rk_step step (and each atns_rhs
+ * launch) are bracketed by a pair of HIP events recorded on the context
+ * stream, one before the step's first stage launch and one after its last,
+ * with no other work in between; the time includes the short gaps between
+ * back-to-back launches.  atns_profile_read synchronizes, returns the number
+ * of timed launches and their summed duration in ms, and clears the record.
+ * Disabling also clears it. */
 atns_status atns_profile_enable(atns_ctx* ctx, int32_t on);
 atns_status atns_profile_read(atns_ctx* ctx, int64_t* launches, double* total_ms);
 

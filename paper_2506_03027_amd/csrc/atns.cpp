@@ -111,6 +111,7 @@ struct atns_ctx {
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;   // reusable events
   size_t ev_used = 0;                // events recorded since the last read
+  std::vector<int> ev_launches;      // stage launches between each event pair
   std::string err;
 };
 
@@ -387,20 +388,31 @@ hipError_t next_event(atns_ctx* c, hipEvent_t* ev) {
   return hipSuccess;
 }
 
+// Profiled runs of stage-kernel launches: one HIP event before the first
+// launch of a run and one after its last, with nothing else enqueued in
+// between, so the measured time is the launches' own plus the short gaps
+// between back-to-back kernels on one stream.
+hipError_t prof_begin(atns_ctx* c, hipStream_t s) {
+  if (!c->profiling) return hipSuccess;
+  hipEvent_t e;
+  const hipError_t r = next_event(c, &e);
+  return r == hipSuccess ? hipEventRecord(e, s) : r;
+}
+
+hipError_t prof_end(atns_ctx* c, hipStream_t s, int launches) {
+  if (!c->profiling) return hipSuccess;
+  hipEvent_t e;
+  const hipError_t r = next_event(c, &e);
+  if (r != hipSuccess) return r;
+  c->ev_launches.push_back(launches);
+  return hipEventRecord(e, s);
+}
+
 template <typename T>
 hipError_t launch_stage(atns_ctx* c, const StageParams<T>& p, int kind) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->profiling) {
-    hipError_t r = next_event(c, &e0);
-    if (r == hipSuccess) r = next_event(c, &e1);
-    if (r == hipSuccess) r = hipEventRecord(e0, c->stream);
-    if (r != hipSuccess) return r;
-  }
-  hipError_t r = (c->cfg.physics == ATNS_NS)
-                     ? launch_ns_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], c->stream)
-                     : launch_euler_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], c->stream);
-  if (r == hipSuccess && c->profiling) r = hipEventRecord(e1, c->stream);
-  return r;
+  return (c->cfg.physics == ATNS_NS)
+             ? launch_ns_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], c->stream)
+             : launch_euler_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], c->stream);
 }
 
 // Whether the RK4 stages run as two fused pairs: 3-D Euler, classical RK4,
@@ -414,18 +426,9 @@ bool pairs_apply(const atns_ctx* c) {
 
 template <typename T>
 hipError_t launch_pair(atns_ctx* c, const StageParams<T>& pA, const StageParams<T>& pB, int pair, hipStream_t s) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->profiling) {
-    hipError_t r = next_event(c, &e0);
-    if (r == hipSuccess) r = next_event(c, &e1);
-    if (r == hipSuccess) r = hipEventRecord(e0, s);
-    if (r != hipSuccess) return r;
-  }
-  hipError_t r = hipErrorInvalidValue;
   if constexpr (std::is_same<T, float>::value)
-    r = launch_euler_pair<float>(pA, pB, (int)c->tiles.size(), pair, c->tile[0], c->tile[1], s);
-  if (r == hipSuccess && c->profiling) r = hipEventRecord(e1, s);
-  return r;
+    return launch_euler_pair<float>(pA, pB, (int)c->tiles.size(), pair, c->tile[0], c->tile[1], s);
+  return hipErrorInvalidValue;
 }
 
 bool is_async(const atns_ctx* c, int64_t step) { return c->cfg.mode != ATNS_SA && step >= c->C; }
@@ -640,6 +643,7 @@ atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
     p.slot_now = c->D ? (int)(c->step % c->D) : 0;
     const bool pairs = pairs_apply(c);
     StageParams<T> ps[4];
+    HIP_TRY(c, prof_begin(c, c->stream));
     for (int e = 0; e < rk.stages; ++e) {
       p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)e * c->slot_stride : nullptr;
       p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
@@ -673,6 +677,7 @@ atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
       }
       if (rk.low_storage) c->cur = 1 - c->cur;
     }
+    HIP_TRY(c, prof_end(c, c->stream, pairs ? rk.stages / 2 : rk.stages));
     if (pairs) c->cur = 1 - c->cur;   // the new state went to X[1 - cur]
     c->step += 1;
   }
@@ -1067,7 +1072,9 @@ atns_status atns_rhs(atns_ctx* c, void* dev_R) {
     p.ring_write = 0;
     p.Y = (const T*)state_ptr(c);
     p.Yout = (T*)dev_R;
+    HIP_TRY(c, prof_begin(c, c->stream));
     HIP_TRY(c, launch_stage<T>(c, p, kRhsOnly));
+    HIP_TRY(c, prof_end(c, c->stream, 1));
     return ATNS_OK;
   };
   return c->esz == 4 ? go(float{}) : go(double{});
@@ -1267,6 +1274,7 @@ atns_status atns_profile_enable(atns_ctx* c, int32_t on) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->profiling = on != 0;
   c->ev_used = 0;
+  c->ev_launches.clear();
   return ATNS_OK;
 }
 
@@ -1274,14 +1282,17 @@ atns_status atns_profile_read(atns_ctx* c, int64_t* launches, double* total_ms) 
   if (!c || !launches || !total_ms) return fail(c, ATNS_EINVAL, "null argument");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   double tot = 0.0;
+  int64_t n = 0;
   for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
     float ms = 0.f;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]));
     tot += ms;
+    n += c->ev_launches[i / 2];
   }
-  *launches = (int64_t)(c->ev_used / 2);
+  *launches = n;
   *total_ms = tot;
   c->ev_used = 0;
+  c->ev_launches.clear();
   return ATNS_OK;
 }
 

@@ -81,3 +81,33 @@ def test_autotune_picks_and_caches(tmp_path):
     g2.set_state(torch.from_numpy(U0))
     assert g2.autotune(reps=2, cache=cache) == best      # served from the cache
     assert len(open(cache).read().split()) == 4
+
+
+def test_profiled_steps_count_launches_and_keep_results():
+    """Profiling times every step's stage launches (eagerly) and leaves the
+    results bit-identical to unprofiled, graph-captured steps."""
+    torch = need_gpu()
+    announce("profile")
+    n, box = (32, 32, 32), (4.0, 4.0, 4.0)
+    U0 = inputs.smooth_random_state(n, box, seed=4)
+    dt = inputs.cfl_dt(U0, n, box, 3, 1.4, 0.03)
+    cfg = dict(n=n, length=box, nblk=(2, 2, 2), physics="euler", mode="at", algo="saa", L=3, seed=2)
+    outs = []
+    for prof in (False, True):
+        _, g = pair(cfg, "f32", dt=dt)
+        g.set_state(torch.from_numpy(U0))
+        g.step(6)
+        g.profile(prof)
+        g.step(3)
+        if prof:
+            launches, ms = g.profile_read()
+            assert launches == 3 * 4 and ms > 0.0
+            g.step(1)
+            assert g.profile_read()[0] == 4        # the read cleared the record
+            g.profile(False)
+            g.step(1)
+        else:
+            g.step(2)
+        outs.append(to_np(g.get_state()))
+        g.close()
+    assert np.array_equal(outs[0], outs[1])
