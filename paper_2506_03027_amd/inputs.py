@@ -145,6 +145,60 @@ def smooth_random_state(n, length, seed, amp=0.05, modes=3, gamma=1.4, ndim=3,
     return to_conserved(rho, u, v, w, p, gamma)
 
 
+def separable_spec(n, length, seed, amp=0.05, modes=2, gamma=1.4, mach=0.3):
+    """Parameters of a seeded smooth periodic 3-D field whose primitive
+    variables are the uniform state of smooth_random_state plus products of
+    1-D sine waves: per variable a list of (amplitude, sx, sy, sz), the 1-D
+    factors sampled on the grid.  Cheap at any size, and its value at one
+    point is cheap too (separable_at), which the full-size sampled checks
+    need."""
+    rng = np.random.default_rng(seed)
+    xs, ys, zs = grid_axes(n, length)
+    base = [1.0, mach * math.sqrt(gamma), -0.5 * mach * math.sqrt(gamma), 0.25 * mach * math.sqrt(gamma), 1.0]
+    terms = []
+    for _ in range(5):
+        tv = []
+        for _ in range(modes):
+            k = rng.integers(1, 4, size=3)
+            ph = rng.uniform(0, 2 * math.pi, size=3)
+            a = float(amp * rng.uniform(0.5, 1.0))
+            tv.append((a, np.sin(2 * math.pi * k[0] * xs / length[0] + ph[0]),
+                       np.sin(2 * math.pi * k[1] * ys / length[1] + ph[1]),
+                       np.sin(2 * math.pi * k[2] * zs / length[2] + ph[2])))
+        terms.append(tv)
+    return {"base": base, "terms": terms, "gamma": gamma}
+
+
+def _separable_conserved(spec, prim):
+    rho, u, v, w, p = (prim(var) for var in range(5))
+    inv_gm1 = 1.0 / (spec["gamma"] - 1.0)   # a product, not a division, on every backend
+    et = p * inv_gm1 + 0.5 * rho * (u * u + v * v + w * w)
+    return [rho, rho * u, rho * v, rho * w, et]
+
+
+def separable_at(spec, x, y, z):
+    """Conserved variables of separable_spec at grid point (x, y, z), in the
+    same operation order as separable_field, so both give the same bits."""
+    def prim(var):
+        f = spec["base"][var]
+        for a, sx, sy, sz in spec["terms"][var]:
+            f = f + a * (float(sz[z]) * (float(sy[y]) * float(sx[x])))
+        return f
+    return _separable_conserved(spec, prim)
+
+
+def separable_field(spec, conv):
+    """The five conserved fields of separable_spec on the whole grid, each a
+    (nz, ny, nx) array of the type conv() turns a 1-D numpy vector into
+    (numpy itself, or a device tensor): only broadcasting arithmetic."""
+    def prim(var):
+        f = spec["base"][var]
+        for a, sx, sy, sz in spec["terms"][var]:
+            f = f + a * (conv(sz)[:, None, None] * (conv(sy)[None, :, None] * conv(sx)[None, None, :]))
+        return f
+    return _separable_conserved(spec, prim)
+
+
 def cfl_dt(U, n, length, ndim, gamma, cfl):
     """dt = CFL / max_x sum_d (|u_d| + c) / h_d, from the given field."""
     h = spacing(n, length)

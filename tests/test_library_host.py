@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import at as oat, delays as odl
-from paper_2506_03027_amd import atns
+from paper_2506_03027_amd import atns, inputs
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "atns.h")
 
@@ -156,3 +156,13 @@ def test_bench_byte_accounting_matches_the_per_point_figures():
     w2 = W["vortex3d_128_lserk2"]
     assert bench.n_levels(w2) == 3 and bench.n_stages(w2) == 2
     assert bench.algorithmic_bytes_per_point_stage(w2, 2, 4)[0] == 80 + 60 * 3 / 8 + 20 * 3 / 8 / 2
+
+
+def test_separable_field_point_values_equal_whole_field():
+    # the full-size GPU checks evaluate the input field point by point on the
+    # host and as whole arrays on the device: both must give the same bits
+    s = inputs.separable_spec((12, 10, 8), (6.0, 5.0, 4.0), seed=3)
+    F = inputs.separable_field(s, lambda v: v)
+    for x, y, z in [(0, 0, 0), (11, 9, 7), (5, 3, 2), (7, 0, 6)]:
+        assert [F[v][z, y, x] for v in range(5)] == inputs.separable_at(s, x, y, z)
+    assert min(F[0].min(), F[4].min()) > 0.5
