@@ -220,6 +220,11 @@ WORKLOADS = {
     "vortex3d_128": dict(n=(128, 128, 128), length=(10.0, 10.0, 10.0), ndim=3,
                          nblk=(4, 4, 4), physics="euler", rk="rk4", mode="at",
                          algo="saa", L=4, cfl=0.02, precision="f32"),
+    # the 128^3 vortex refined once with the same 4 x 4 x 4 blocks (64^3 each):
+    # one 5-variable level (335 MB) no longer fits the 256 MB last-level cache
+    "vortex3d_256": dict(n=(256, 256, 256), length=(10.0, 10.0, 10.0), ndim=3,
+                         nblk=(4, 4, 4), physics="euler", rk="rk4", mode="at",
+                         algo="saa", L=4, cfl=0.02, precision="f32"),
     # the second-order method of Table 1 cases 1-3 on the same grid and blocks
     "vortex3d_128_lserk2": dict(n=(128, 128, 128), length=(10.0, 10.0, 10.0), ndim=3,
                                 nblk=(4, 4, 4), physics="euler", rk="lserk2", mode="at",
