@@ -616,7 +616,7 @@ def main():
                     help="learned-halo run (Taylor-Green workloads): train, then AT with and without it")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus 1 only)",
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus 1 only)",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -7,7 +7,7 @@ itself uses, and the correction is added to every stage's AT halo value:
     Uhat_MLP^(e)(x) = Uhat_AT^(e)(x) + delta(x),   delta_v = r_v * out_v,
 
 unless the correction is implausibly large, |out|_2 > tau, in which case the
-AT value is kept (the fallback; the AT stencil stays the judge of the MLP).
+AT value is kept (the fallback: the AT stencil decides whether the MLP output is used).
 
 Features (64 per sample).  The halo point x lies in the neighbour's
 boundary layer; along the face normal it has layer neighbours j-1, j, j+1

@@ -1433,7 +1433,7 @@ atns_status atns_autotune(atns_ctx* c, int32_t reps, const char* cache_path, int
   if (reps < 1) return fail(c, ATNS_EINVAL, "reps must be positive");
   const std::string key = tune_key(c);
   int pick[3];
-  // entries naming a shape this build does not provide are ignored
+  // entries naming a shape the library does not provide are ignored
   const bool cached = cache_lookup(cache_path, key, pick) && shape_supported(c->cfg.physics, pick[0], pick[1]) &&
                       pick[2] >= 1 && pick[2] <= 32767;
   if (!cached) {
