@@ -207,6 +207,20 @@ atns_status atns_rk_step(atns_ctx* ctx, int32_t nsteps);
  * separate kernels.  Default off. */
 atns_status atns_set_fusion(atns_ctx* ctx, int32_t on);
 
+/* Halo assembly inside the first stage (on != 0; default off): in
+ * graph-captured asynchronous steps of Euler contexts, the first stage
+ * kernel computes, before its plane loop, the values of every stage at the
+ * halo points its tile reads -- Eq. 7 with Eqs. 8-15 (AT) or the stale level
+ * (AS), from the ring levels and the step's delays, which it draws itself --
+ * and writes them for the later stages, in place of a separate halo kernel
+ * launch.  Same arithmetic, so the same bits either way.  Not applied to
+ * Navier-Stokes contexts, batch members, steps with the learned halo or the
+ * fused stage pairs, or eager steps.  It saves a launch and one halo write
+ * and read, but the tile's assembly phase before its plane loop is
+ * latency-bound, and on the vortex workloads the step is 1-2% slower.
+ * Errors: ATNS_EINVAL for a null context. */
+atns_status atns_set_halo_fusion(atns_ctx* ctx, int32_t on);
+
 /* Advance nsteps free-running asynchronous steps: the synchronization-
  * avoiding algorithm (Alg. 3) with delays that arise from the run itself
  * instead of a schedule.  One persistent workgroup per block advances its

@@ -99,6 +99,8 @@ struct atns_ctx {
   int64_t step = 0;
   bool state_set = false;
   bool fuse = false;                 // classical RK4 stages 1-2 and 3-4 fused in pairs
+  bool halo_fusion = false;          // halo assembly inside the first stage (graph steps)
+  bool batch_member = false;         // stepped by a batch (its kernels never fuse halos)
   // free-running asynchronous steps: progress counters, abort flag, the
   // block-major tile list (for tiles async_tiles) and per-block ranges
   int* d_prog = nullptr;
@@ -241,6 +243,7 @@ void build_layout(atns_ctx* c) {
     BlockDev& B = c->blocks[b];
     for (int s = 0; s < kNumSlots; ++s) {
       B.hoff[s] = -1;
+      B.roff[s] = -1;
       if (!slot_used(c, s)) continue;
       int dir[3];
       slot_dir(s, dir);
@@ -251,6 +254,7 @@ void build_layout(atns_ctx* c) {
       HaloRegion r;
       r.dst = hoff;
       r.src = c->blocks[B.nbr[s]].lay[slot_opposite(s)];
+      B.roff[s] = r.src;
       r.npts = (int)cnt;
       r.kidx = b * kNumSlots + s;
       const int rid = (int)c->regions.size();
@@ -424,6 +428,15 @@ bool pairs_apply(const atns_ctx* c) {
   return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 16 && ty == 8) || (tx == 32 && ty == 16);
 }
 
+// Whether graph-captured steps assemble the stage halos inside the first
+// stage kernel instead of a separate halo kernel: Euler with delayed halos,
+// without the learned-halo correction (which works on assembled halos) and
+// without the stage pairs.
+bool fuse_halos(const atns_ctx* c) {
+  return c->halo_fusion && !c->batch_member && c->cfg.physics == ATNS_EULER && c->cfg.mode != ATNS_SA &&
+         !c->mlp_on && !pairs_apply(c) && c->hbuf != nullptr;
+}
+
 template <typename T>
 hipError_t launch_pair(atns_ctx* c, const StageParams<T>& pA, const StageParams<T>& pB, int pair, hipStream_t s) {
   if constexpr (std::is_same<T, float>::value)
@@ -506,6 +519,12 @@ StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind, bool fuse
   p.halo = kHaloSync;
   p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)e * c->slot_stride : nullptr;
   p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
+  if (e == 0 && fuse_halos(c)) {
+    p.fuse_halo = 1;
+    p.S = rk.stages;
+    p.W = c->d_W;
+    p.dd = DelayDraw{1, c->nb, c->cfg.algo == ATNS_SAA ? 1 : 0, (unsigned long long)c->cfg.seed};
+  }
   if (e == rk.stages - 1) {   // the last stage also advances the step counter
     p.step_end = c->d_nstep;
     p.done = c->d_done;
@@ -538,7 +557,7 @@ StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind, bool fuse
 // Enqueue the halo work of one asynchronous step with the device step counter.
 template <typename T>
 atns_status enqueue_graph_halos(atns_ctx* c, hipStream_t s) {
-  if (c->cfg.mode == ATNS_SA) return ATNS_OK;
+  if (c->cfg.mode == ATNS_SA || fuse_halos(c)) return ATNS_OK;   // fused: the first stage does it
   // the halo kernel draws the step's delays itself (no injection here)
   const DelayDraw dd{1, c->nb, c->cfg.algo == ATNS_SAA ? 1 : 0, (unsigned long long)c->cfg.seed};
   HIP_TRY(c, launch_halo<T>((const T*)c->ring, (T*)c->hbuf, c->d_regions, c->d_work, (int)c->work.size(),
@@ -1087,6 +1106,13 @@ atns_status atns_set_fusion(atns_ctx* c, int32_t on) {
   return ATNS_OK;
 }
 
+atns_status atns_set_halo_fusion(atns_ctx* c, int32_t on) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  c->halo_fusion = on != 0;
+  drop_graphs(c);
+  return ATNS_OK;
+}
+
 atns_status atns_rk_step(atns_ctx* c, int32_t nsteps) {
   if (!c) return fail(c, ATNS_EINVAL, "null context");
   if (nsteps < 0) return fail(c, ATNS_EINVAL, "negative step count");
@@ -1169,6 +1195,7 @@ atns_status step_async_impl(atns_ctx* c, int nsteps, long long spin_limit, int8_
   for (int e = 0; e < stages; ++e) {
     int kind = 0;
     ps[e] = graph_stage_params<T>(c, e, &kind, false);
+    ps[e].fuse_halo = 0;   // the persistent kernel assembles its own halos
     ps[e].nstep = nullptr;
     ps[e].step_end = nullptr;
     ps[e].done = nullptr;
@@ -1924,6 +1951,7 @@ atns_status atns_batch_create(const atns_config* cfgs, int32_t n, void* stream, 
       delete b;
       return st;
     }
+    c->batch_member = true;
     b->m.push_back(c);
   }
   auto bad = [&](atns_status s, const char* m) {

@@ -21,6 +21,44 @@ __device__ __forceinline__ int wrap(int g, int n) {
   return g;
 }
 
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output i of the stream
+// seeded with `seed` is mix(seed + (i + 1) * golden).
+__device__ __forceinline__ unsigned long long sm64(unsigned long long seed, unsigned long long i) {
+  unsigned long long z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Alg. 3 guard: delays beyond L-1 or beyond the available history are 0.
+__device__ __forceinline__ int guard_delay(long long k, long long n, int L, int C) {
+  return (k < 0 || k > L - 1 || k > n - C + 1) ? 0 : (int)k;
+}
+
+// Delay of step n (n >= C) for (block, slot) index i = b * 18 + slot:
+// CAA (n - C) mod L, SAA SplitMix64 draw mod L; then the guard.
+// x mod L for a small L (1 <= L <= 16) from 32-bit pieces: with
+// x = hi 2^32 + lo, x mod L = ((hi mod L)(2^32 mod L) + lo mod L) mod L,
+// the same value as the 64-bit remainder, at 32-bit cost.
+__device__ __forceinline__ unsigned mod_small(unsigned long long x, unsigned L) {
+  const unsigned hi = (unsigned)(x >> 32), lo = (unsigned)x;
+  const unsigned p32 = (unsigned)((1ull << 32) % L);
+  return ((hi % L) * p32 + lo % L) % L;
+}
+
+__device__ __forceinline__ int draw_delay(long long n, int i, int nblocks, int L, unsigned long long seed, int algo,
+                                          int C) {
+  if (n < C) return 0;   // synchronous steps (not drawn)
+  long long k;
+  if (algo == 0) {
+    k = mod_small((unsigned long long)(n - C), (unsigned)L);
+  } else {
+    const unsigned long long draw = (unsigned long long)n * (unsigned long long)nblocks * kNumSlots + i;
+    k = mod_small(sm64(seed, draw), (unsigned)L);
+  }
+  return guard_delay(k, n, L, C);
+}
+
 // Stage halos of one halo point i of region rg for delay k (Eq. 7 with
 // Eqs. 8-15): read the C delayed levels U^{n-k-l} of the neighbour's layer
 // from the ring (slots slot_now - k - l mod D) and write the S stage values
@@ -57,6 +95,77 @@ __device__ __forceinline__ void assemble_halo_point(const T* __restrict__ ring, 
       for (int l = 0; l < CL; ++l) a = fma(w[l], lev[l], a);
       halo[e * halo_stride + dof] = (T)a;
     }
+  }
+}
+
+// Halo values of the first stage of a step with fused halo assembly: every
+// halo point a tile's plane loop reads gets its S stage values, by the
+// arithmetic of halo_kernel (assemble_halo_point), written to the stage-halo
+// buffers (stage e at hbuf + e * slot_stride).  The Euler tile reads a
+// 2-point apron: along x the columns x0-2 .. x0+nx+1 at its rows and planes,
+// along y likewise, and along z its own columns at planes z0-2 .. z0+nz+1
+// (3-D); the parts of these ranges beyond a block face are that face's halo
+// points.  A point read by two tiles (next to a tile thinner than the apron)
+// is written by both with the same bits.  Ends with a workgroup barrier,
+// after which the tile reads the values.
+template <typename T, int S, int CL, bool STALE>
+__device__ void assemble_tile_halos(const StageParams<T>& p, const BlockDev* __restrict__ B, const TileDev& t,
+                                    long long n) {
+  constexpr int A = 2;   // apron width of the Euler tile
+  T* hb = const_cast<T*>(p.hbuf);
+  const int H = p.H;
+  const int lo[3] = {t.x0, t.y0, t.z0};
+  const int len[3] = {t.nx, t.ny, t.nz};
+  for (int f = 0; f < 6; ++f) {
+    if (B->hoff[f] < 0) continue;
+    const int ax = f >> 1;
+    const int r0 = lo[ax] - A, r1 = lo[ax] + len[ax] + A;   // read range along the face normal
+    int a0, a1;                                              // its part beyond the face, layer-local
+    if (f & 1) {
+      a0 = (r0 > B->s[ax] ? r0 : B->s[ax]) - B->s[ax];
+      a1 = r1 - B->s[ax];
+    } else {
+      a0 = r0 + H;
+      a1 = (r1 < 0 ? r1 : 0) + H;
+    }
+    a0 = a0 > 0 ? a0 : 0;
+    a1 = a1 < H ? a1 : H;
+    if (a1 <= a0) continue;
+    int e0[3], c0[3], b0[3];   // region extents; this tile's box in it and the box origin
+    for (int d = 0; d < 3; ++d) {
+      e0[d] = d == ax ? H : B->s[d];
+      c0[d] = d == ax ? a1 - a0 : len[d];
+      b0[d] = d == ax ? a0 : lo[d];
+    }
+    HaloRegion rg;
+    rg.dst = B->hoff[f];
+    rg.src = B->roff[f];
+    rg.npts = e0[0] * e0[1] * e0[2];
+    const int k = draw_delay(n, t.blk * kNumSlots + f, p.dd.nblocks, p.L, p.dd.seed, p.dd.algo, CL);
+    const int cnt = c0[0] * c0[1] * c0[2];
+    for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+      const int ix = b0[0] + j % c0[0];
+      const int iy = b0[1] + (j / c0[0]) % c0[1];
+      const int iz = b0[2] + j / (c0[0] * c0[1]);
+      const int li = (iz * e0[1] + iy) * e0[0] + ix;
+      assemble_halo_point<T, S, CL, STALE>(p.ring, hb, rg, li, k, p.slot_now, p.D, p.W, p.L, p.slot_stride,
+                                           p.slot_stride);
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void fused_first_stage_halos(const StageParams<T>& p, const BlockDev* __restrict__ B,
+                                                        const TileDev& t) {
+  const long long n = *p.nstep;
+  const bool stale = p.halo == kHaloStale;
+  if (p.S == 4) {
+    if (stale) assemble_tile_halos<T, 4, 5, true>(p, B, t, n); else assemble_tile_halos<T, 4, 5, false>(p, B, t, n);
+  } else if (p.S == 5) {
+    if (stale) assemble_tile_halos<T, 5, 5, true>(p, B, t, n); else assemble_tile_halos<T, 5, 5, false>(p, B, t, n);
+  } else {
+    if (stale) assemble_tile_halos<T, 2, 3, true>(p, B, t, n); else assemble_tile_halos<T, 2, 3, false>(p, B, t, n);
   }
 }
 

@@ -35,7 +35,9 @@ __device__ __forceinline__ EulerLds<T, TX, TY>& euler_lds() {
   return s;
 }
 
-template <typename T, int TX, int TY, int KIND>
+// FUSE: the kernel may assemble the step's halos in its first stage (the
+// per-launch stage kernels); the batch and free-running kernels never do.
+template <typename T, int TX, int TY, int KIND, bool FUSE = false>
 __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDev t) {
   // every apron point (4 per tile row and column) has a thread of its own
   static_assert(4 * (TX + TY) <= TX * TY, "tile shape too narrow for its apron");
@@ -46,6 +48,11 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
   EulerLds<T, TX, TY>& lds = euler_lds<T, TX, TY>();
   stage_block(p.blocks + t.blk, &lds.B);
   const BlockDev* __restrict__ B = &lds.B;
+  if constexpr (FUSE && (KIND == kRK4First || KIND == kLSFirst)) {
+    // graph-captured steps with fused halo assembly: this tile's halo values
+    // of every stage, before they are read (the condition is uniform)
+    if (p.fuse_halo && p.nstep && p.halo != kHaloSync) fused_first_stage_halos(p, B, t);
+  }
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
   const bool act = (tx < t.nx) && (ty < t.ny);
@@ -190,7 +197,7 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
 template <typename T, int TX, int TY, int KIND>
 __global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T> p) {
   const StageParams<T> q = resolve_step(p);
-  euler_tile<T, TX, TY, KIND>(q, p.tiles[blockIdx.x]);
+  euler_tile<T, TX, TY, KIND, true>(q, p.tiles[blockIdx.x]);
   if (p.step_end) finish_step(p.step_end, p.done);
 }
 
@@ -267,9 +274,19 @@ template hipError_t launch_euler_async<double>(const StageParams<double>*, const
 template <typename T, int TX, int TY>
 hipError_t launch_euler_batch_shape(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind,
                                     hipStream_t s, int* resident) {
-  if (resident)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(resident, (const void*)euler_batch_kernel<T, TX, TY, kRK4Mid>,
-                                                        TX * TY, 0);
+  if (resident) {   // the least over the three stage kinds
+    const void* fns[3] = {(const void*)euler_batch_kernel<T, TX, TY, kRK4First>, (const void*)euler_batch_kernel<T, TX, TY, kRK4Mid>,
+                          (const void*)euler_batch_kernel<T, TX, TY, kRK4Last>};
+    int least = 1 << 30;
+    for (const void* f : fns) {
+      int r = 0;
+      const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, f, TX * TY, 0);
+      if (e != hipSuccess) return e;
+      least = r < least ? r : least;
+    }
+    *resident = least;
+    return hipSuccess;
+  }
   dim3 g(grid), b(TX * TY);
   switch (kind) {
     case kRK4First: euler_batch_kernel<T, TX, TY, kRK4First><<<g, b, 0, s>>>(ps, tl, ntiles); break;
@@ -280,8 +297,8 @@ hipError_t launch_euler_batch_shape(const StageParams<T>* ps, const BatchTile* t
   return hipGetLastError();
 }
 
-// With resident != nullptr: only report how many workgroups of the (middle
-// stage) kernel fit on one CU.
+// With resident != nullptr: only report how many workgroups of the kernel
+// fit on one CU (the least over its stage kinds).
 template <typename T>
 hipError_t launch_euler_batch(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind, int tx,
                               int ty, hipStream_t s, int* resident) {

@@ -4,44 +4,6 @@
 
 namespace atns {
 
-// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output i of the stream
-// seeded with `seed` is mix(seed + (i + 1) * golden).
-__device__ __forceinline__ unsigned long long sm64(unsigned long long seed, unsigned long long i) {
-  unsigned long long z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-// Alg. 3 guard: delays beyond L-1 or beyond the available history are 0.
-__device__ __forceinline__ int guard_delay(long long k, long long n, int L, int C) {
-  return (k < 0 || k > L - 1 || k > n - C + 1) ? 0 : (int)k;
-}
-
-// Delay of step n (n >= C) for (block, slot) index i = b * 18 + slot:
-// CAA (n - C) mod L, SAA SplitMix64 draw mod L; then the guard.
-// x mod L for a small L (1 <= L <= 16) from 32-bit pieces: with
-// x = hi 2^32 + lo, x mod L = ((hi mod L)(2^32 mod L) + lo mod L) mod L,
-// the same value as the 64-bit remainder, at 32-bit cost.
-__device__ __forceinline__ unsigned mod_small(unsigned long long x, unsigned L) {
-  const unsigned hi = (unsigned)(x >> 32), lo = (unsigned)x;
-  const unsigned p32 = (unsigned)((1ull << 32) % L);
-  return ((hi % L) * p32 + lo % L) % L;
-}
-
-__device__ __forceinline__ int draw_delay(long long n, int i, int nblocks, int L, unsigned long long seed, int algo,
-                                          int C) {
-  if (n < C) return 0;   // synchronous steps (not drawn)
-  long long k;
-  if (algo == 0) {
-    k = mod_small((unsigned long long)(n - C), (unsigned)L);
-  } else {
-    const unsigned long long draw = (unsigned long long)n * (unsigned long long)nblocks * kNumSlots + i;
-    k = mod_small(sm64(seed, draw), (unsigned)L);
-  }
-  return guard_delay(k, n, L, C);
-}
-
 // Delays of step n for every (block, slot): the rule above, or the injected
 // value (guarded the same way).
 __global__ void delays_kernel(int8_t* out, const int8_t* inject, long long n, int nblocks, int L, int C,

@@ -437,9 +437,19 @@ template hipError_t launch_ns_async<double>(const StageParams<double>*, const As
 template <typename T, int TX, int TY>
 hipError_t launch_ns_batch_shape(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind,
                                  hipStream_t s, int* resident) {
-  if (resident)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(resident, (const void*)ns_batch_kernel<T, TX, TY, kRK4Mid>,
-                                                        (TX + 8) * (TY + 8), 0);
+  if (resident) {   // the least over the three stage kinds
+    const void* fns[3] = {(const void*)ns_batch_kernel<T, TX, TY, kRK4First>, (const void*)ns_batch_kernel<T, TX, TY, kRK4Mid>,
+                          (const void*)ns_batch_kernel<T, TX, TY, kRK4Last>};
+    int least = 1 << 30;
+    for (const void* f : fns) {
+      int r = 0;
+      const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, f, (TX + 8) * (TY + 8), 0);
+      if (e != hipSuccess) return e;
+      least = r < least ? r : least;
+    }
+    *resident = least;
+    return hipSuccess;
+  }
   dim3 g(grid), b((TX + 8) * (TY + 8));
   switch (kind) {
     case kRK4First: ns_batch_kernel<T, TX, TY, kRK4First><<<g, b, 0, s>>>(ps, tl, ntiles); break;
@@ -450,8 +460,8 @@ hipError_t launch_ns_batch_shape(const StageParams<T>* ps, const BatchTile* tl, 
   return hipGetLastError();
 }
 
-// With resident != nullptr: only report how many workgroups of the (middle
-// stage) kernel fit on one CU.
+// With resident != nullptr: only report how many workgroups of the kernel
+// fit on one CU (the least over its stage kinds).
 template <typename T>
 hipError_t launch_ns_batch(const StageParams<T>* ps, const BatchTile* tl, int ntiles, int grid, int kind, int tx,
                            int ty, hipStream_t s, int* resident) {

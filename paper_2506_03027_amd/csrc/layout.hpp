@@ -56,6 +56,8 @@ struct BlockDev {
   long long lay[kNumSlots];  // offset of this block's layer for slot s (-1: unused)
   long long hoff[kNumSlots]; // offset of this block's halo region s in a
                              // stage-halo buffer (-1: unused)
+  long long roff[kNumSlots]; // offset in a ring slot of the neighbour's layer
+                             // that feeds halo region s (-1: unused)
 };
 
 // One reader-side halo region: block b's halo in slot direction s, which is
@@ -174,6 +176,14 @@ struct StageParams {
   double cA;             // epilogue coefficients (see stage kinds)
   double cB;
   int ring_write;        // write the boundary layers of the result
+  // Halo assembly inside the first stage of a graph-captured step (fuse_halo
+  // != 0): before its plane loop, each tile computes, for the halo points it
+  // reads, the values of all S stages (weights W, delays drawn by dd) into
+  // the stage-halo buffers, in place of a separate halo kernel.
+  int fuse_halo;
+  int S;
+  const double* W;
+  DelayDraw dd;
 };
 
 }  // namespace atns
