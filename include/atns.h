@@ -248,7 +248,8 @@ atns_status atns_step_async(atns_ctx* ctx, int32_t nsteps, int64_t spin_limit, i
  * (1/2V) int rho|u|^2 dV and enstrophy (1/2V) int rho|w|^2 dV, vorticity
  * by CD4 on the synchronous global field.  Synchronizes.  Returns
  * ATNS_ENONFINITE (with the values still written) if any value is not
- * finite. */
+ * finite, and ATNS_EINVAL for grids with 5 nx ny nz >= 2^31 points (the
+ * kernel's 32-bit offsets; 512^3 fits). */
 atns_status atns_reduce(atns_ctx* ctx, double* host_out);
 
 /* Number of blocks, and the ring depth D (levels kept), of a context. */

@@ -1264,6 +1264,8 @@ atns_status atns_step_async(atns_ctx* c, int32_t nsteps, int64_t spin_limit, int
 atns_status atns_reduce(atns_ctx* c, double* host_out) {
   if (!c || !host_out) return fail(c, ATNS_EINVAL, "null argument");
   if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+  // the reduction kernel indexes the five fields with 32-bit offsets
+  if (5 * c->field >= (1ll << 31)) return fail(c, ATNS_EINVAL, "grid too large for the reduction (5 n^3 >= 2^31)");
   double inv12h[3];
   for (int d = 0; d < 3; ++d) inv12h[d] = 1.0 / (12.0 * c->h[d]);
   const double dV = c->h[0] * c->h[1] * (c->cfg.ndim == 3 ? c->h[2] : c->cfg.len[2]);

@@ -244,24 +244,33 @@ hipError_t launch_copy_probe(const void* src, void* dst, long long bytes, hipStr
 constexpr int kDiagThreads = 256;
 
 template <typename T>
-__device__ __forceinline__ void vel_at(const T* U, long long field, long long g, double vel[3]) {
+__device__ __forceinline__ void vel_at(const T* U, int field, int g, double vel[3]) {
   const double ir = 1.0 / (double)U[g];
   vel[0] = (double)U[field + g] * ir;
   vel[1] = (double)U[2 * field + g] * ir;
   vel[2] = (double)U[3 * field + g] * ir;
 }
 
+// Per-workgroup partial sums of the five conserved totals, rho |u|^2 and
+// rho |omega|^2 (omega from CD4 velocity derivatives on the periodic global
+// field), in FP64.  Grid-stride over the points in a fixed order, so the
+// result does not depend on timing.  Indices are 32-bit (5 fields of a
+// 512^3 grid stay below 2^31), and each thread walks its points with an
+// incremental (x, y, z) instead of a division per point.
 template <typename T>
 __global__ void __launch_bounds__(kDiagThreads)
     diag_partial_kernel(const T* U, int nx, int ny, int nz, int ndim, double ihx, double ihy,
                         double ihz, double* partials) {
-  const long long field = (long long)nx * ny * nz;
+  const int plane = nx * ny;
+  const int field = plane * nz;
+  const int stride = gridDim.x * blockDim.x;
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  // (x, y, z) of g and of the stride (stride < field is not required)
+  int x = g % nx, y = (g / nx) % ny, z = g / plane;
+  const int dx = stride % nx, dy = (stride / nx) % ny, dz = stride / plane;
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < field;
-       g += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(g % nx);
-    const int y = (int)((g / nx) % ny);
-    const int z = (int)(g / ((long long)nx * ny));
+  const bool three = ndim == 3;
+  for (; g < field; g += stride) {
     double u[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = (double)U[v * field + g];
@@ -270,12 +279,13 @@ __global__ void __launch_bounds__(kDiagThreads)
     acc[5] += (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
     // CD4 velocity derivatives along each direction: dv[d][c] = d u_c / d x_d
     double dv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    const int nd = (ndim == 3) ? 3 : 2;
-    for (int d = 0; d < nd; ++d) {
-      const int n = (d == 0) ? nx : (d == 1 ? ny : nz);
-      const long long st = (d == 0) ? 1 : (d == 1 ? (long long)nx : (long long)nx * ny);
-      const int c = (d == 0) ? x : (d == 1 ? y : z);
-      const double ih = (d == 0) ? ihx : (d == 1 ? ihy : ihz);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (d == 2 && !three) break;
+      const int n = d == 0 ? nx : (d == 1 ? ny : nz);
+      const int st = d == 0 ? 1 : (d == 1 ? nx : plane);
+      const int c = d == 0 ? x : (d == 1 ? y : z);
+      const double ih = d == 0 ? ihx : (d == 1 ? ihy : ihz);
       double vm2[3], vm1[3], vp1[3], vp2[3];
       vel_at(U, field, g + (wrap(c - 2, n) - c) * st, vm2);
       vel_at(U, field, g + (wrap(c - 1, n) - c) * st, vm1);
@@ -288,6 +298,20 @@ __global__ void __launch_bounds__(kDiagThreads)
     const double wy = dv[2][0] - dv[0][2];
     const double wz = dv[0][1] - dv[1][0];
     acc[6] += u[0] * (wx * wx + wy * wy + wz * wz);
+    // advance (x, y, z) by the stride
+    x += dx;
+    int cy = 0;
+    if (x >= nx) {
+      x -= nx;
+      cy = 1;
+    }
+    y += dy + cy;
+    int cz = 0;
+    while (y >= ny) {
+      y -= ny;
+      ++cz;
+    }
+    z += dz + cz;
   }
   // workgroup reduction in a fixed order
   __shared__ double red[7][kDiagThreads];
