@@ -282,9 +282,16 @@ __global__ void __launch_bounds__(256) mlp_halo_kernel(MlpFeatArgs<T> a, MlpNet 
   __shared__ InferScratch S[4];
   load_net(net, L);
   __syncthreads();
+  // the ring slot of level n, resolved once (not per point)
+  MlpFeatArgs<T> af = a;
+  if (af.nstep) {
+    af.slot_now = (int)(*af.nstep % af.D);
+    af.nstep = nullptr;
+  }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   InferScratch& W = S[wave];
   unsigned long long n_ok = 0, n_fb = 0;
+  constexpr int kItems = (kMlpChunk * 5 + 63) / 64;   // (point, variable) items per lane
   for (long long c = (long long)blockIdx.x * 4 + wave; c < nchunks; c += (long long)gridDim.x * 4) {
     const HaloWork ck = chunks[c];
     const HaloRegion rg = regions[ck.region];
@@ -295,7 +302,7 @@ __global__ void __launch_bounds__(256) mlp_halo_kernel(MlpFeatArgs<T> a, MlpNet 
       const int pt = ck.start + p;
       unsigned short* x = W.x + p * kMlpIn;
       if (pt < rg.npts) {
-        level_features(a, rg, fi, pt, k, l, x);
+        level_features(af, rg, fi, pt, k, l, x);
       } else {
 #pragma unroll
         for (int f = 0; f < 15; ++f) x[l * 15 + f] = 0;
@@ -303,6 +310,20 @@ __global__ void __launch_bounds__(256) mlp_halo_kernel(MlpFeatArgs<T> a, MlpNet 
       if (l == 0) {
         x[60] = f2bf(pt < rg.npts && a.L > 1 ? (float)k / (float)(a.L - 1) : 0.f);
         x[61] = x[62] = x[63] = 0;
+      }
+    }
+    // the stage halo values this lane may correct, loaded now so that their
+    // latency hides behind the forward pass
+    T hv[kItems][kMlpMaxStages];
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+      const int j = lane + 64 * q;
+      const int p = j % kMlpChunk, v = j / kMlpChunk;
+      if (j < kMlpChunk * 5 && ck.start + p < rg.npts) {
+        const long long o = rg.dst + (long long)v * rg.npts + ck.start + p;
+#pragma unroll
+        for (int e = 0; e < kMlpMaxStages; ++e)
+          if (e < stages) hv[q][e] = hbuf[e * halo_stride + o];
       }
     }
     wave_sync();
@@ -320,12 +341,16 @@ __global__ void __launch_bounds__(256) mlp_halo_kernel(MlpFeatArgs<T> a, MlpNet 
     n_ok += __popcll(okmask);
     n_fb += __popcll(__ballot(valid && !ok));
     // the 16 x 5 (point, variable) corrections spread over all lanes
-    for (int j = lane; j < kMlpChunk * 5; j += 64) {
+#pragma unroll
+    for (int q = 0; q < kItems; ++q) {
+      const int j = lane + 64 * q;
       const int p = j % kMlpChunk, v = j / kMlpChunk;
-      if ((okmask >> p) & 1ull) {
+      if (j < kMlpChunk * 5 && ((okmask >> p) & 1ull)) {
         const double d = (double)a.r[v] * (double)W.o[p * kMlpOut + v];
         const long long o = rg.dst + (long long)v * rg.npts + ck.start + p;
-        for (int e = 0; e < stages; ++e) hbuf[e * halo_stride + o] = (T)((double)hbuf[e * halo_stride + o] + d);
+#pragma unroll
+        for (int e = 0; e < kMlpMaxStages; ++e)
+          if (e < stages) hbuf[e * halo_stride + o] = (T)((double)hv[q][e] + d);
       }
     }
     wave_sync();   // the next chunk overwrites this wave's scratch
@@ -628,6 +653,7 @@ hipError_t mlp_halo(const MlpFeatArgs<T>& a, const MlpNet& net, const HaloRegion
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const long long nblk = std::min<long long>((nchunks + 3) / 4, (long long)cus * 4);
   if (nblk < 1) return hipSuccess;
+  if (stages < 1 || stages > kMlpMaxStages) return hipErrorInvalidValue;
   mlp_halo_kernel<T><<<(unsigned)nblk, 256, 0, s>>>(a, net, regions, faces, chunks, nchunks, delays, hbuf,
                                                     halo_stride, stages, counters);
   return hipGetLastError();

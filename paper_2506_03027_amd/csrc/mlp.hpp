@@ -18,6 +18,7 @@ constexpr int kOffW3 = kOffB2 + kMlpH;
 constexpr int kOffB3 = kOffW3 + kMlpOut * kMlpH;
 constexpr int kMlpParams = kOffB3 + kMlpOut;   // 9360
 constexpr int kMlpChunk = 16;                  // face-halo points per wave
+constexpr int kMlpMaxStages = 5;               // RK stages a correction is added to (LSERK4)
 
 struct MlpNet {
   float* params;        // FP32 master parameters (kMlpParams)
