@@ -4,17 +4,19 @@ Metric: grid-point x RK-stage updates per second of the FP32 asynchrony-
 tolerant solver (one "step" = one RK step of the whole hot path: delay draw,
 AT halo assembly from the delayed-level ring, CD4 flux divergence, RK stage
 updates, ring write of the new boundary layers), with inputs resident in HBM.
-Reported beside it: the plain FP64 synchronous (SA) path on the same grid,
-the roofline of the dominant (fused stage) kernel from HIP events recorded
-around each of its launches, and the FP64 oracle timed on the host CPU on a
-bounded sample of the same workload (with the FP32 GPU result's L2 error
-against it).
+Reported beside it, on the same grid, start and step count: the plain FP64
+synchronous (SA) path, and, for the Taylor-Green workloads, the FP32 AT solver
+with the learned halo correction; the relative L2 of every path against the
+FP64 SA result; the roofline of the dominant (fused stage) kernel from HIP
+events recorded around its launches and of the whole step; and the FP64 oracle
+timed on the host CPU on a bounded sample of the same workload (with the FP32
+GPU result's L2 error against it).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--no-mlp]
 
-NAME is one of the single-instance workloads (default vortex3d_128: the 3-D
-vortex on 128^3 in 4x4x4 blocks with SAA delays) or batch48, the batched
-persistent launch of 48 uneven instances.
+NAME is one of the single-instance workloads (default tgv_512: the
+Taylor-Green vortex, Re 1600 Mach 0.1, 512^3 in 32^3 blocks, SAA delays up to
+4) or batch48, the batched persistent launch of 48 uneven instances.
 """
 import argparse
 import json
@@ -125,22 +127,75 @@ def time_steps(torch, g, steps):
 TUNE_CACHE = os.environ.get("ATNS_TUNE_CACHE", os.path.join("/tmp", "atns_tune.txt"))
 
 
-def gpu_run(torch, w, precision, mode, steps, warmup, U0, dt):
+def run_path(torch, w, precision, mode, steps, warmup, dt, U0=None, net=None):
+    """One path of the workload from the initial field: the autotuned tiles,
+    `warmup` untimed steps, `steps` timed graph-captured steps, then `steps`
+    eager steps with the stage kernels bracketed by HIP events.  net (the
+    learned halo: theta, s, r, tau) switches the correction on.  Returns the
+    timings, the tiles, the learned-halo counts of the timed steps and the
+    final state (on the device)."""
     g = make_solver(w, precision, mode)
     g.set_dt(dt)
-    g.set_state(torch.from_numpy(U0))
-    tiles = g.autotune(reps=10, cache=TUNE_CACHE)   # tile shape of the stage kernels
+    if U0 is None:
+        g.init_case(atns.CASE_TGV if w["physics"] == "ns" else atns.CASE_VORTEX)
+    else:
+        g.set_state(torch.from_numpy(U0))
+    if net is not None:
+        g.mlp_set_params(net["theta"])
+        g.mlp_set_scales(net["s"], net["r"])
+        g.mlp_enable(True, net["tau"])
+    tiles = g.autotune(reps=10, cache=TUNE_CACHE)
     g.step(warmup)
+    if net is not None:
+        g.mlp_stats()
     ms = time_steps(torch, g, steps)
-    # per-launch durations of the fused stage kernel, from HIP events on the
-    # library's stream, over a second pass of the same length
+    stats = g.mlp_stats() if net is not None else (0, 0)
     g.profile(True)
     g.step(steps)
     launches, kms = g.profile_read()
     g.profile(False)
-    diag, finite = g.reduce()
+    _, finite = g.reduce()
+    U = g.get_state()
     g.close()
-    return ms, launches, kms, finite, tiles
+    return {"ms": ms, "launches": launches, "kms": kms, "finite": finite, "tiles": tiles, "stats": stats, "U": U}
+
+
+def train_halo_net(torch, w, dt, tau=10.0):
+    """The learned halo's network, trained on FP64 synchronous Taylor-Green
+    runs the solver generates at 256^3 in 16x16x8 blocks with the run's dt
+    (the network is the library's; its training kernels run on the GPU)."""
+    tw = dict(inputs.WORKLOADS["tgv_256"], mode="sa", L=w["L"])
+    tr = make_solver(tw, atns.F64)
+    tr.set_dt(dt)
+    tr.init_case(atns.CASE_TGV)
+    tr.step(C_LEVELS + w["L"] + 2)
+    tr.mlp_set_scales(np.ones(5), np.ones(5))
+    X, Y = tr.mlp_sample(8192, 1)
+    X, Y = X.double().cpu().numpy(), Y.double().cpu().numpy()
+    s = (np.sqrt((X[:, :60].reshape(-1, 4, 5, 3) ** 2).mean(axis=(0, 1, 3))) + 1e-30).astype(np.float32)
+    r = (np.sqrt((Y[:, :5] ** 2).mean(axis=0)) + 1e-30).astype(np.float32)
+    tr.mlp_set_scales(s, r)
+    rng = np.random.default_rng(0)
+    theta0 = np.concatenate([rng.standard_normal(64 * 64) * math.sqrt(2.0 / 64), np.zeros(64),
+                             rng.standard_normal(64 * 64) * math.sqrt(2.0 / 64), np.zeros(64),
+                             rng.standard_normal(16 * 64) * math.sqrt(2.0 / 64), np.zeros(16)])
+    tr.mlp_set_params((0.5 * theta0).astype(np.float32))
+    losses = []
+    t0 = time.perf_counter()
+    for rnd in range(6):
+        tr.step(2)
+        losses.extend(tr.mlp_train(100, 1024, 1e-3, 100 + rnd).tolist())
+    train_s = time.perf_counter() - t0
+    theta = tr.mlp_get_params()
+    Xv, Yv = tr.mlp_sample(4096, 999)
+    out = tr.mlp_forward(Xv)[:, :5].double().cpu().numpy()
+    Yn = Yv[:, :5].double().cpu().numpy()
+    tr.close()
+    return {"theta": theta, "s": s, "r": r, "tau": tau,
+            "training": {"grid": list(tw["n"]), "blocks": list(tw["nblk"]), "precision": "f64", "mode": "sa",
+                         "iters": len(losses), "batch": 1024, "seconds": train_s,
+                         "loss_first10": float(np.mean(losses[:10])), "loss_last50": float(np.mean(losses[-50:])),
+                         "halo_mse_at": float((Yn ** 2).mean()), "halo_mse_mlp": float(((out - Yn) ** 2).mean())}}
 
 
 PROBE_BYTES = 1 << 30
@@ -188,34 +243,81 @@ def stored_traffic(workload):
     return rec.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(torch, w, budget_s=15.0):
-    """The FP64 oracle on a bounded sample of the workload: the same block
-    shape and halo scheme on a smaller grid, started from a delayed history
-    of the translating vortex so that every timed step is asynchronous.  The
-    FP32 GPU path runs the same sample for the L2 error."""
+def host_info():
+    """CPU model and core counts of the host the oracle is timed on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+
+
+def oracle_sample(w):
+    """The bounded oracle sample of a workload: the same block shape, halo
+    scheme and delays on a grid of two blocks per axis (at most 64 points),
+    started from a delayed history so that every timed step is asynchronous.
+    Returns (config, history {step: field}, dt, first timed step)."""
     from oracle import solver
     blk = [w["n"][d] // w["nblk"][d] for d in range(3)]
     n = tuple(w["n"][d] if w["n"][d] <= 64 else max(64, 2 * blk[d]) for d in range(3))
     nblk = tuple(n[d] // blk[d] for d in range(3))
-    s = dict(w, n=n, nblk=nblk)
     length = w["length"]
-    stages = n_stages(w)
+    C = n_levels(w)
     cfg = solver.Config(n, length, w["ndim"], nblk, w["physics"], mach=w.get("mach", 0.1),
                         re=w.get("re", 1600.0), rk=w["rk"], mode=w["mode"], algo=w.get("algo", "saa"),
-                        L=w["L"], seed=w.get("seed", 1), C=n_levels(w),
-                        order=2 if w["rk"] == "lserk2" else 4)
+                        L=w["L"], seed=w.get("seed", 1), C=C, order=2 if w["rk"] == "lserk2" else 4)
+    s = dict(w, n=n, nblk=nblk)
     U0 = initial_state(s)
     dt = inputs.cfl_dt(U0, n, length, w["ndim"], 1.4, w["cfl"])
     cfg.dt = dt
-    o = solver.Oracle(cfg)
-    D = n_levels(w) + w["L"]
+    D = C + 2 * w["L"] - 1           # the library's ring depth in the asynchronous modes
     n0 = 2 * D
     hist = {}
-    for m in range(n0 - D + 1, n0 + 1):
-        if w["physics"] == "ns":
-            hist[m] = U0
-        else:
+    if w["physics"] == "ns":
+        # the Taylor-Green field plus smooth perturbations that vary in time
+        g1 = 0.02 * (inputs.smooth_random_state(n, length, seed=41) - 1.0)
+        g2 = 0.02 * (inputs.smooth_random_state(n, length, seed=42) - 1.0)
+        for m in range(n0 - D + 1, n0 + 1):
+            hist[m] = U0 + math.sin(0.3 * (m - n0)) * g1 + (1.0 - math.cos(0.3 * (m - n0))) * g2
+    else:
+        for m in range(n0 - D + 1, n0 + 1):
             hist[m] = inputs.vortex_state(n, length, w["ndim"], t=(m - n0) * dt)
+    return cfg, s, hist, dt, n0
+
+
+def _oracle_steps(args):
+    """Worker: run `steps` oracle steps of the sample; (steps, seconds)."""
+    w, steps = args
+    from oracle import solver
+    cfg, _, hist, _, _ = oracle_sample(w)
+    o = solver.Oracle(cfg)
+    for m in sorted(hist):
+        o.set_state(hist[m], step=m)
+    t0 = time.perf_counter()
+    o.step(steps)
+    return steps, time.perf_counter() - t0
+
+
+def cpu_oracle_timing(w, budget_s=15.0):
+    """The FP64 oracle on a bounded sample of the workload (oracle_sample):
+    first on one host core until budget_s, then as independent copies on
+    every usable core at once (the oracle itself is single-threaded).  Runs
+    before the process touches the GPU, so the worker processes it forks
+    inherit no device state.  Returns the record and the oracle's final
+    state for the GPU comparison (cpu_baseline_l2)."""
+    from oracle import solver
+    import multiprocessing as mp
+    cfg, s, hist, dt, n0 = oracle_sample(w)
+    n = cfg.n
+    stages = n_stages(w)
+    npts = n[0] * n[1] * n[2]
+    o = solver.Oracle(cfg)
+    for m in sorted(hist):
         o.set_state(hist[m], step=m)
     t0 = time.perf_counter()
     done = 0
@@ -223,23 +325,40 @@ def cpu_baseline(torch, w, budget_s=15.0):
         o.step(1)
         done += 1
     elapsed = time.perf_counter() - t0
-    npts = n[0] * n[1] * n[2]
-    value = npts * stages * done / elapsed
-    # the same sample through the FP32 GPU path
+    one = npts * stages * done / elapsed
+    info = host_info()
+    procs = max(1, min(16, info["usable_cpus"]))
+    k = max(1, done // 2)
+    t1 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        pool.map(_oracle_steps, [(w, k)] * procs)
+    wall = time.perf_counter() - t1
+    allc = npts * stages * k * procs / wall
+    sample = ("%s grid %dx%dx%d in %d blocks of %dx%dx%d (the workload's blocks), %s L=%d, asynchronous "
+              "RK steps from a delayed history, FP64 numpy oracle" % (
+                  w["physics"], n[0], n[1], n[2], cfg.nblk[0] * cfg.nblk[1] * cfg.nblk[2],
+                  n[0] // cfg.nblk[0], n[1] // cfg.nblk[1], n[2] // cfg.nblk[2], w.get("algo", "saa").upper(),
+                  w["L"]))
+    rec = {"value": allc, "unit": "grid-point-stage/s", "cores": procs, "kind": "oracle",
+           "sample": sample + "; %d copies at once, one per core, %d steps each" % (procs, k),
+           "seconds": wall, "host": info,
+           "one_core": {"value": one, "cores": 1, "steps": done, "seconds": elapsed}}
+    return rec, o.U, done
+
+
+def cpu_baseline_l2(torch, w, U_oracle, steps):
+    """The oracle sample run through the FP32 GPU path: relative L2 and L-inf
+    against the oracle's state after the same steps."""
+    cfg, s, hist, dt, n0 = oracle_sample(w)
     g = make_solver(s, atns.F32)
     g.set_dt(dt)
     for m in sorted(hist):
         g.set_state(torch.from_numpy(hist[m]), step=m)
-    g.step(done)
+    g.step(steps)
     G = g.get_state().double().cpu().numpy()
     g.close()
-    l2 = float(np.linalg.norm(G - o.U) / np.linalg.norm(o.U))
-    linf = float(np.abs(G - o.U).max() / np.abs(o.U).max())
-    return {"value": value, "unit": "grid-point-stage/s", "cores": 1, "kind": "oracle",
-            "sample": "%s grid %dx%dx%d, %d blocks, %d asynchronous RK steps from a delayed "
-                      "history, FP64 numpy on one host core" % (
-                          w["physics"], n[0], n[1], n[2], nblk[0] * nblk[1] * nblk[2], done),
-            "seconds": elapsed, "fp32_gpu_rel_l2_vs_oracle": l2, "fp32_gpu_rel_linf_vs_oracle": linf}
+    return {"fp32_gpu_rel_l2_vs_oracle": float(np.linalg.norm(G - U_oracle) / np.linalg.norm(U_oracle)),
+            "fp32_gpu_rel_linf_vs_oracle": float(np.abs(G - U_oracle).max() / np.abs(U_oracle).max())}
 
 
 def solver_kwargs(w):
@@ -320,121 +439,6 @@ def batch_main(a, torch):
         "solo_sum": {"value": total * stages * a.steps / (solo_ms * 1e-3), "ms_per_step": solo_ms / a.steps,
                      "note": "each instance alone, own autotuned tiles, graph-captured steps"},
         "batch_vs_solo_sum": solo_ms / ms,
-        "kernel_hash": kernel_source_hash(),
-    }
-    print(json.dumps(out))
-
-
-def mlp_main(a, torch):
-    """Learned-halo run at the workload's size.  The network is trained on
-    FP64 synchronous Taylor-Green runs the solver generates at 256^3 in
-    16x16x8 blocks (same dt as the run), then the FP32 AT solver runs with
-    and without the correction from the same state; the FP64 synchronous
-    solver at the same size is the reference of both errors."""
-    w = inputs.WORKLOADS[a.workload]
-    stages = 4
-    n = w["n"]
-    npts = n[0] * n[1] * n[2]
-    coarse = tuple(min(64, x) for x in n)
-    dt = inputs.cfl_dt(inputs.tgv_state(coarse, mach=w.get("mach", 0.1)), n, w["length"], 3, 1.4, w["cfl"])
-    # 1. training on FP64 synchronous runs at 256^3
-    tw = dict(inputs.WORKLOADS["tgv_256"], mode="sa", L=w["L"])
-    tr = make_solver(tw, atns.F64)
-    tr.set_dt(dt)
-    tr.init_case(atns.CASE_TGV)
-    tr.step(C_LEVELS + w["L"] + 2)
-    tr.mlp_set_scales(np.ones(5), np.ones(5))
-    X, Y = tr.mlp_sample(8192, 1)
-    X, Y = X.double().cpu().numpy(), Y.double().cpu().numpy()
-    s = (np.sqrt((X[:, :60].reshape(-1, 4, 5, 3) ** 2).mean(axis=(0, 1, 3))) + 1e-30).astype(np.float32)
-    r = (np.sqrt((Y[:, :5] ** 2).mean(axis=0)) + 1e-30).astype(np.float32)
-    tr.mlp_set_scales(s, r)
-    rng = np.random.default_rng(0)
-    theta0 = np.concatenate([rng.standard_normal(64 * 64) * math.sqrt(2.0 / 64), np.zeros(64),
-                             rng.standard_normal(64 * 64) * math.sqrt(2.0 / 64), np.zeros(64),
-                             rng.standard_normal(16 * 64) * math.sqrt(2.0 / 64), np.zeros(16)])
-    tr.mlp_set_params((0.5 * theta0).astype(np.float32))
-    losses = []
-    t0 = time.perf_counter()
-    for rnd in range(6):
-        tr.step(2)
-        losses.extend(tr.mlp_train(100, 1024, 1e-3, 100 + rnd).tolist())
-    train_s = time.perf_counter() - t0
-    theta = tr.mlp_get_params()
-    Xv, Yv = tr.mlp_sample(4096, 999)
-    out = tr.mlp_forward(Xv)[:, :5].double().cpu().numpy()
-    Yn = Yv[:, :5].double().cpu().numpy()
-    mse_mlp, mse_at = float(((out - Yn) ** 2).mean()), float((Yn ** 2).mean())
-    tr.close()
-    tau = 10.0
-    total = C_LEVELS + 1 + a.warmup + a.steps
-
-    # 2. FP32 AT without and with the correction, same start and delays
-    def run(use_mlp):
-        g = make_solver(w, atns.F32)
-        g.set_dt(dt)
-        g.init_case(atns.CASE_TGV)
-        if use_mlp:
-            g.mlp_set_params(theta)
-            g.mlp_set_scales(s, r)
-            g.mlp_enable(True, tau)
-        tiles = g.autotune(reps=10, cache=TUNE_CACHE)
-        g.step(C_LEVELS + 1 + a.warmup)
-        g.mlp_stats() if use_mlp else None
-        ms = time_steps(torch, g, a.steps)
-        stats = g.mlp_stats() if use_mlp else (0, 0)
-        U = g.get_state().double()
-        g.close()
-        return ms, stats, U, tiles
-
-    ms_at, _, U_at, tiles = run(False)
-    ms_mlp, stats, U_mlp, _ = run(True)
-    # 3. FP64 synchronous reference at the same size and step count
-    ref = make_solver(dict(w, mode="sa", L=1), atns.F64)
-    ref.set_dt(dt)
-    ref.init_case(atns.CASE_TGV)
-    ref.step(total)
-    U_ref = ref.get_state()
-    ref.close()
-    nrm = float(torch.linalg.vector_norm(U_ref))
-
-    def rel(U):
-        return float(torch.linalg.vector_norm(U - U_ref)) / nrm
-
-    l2_at, l2_mlp = rel(U_at), rel(U_mlp)
-    l2_pair = float(torch.linalg.vector_norm(U_mlp - U_at)) / nrm
-    del U_at, U_mlp, U_ref
-    face_pts = (stats[0] + stats[1]) / a.steps
-    flops = face_pts * 2.0 * (64 * 64 + 64 * 64 + 16 * 64)
-    extra_ms = (ms_mlp - ms_at) / a.steps
-    tflops = flops / (extra_ms * 1e-3) / 1e12 if extra_ms > 0 else None
-    out = {
-        "metric": "grid-point-stage updates/s (FP32 AT+MLP vs FP64 SA)",
-        "value": npts * stages * a.steps / (ms_mlp * 1e-3),
-        "unit": "grid-point-stage/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": C_LEVELS + 1 + a.warmup,
-        "ms_per_step": ms_mlp / a.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": a.workload, "grid": list(n), "blocks": list(w["nblk"]), "physics": "ns",
-                   "scheme": "CD4 + AT halos + learned face-halo correction, RK4", "algo": "SAA",
-                   "L": w["L"], "cfl": w["cfl"], "tiles": list(tiles), "tau": tau},
-        "without_mlp": {"value": npts * stages * a.steps / (ms_at * 1e-3), "ms_per_step": ms_at / a.steps},
-        "mlp": {"face_points_per_step": face_pts, "applied": stats[0], "fallback": stats[1],
-                "flops_per_step": flops, "extra_ms_per_step": extra_ms, "achieved_tflops": tflops,
-                "mfma_frac_of_bf16_peak": (tflops / 2500.0) if tflops else None,
-                "training": {"grid": list(tw["n"]), "blocks": list(tw["nblk"]), "precision": "f64",
-                             "mode": "sa", "iters": len(losses), "batch": 1024, "seconds": train_s,
-                             "loss_first10": float(np.mean(losses[:10])),
-                             "loss_last50": float(np.mean(losses[-50:])),
-                             "halo_mse_at": mse_at, "halo_mse_mlp": mse_mlp}},
-        "rel_l2_vs_fp64_sa": {"at": l2_at, "at_mlp": l2_mlp, "at_mlp_minus_at": l2_pair,
-                              "steps": total, "reference": "FP64 synchronous GPU run, same grid and dt"},
         "kernel_hash": kernel_source_hash(),
     }
     print(json.dumps(out))
@@ -596,65 +600,69 @@ def series_main(a, torch):
     print(json.dumps(out))
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="vortex3d_128")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--series", type=int, default=0,
-                    help="run this many steps with the FP64 diagnostics reduced after every step")
-    ap.add_argument("--series-out", default=None, help="CSV file for --series")
-    ap.add_argument("--series-ref", action="store_true",
-                    help="with --series: also run the FP64 synchronous solver and compare the series")
-    ap.add_argument("--free-running", action="store_true",
-                    help="free-running asynchronous steps (one persistent workgroup per block) next to the "
-                         "scheduled graph-captured steps on the same workload")
-    ap.add_argument("--mlp", action="store_true",
-                    help="learned-halo run (Taylor-Green workloads): train, then AT with and without it")
-    a = ap.parse_args()
-    if a.gpus != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus 1 only)",
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
-    torch.cuda.set_device(0)
-    if a.workload == "batch48":
-        batch_main(a, torch)
-        return
-    if a.mlp:
-        mlp_main(a, torch)
-        return
-    if a.free_running:
-        free_running_main(a, torch)
-        return
-    if a.series:
-        series_main(a, torch)
-        return
+METRIC = "grid-point\u00b7RK-stage updates/s, FP32 AT(+MLP) vs FP64 plain, at stated L2 err"
+
+
+def coarse_dt(w):
+    """dt from the CFL number, with the wave speeds sampled on a copy of the
+    initial field at most 64 points per axis (the field is analytic)."""
+    coarse = tuple(min(64, x) for x in w["n"])
+    if w["physics"] == "ns":
+        Uc = inputs.tgv_state(coarse, mach=w.get("mach", 0.1))
+    else:
+        Uc = inputs.vortex_state(coarse, w["length"], w["ndim"])
+    return inputs.cfl_dt(Uc, w["n"], w["length"], w["ndim"], 1.4, w["cfl"])
+
+
+def equal_accuracy(torch, w, dt, total, U_ref):
+    """Discretization error of the FP64 synchronous solution, estimated from
+    the same run on the grid coarsened by 2 (twice the step, half the steps;
+    the initial field is analytic): e_h ~ |U_2h - U_h| / (2^4 - 1) for a
+    fourth-order scheme in space and time."""
+    n2 = tuple(x // 2 for x in w["n"])
+    if any(x % 2 for x in w["n"]) or total % 2 or min(n2[d] // w["nblk"][d] for d in range(w["ndim"])) < 4:
+        return None
+    w2 = dict(w, n=n2)
+    g = make_solver(dict(w2, mode="sa", L=1), atns.F64)
+    g.set_dt(2 * dt)
+    g.init_case(atns.CASE_TGV if w["physics"] == "ns" else atns.CASE_VORTEX)
+    g.step(total // 2)
+    U2 = g.get_state()
+    g.close()
+    sub = U_ref[:, ::2, ::2, ::2] if w["ndim"] == 3 else U_ref[:, :, ::2, ::2]
+    e2h = float(torch.linalg.vector_norm(U2 - sub) / torch.linalg.vector_norm(sub))
+    return {"grid_2h": list(n2), "rel_l2_2h_vs_h": e2h, "fp64_sa_disc_err_est": e2h / 15.0}
+
+
+def headline_main(a, torch, cpu):
+    """FP32 AT (the metric), FP32 AT with the learned halo and FP64 SA on the
+    workload from the same initial field, dt and step count; the L2 of each
+    against FP64 SA; rooflines; the CPU baseline."""
     w = inputs.WORKLOADS[a.workload]
     stages = n_stages(w)
     npts = w["n"][0] * w["n"][1] * w["n"][2]
-    U0 = initial_state(w)
-    dt = inputs.cfl_dt(U0, w["n"], w["length"], w["ndim"], 1.4, w["cfl"])
+    ns = w["physics"] == "ns"
+    dt = coarse_dt(w)
+    U0 = None                                 # the analytic initial field, computed on the device
     warmup = max(a.warmup, n_levels(w) + 1)   # the first C steps are synchronous
+    warmup += warmup % 2                      # an even total step count (equal_accuracy)
+    total = warmup + 2 * a.steps
 
-    ms, launches, kms, finite, tiles = gpu_run(torch, w, atns.F32, None, a.steps, warmup, U0, dt)
-    value = npts * stages * a.steps / (ms * 1e-3)
+    at = run_path(torch, w, atns.F32, None, a.steps, warmup, dt, U0)
+    value = npts * stages * a.steps / (at["ms"] * 1e-3)
     bpp, f = algorithmic_bytes_per_point_stage(w, stages, 4)
     kbpp = stage_kernel_bytes_per_point(w, stages, 4)
-    avg_launch_ms = kms / max(1, launches)
+    avg_launch_ms = at["kms"] / max(1, at["launches"])
     achieved = kbpp * npts / (avg_launch_ms * 1e-3) / 1e9
-    step_achieved = bpp * npts * stages * a.steps / (ms * 1e-3) / 1e9
+    step_achieved = bpp * npts * stages * a.steps / (at["ms"] * 1e-3) / 1e9
     out = {
-        "metric": "grid-point-stage updates/s (FP32 AT vs FP64 SA)",
+        "metric": METRIC,
         "value": value,
         "unit": "grid-point-stage/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": warmup,
-        "ms_per_step": ms / a.steps,
+        "ms_per_step": at["ms"] / a.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -664,34 +672,113 @@ def main():
                    "physics": w["physics"],
                    "scheme": "%s + %s halos, %s" % ("CD2" if w["rk"] == "lserk2" else "CD4", w["mode"].upper(),
                                                     w["rk"].upper()),
-                   "algo": w.get("algo", "saa").upper(), "L": w["L"], "cfl": w["cfl"],
-                   "tiles": list(tiles)},
+                   "algo": w.get("algo", "saa").upper(), "L": w["L"], "cfl": w["cfl"], "dt": dt,
+                   "tiles": list(at["tiles"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(a.workload),
-                     "kernel": "%s_stage_kernel" % ("ns" if w["physics"] == "ns" else "euler"),
+                     "kernel": "%s_stage_kernel" % ("ns" if ns else "euler"),
                      "bytes_per_point_launch": kbpp, "halo_points_per_point": f,
-                     "avg_launch_ms": avg_launch_ms, "launches": launches,
+                     "avg_launch_ms": avg_launch_ms, "launches": at["launches"],
+                     "basis": "stage-kernel algorithmic bytes (state, RK register, one assembled halo value per "
+                              "halo point, ring write) over the kernel's average launch time from HIP events",
                      "step": {"bytes_per_point_stage": bpp, "achieved": step_achieved,
                               "frac": step_achieved / HBM_PEAK_GBS,
                               "basis": "whole-step algorithmic bytes (C delayed levels per halo point and "
                                        "stage) over the graph-launch time per step"}},
-        "finite": finite,
+        "finite": at["finite"],
     }
+    U_at = at.pop("U")
+    # the learned halo, trained on the GPU by the library's kernels
+    U_mlp = None
+    if ns and w["rk"] == "rk4" and w["mode"] == "at" and not a.no_mlp:
+        net = train_halo_net(torch, w, dt)
+        ml = run_path(torch, w, atns.F32, None, a.steps, warmup, dt, U0, net=net)
+        U_mlp = ml.pop("U")
+        face_pts = (ml["stats"][0] + ml["stats"][1]) / a.steps
+        flops = face_pts * 2.0 * (64 * 64 + 64 * 64 + 16 * 64)
+        extra_ms = (ml["ms"] - at["ms"]) / a.steps
+        tflops = flops / (extra_ms * 1e-3) / 1e12 if extra_ms > 0 else None
+        out["at_mlp"] = {"value": npts * stages * a.steps / (ml["ms"] * 1e-3), "ms_per_step": ml["ms"] / a.steps,
+                         "tau": net["tau"], "applied": ml["stats"][0], "fallback": ml["stats"][1],
+                         "face_points_per_step": face_pts, "flops_per_step": flops,
+                         "extra_ms_per_step": extra_ms, "achieved_tflops": tflops,
+                         "mfma_frac_of_bf16_peak": (tflops / 2500.0) if tflops else None,
+                         "training": net["training"]}
     probe = hbm_probe(torch)
     out["hbm_probe"] = probe
     out["roofline"]["frac_of_probe"] = achieved / probe["GBps"]
     out["kernel_hash"] = kernel_source_hash()
     if not a.no_fp64:
-        ms64, l64, k64, fin64, _ = gpu_run(torch, w, atns.F64, "sa", a.steps, warmup, U0, dt)
+        sa = run_path(torch, dict(w, mode="sa", L=1), atns.F64, "sa", a.steps, warmup, dt, U0)
+        U_ref = sa.pop("U")
         b64 = stage_kernel_bytes_per_point(dict(w, mode="sa"), stages, 8)
-        out["fp64_sa"] = {"value": npts * stages * a.steps / (ms64 * 1e-3),
-                          "ms_per_step": ms64 / a.steps,
-                          "avg_launch_ms": k64 / max(1, l64),
-                          "hbm_frac": b64 * npts / (k64 / max(1, l64) * 1e-3) / 1e9 / HBM_PEAK_GBS}
-        out["speedup_vs_fp64_sa"] = out["value"] / out["fp64_sa"]["value"]
-    if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(torch, w)
+        k64 = sa["kms"] / max(1, sa["launches"])
+        out["fp64_sa"] = {"value": npts * stages * a.steps / (sa["ms"] * 1e-3), "ms_per_step": sa["ms"] / a.steps,
+                          "avg_launch_ms": k64, "hbm_frac": b64 * npts / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "tiles": list(sa["tiles"])}
+        nrm = float(torch.linalg.vector_norm(U_ref))
+        rel = lambda U: float(torch.linalg.vector_norm(U.double() - U_ref)) / nrm
+        relinf = lambda U: float((U.double() - U_ref).abs().max() / U_ref.abs().max())
+        l2 = {"steps": total, "reference": "FP64 synchronous GPU run, same grid, initial field and dt",
+              "at": rel(U_at), "at_linf": relinf(U_at)}
+        if U_mlp is not None:
+            l2["at_mlp"] = rel(U_mlp)
+            l2["at_mlp_linf"] = relinf(U_mlp)
+            l2["at_mlp_minus_at"] = float(torch.linalg.vector_norm(U_mlp - U_at)) / nrm
+        out["rel_l2_vs_fp64_sa"] = l2
+        out["speedup_vs_fp64_sa"] = value / out["fp64_sa"]["value"]
+        del U_at, U_mlp
+        eq = equal_accuracy(torch, w, dt, total, U_ref)
+        if eq is not None:
+            eq["fp32_at_err_vs_fp64_sa"] = l2["at"]
+            eq["ratio"] = l2["at"] / eq["fp64_sa_disc_err_est"]
+            eq["note"] = ("the FP32 AT path departs from the FP64 synchronous solution by this fraction of the "
+                          "latter's own discretization error, so the two are at equal accuracy to within it and "
+                          "speedup_vs_fp64_sa is the speed-up at equal accuracy")
+            out["equal_accuracy"] = eq
+        del U_ref
+    if cpu is not None:
+        rec, U_or, steps_or = cpu
+        rec.update(cpu_baseline_l2(torch, w, U_or, steps_or))
+        out["cpu_baseline"] = rec
     print(json.dumps(out))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=6)
+    ap.add_argument("--workload", default="tgv_512")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-halo path")
+    ap.add_argument("--series", type=int, default=0,
+                    help="run this many steps with the FP64 diagnostics reduced after every step")
+    ap.add_argument("--series-out", default=None, help="CSV file for --series")
+    ap.add_argument("--series-ref", action="store_true",
+                    help="with --series: also run the FP64 synchronous solver and compare the series")
+    ap.add_argument("--free-running", action="store_true",
+                    help="free-running asynchronous steps (one persistent workgroup per block) next to the "
+                         "scheduled graph-captured steps on the same workload")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path (--gpus 1 only)",
+              file=sys.stderr)
+        sys.exit(2)
+    single = a.workload != "batch48" and not a.free_running and not a.series
+    # the oracle's timing runs before anything touches the GPU (it forks workers)
+    cpu = cpu_oracle_timing(inputs.WORKLOADS[a.workload]) if (single and not a.no_cpu) else None
+    import torch
+    torch.cuda.set_device(0)
+    if a.workload == "batch48":
+        batch_main(a, torch)
+    elif a.free_running:
+        free_running_main(a, torch)
+    elif a.series:
+        series_main(a, torch)
+    else:
+        headline_main(a, torch, cpu)
 
 
 if __name__ == "__main__":

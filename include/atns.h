@@ -108,7 +108,8 @@ const char* atns_version(void);
 
 /* Create a context on the current HIP device.  Validates the configuration
  * (EINVAL: block smaller than the halo depth in an active direction, split
- * not summing to n, L < 1 or L > 16, unknown enums, ndim == 2 with nz != 1)
+ * not summing to n, L < 1 or L > 16, unknown enums, ndim == 2 with nz != 1,
+ * a Navier-Stokes grid with 5 nx ny nz >= 2^31 points)
  * before any device call.  stream: a hipStream_t, or NULL.  On success *out
  * owns all device buffers: state and RK registers, the delayed-level ring
  * (C + 2L - 1 levels of each block's boundary layers in modes AT and AS,
@@ -183,10 +184,18 @@ atns_status atns_set_delays(atns_ctx* ctx, int64_t step0, int32_t nsteps, const 
  * report all zeros and set *synchronous = 1. */
 atns_status atns_get_delays(atns_ctx* ctx, int64_t step, int8_t* host_k, int32_t* synchronous);
 
-/* Right-hand side R(U^n) of the current state with the halo of stage 0 of
- * the current step (synchronous, AS or AT as configured), into dev_R (field
- * layout, context precision).  Does not advance the step. */
-atns_status atns_rhs(atns_ctx* ctx, void* dev_R);
+/* Right-hand side R(U^n) of the current state, into dev_R (field layout,
+ * context precision), with the halo values that stage `stage` of the current
+ * step reads (0 <= stage < s; s = 4 for RK4, 5 for LSERK4, 2 for LSERK2):
+ * under AT the buffer extrapolation of Eqs. 14-15 for stage 0 and the
+ * RK-consistent buffer update of Eqs. 8-13 (Table 5, App. C) for later
+ * stages, Uhat^(e) = sum_l W[e][k][l] U^{n-k-l}; under AS the stale level
+ * U^{n-k} for every stage; synchronous steps (SA mode, or n < C) read the
+ * current state itself, whatever the stage.  The owned points always take
+ * the current state, so this evaluates the stage operator of Eq. 1 on U^n
+ * with that stage's halo.  Does not advance the step.  EINVAL for a stage
+ * outside 0..s-1 or a null pointer; ESTATE before a state is set. */
+atns_status atns_rhs(atns_ctx* ctx, int32_t stage, void* dev_R);
 
 /* Advance nsteps steps (asynchronous on the context stream).  Each step: the
  * delay draw, s fused stencil + RK-stage kernels (the halo of stage e from
@@ -278,7 +287,8 @@ atns_status atns_profile_read(atns_ctx* ctx, int64_t* launches, double* total_ms
 
 /* Tile shape of the stage kernels: a workgroup walks a TX x TY column of one
  * block through TZ planes.  Supported (TX, TY): Euler (16,16) (32,8) (16,8)
- * (64,8) (32,16); Navier-Stokes (16,16) (32,8) (16,8).  Tiles never straddle
+ * (64,8) (32,16); Navier-Stokes (16,16) (32,8) (16,8), and (32,16) in single
+ * precision.  Tiles never straddle
  * blocks; ragged edges are handled.  EINVAL for other shapes or tz < 1. */
 atns_status atns_set_tiles(atns_ctx* ctx, int32_t tx, int32_t ty, int32_t tz);
 atns_status atns_get_tiles(const atns_ctx* ctx, int32_t* tx, int32_t* ty, int32_t* tz);

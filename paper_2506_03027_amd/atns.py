@@ -83,7 +83,7 @@ def lib():
             "atns_set_dt": ([vp, dbl], i32),
             "atns_set_delays": ([vp, i64, i32, vp], i32),
             "atns_get_delays": ([vp, i64, vp, ctypes.POINTER(i32)], i32),
-            "atns_rhs": ([vp, vp], i32),
+            "atns_rhs": ([vp, i32, vp], i32),
             "atns_rk_step": ([vp, i32], i32),
             "atns_step_async": ([vp, i32, i64, vp], i32),
             "atns_set_fusion": ([vp, i32], i32),
@@ -266,10 +266,11 @@ class Solver:
         _check(lib().atns_get_step(self.ctx, ctypes.byref(s)), self.ctx)
         return s.value
 
-    def rhs(self):
+    def rhs(self, stage=0):
+        """R(U^n) with the halo values RK stage `stage` of the current step reads."""
         out = self.torch.empty(self.shape, dtype=self.dtype, device="cuda")
         self.torch.cuda.synchronize()
-        _check(lib().atns_rhs(self.ctx, ctypes.c_void_p(out.data_ptr())), self.ctx)
+        _check(lib().atns_rhs(self.ctx, int(stage), ctypes.c_void_p(out.data_ptr())), self.ctx)
         self.torch.cuda.synchronize()
         return out
 

@@ -182,6 +182,9 @@ atns_status validate(const atns_config* cfg, std::vector<int> split[3], atns_ctx
   }
   if (cfg->ndim == 2 && (cfg->n[2] != 1 || cfg->nblk[2] != 1))
     return fail(c, ATNS_EINVAL, "2D needs nz == 1 and one block in z");
+  // the Navier-Stokes stage kernel addresses a field with 32-bit offsets
+  if (cfg->physics == ATNS_NS && 5.0 * cfg->n[0] * cfg->n[1] * cfg->n[2] >= 2147483648.0)
+    return fail(c, ATNS_EINVAL, "Navier-Stokes grid too large: 5 nx ny nz must stay below 2^31");
   return ATNS_OK;
 }
 
@@ -303,18 +306,22 @@ void build_tiles(atns_ctx* c, int TX, int TY, int TZ) {
 }
 
 // (TX, TY) column shapes the stage kernels are instantiated for.  The
-// Navier-Stokes kernel runs one thread per point of the tile plus a 4-point
-// apron, which caps its tiles at (16,16) and (32,8) (at most 1024 threads).
+// single-precision Navier-Stokes kernel runs one thread per tile column and
+// also takes 32 x 16; the double-precision one runs one thread per point of
+// the tile plus a 4-point apron, whose LDS caps it at the first three.
 constexpr int kNumEulerShapes = 5;
 constexpr int kEulerShapes[kNumEulerShapes][2] = {{16, 16}, {32, 8}, {16, 8}, {64, 8}, {32, 16}};
-constexpr int kNumNsShapes = 3;
-constexpr int kNsShapes[kNumNsShapes][2] = {{16, 16}, {32, 8}, {16, 8}};
+constexpr int kNumNsShapes = 4;
+constexpr int kNsShapes[kNumNsShapes][2] = {{16, 16}, {32, 8}, {16, 8}, {32, 16}};
 
-int num_shapes(int physics) { return physics == ATNS_NS ? kNumNsShapes : kNumEulerShapes; }
+// esz: bytes per value of the context's precision
+int num_shapes(int physics, size_t esz) {
+  return physics == ATNS_NS ? (esz == 4 ? kNumNsShapes : kNumNsShapes - 1) : kNumEulerShapes;
+}
 const int* shape_at(int physics, int i) { return physics == ATNS_NS ? kNsShapes[i] : kEulerShapes[i]; }
 
-bool shape_supported(int physics, int tx, int ty) {
-  for (int i = 0; i < num_shapes(physics); ++i)
+bool shape_supported(int physics, size_t esz, int tx, int ty) {
+  for (int i = 0; i < num_shapes(physics, esz); ++i)
     if (shape_at(physics, i)[0] == tx && shape_at(physics, i)[1] == ty) return true;
   return false;
 }
@@ -542,6 +549,7 @@ StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind, bool fuse
     *kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
     p.cA = rk.b[e];
     p.cB = e < 3 ? rk.a[e + 1][e] : 0.0;
+    p.fold = e == 2 ? 1 : 0;   // U^n joins the accumulator in the last middle stage
   } else {
     const int cur = (c->cur + e) & 1;
     p.Y = (const T*)c->X[cur];
@@ -680,6 +688,7 @@ atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
         kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
         p.cA = rk.b[e];
         p.cB = e < 3 ? rk.a[e + 1][e] : 0.0;
+        p.fold = e == 2 ? 1 : 0;   // U^n joins the accumulator in the last middle stage
       } else {
         p.Y = (const T*)c->X[c->cur];
         p.Yout = (T*)c->X[1 - c->cur];
@@ -1074,8 +1083,9 @@ atns_status atns_get_delays(atns_ctx* c, int64_t step, int8_t* host_k, int32_t* 
   return ATNS_OK;
 }
 
-atns_status atns_rhs(atns_ctx* c, void* dev_R) {
+atns_status atns_rhs(atns_ctx* c, int32_t stage, void* dev_R) {
   if (!c || !dev_R) return fail(c, ATNS_EINVAL, "null argument");
+  if (stage < 0 || stage >= c->rk.stages) return fail(c, ATNS_EINVAL, "stage outside 0..s-1");
   if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
   const bool async = is_async(c, c->step);
   auto go = [&](auto tag) -> atns_status {
@@ -1087,7 +1097,7 @@ atns_status atns_rhs(atns_ctx* c, void* dev_R) {
     StageParams<T> p = base_params<T>(c);
     p.halo = !async ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
     p.slot_now = c->D ? (int)(c->step % c->D) : 0;
-    p.hbuf = (const T*)c->hbuf;
+    p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)stage * c->slot_stride : nullptr;
     p.ring_write = 0;
     p.Y = (const T*)state_ptr(c);
     p.Yout = (T*)dev_R;
@@ -1327,7 +1337,7 @@ atns_status atns_profile_read(atns_ctx* c, int64_t* launches, double* total_ms) 
 
 atns_status atns_set_tiles(atns_ctx* c, int32_t tx, int32_t ty, int32_t tz) {
   if (!c) return fail(c, ATNS_EINVAL, "null context");
-  if (!shape_supported(c->cfg.physics, tx, ty) || tz < 1 || tz > 32767)
+  if (!shape_supported(c->cfg.physics, c->esz, tx, ty) || tz < 1 || tz > 32767)
     return fail(c, ATNS_EINVAL, "unsupported tile shape");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->tile[0] = tx;
@@ -1389,11 +1399,17 @@ void cache_store(const char* path, const std::string& key, const int v[3]) {
 // accumulator (RK4), or Q and the spare buffer (LSERK4).  The last stage's
 // output goes to a stage register instead of the state, and its ring write to
 // slot (n + 1) mod D, whose level n + 1 - D no stage of step n reads.
+// Contexts with delayed halos read the stage-halo buffer, as their
+// asynchronous steps do (probe_halos fills it).
 template <typename T>
 StageParams<T> probe_stage(atns_ctx* c, int e, int* kind_out) {
   const RKScheme& rk = c->rk;
   StageParams<T> p = base_params<T>(c);
   p.halo = kHaloSync;
+  if (c->hbuf) {
+    p.halo = c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT;
+    p.hbuf = (const T*)c->hbuf + (size_t)e * c->slot_stride;
+  }
   p.slot_now = c->D ? (int)(c->step % c->D) : 0;
   p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
   int kind;
@@ -1410,6 +1426,7 @@ StageParams<T> probe_stage(atns_ctx* c, int e, int* kind_out) {
     kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
     p.cA = rk.b[e];
     p.cB = e < 3 ? rk.a[e + 1][e] : 0.0;
+    p.fold = e == 2 ? 1 : 0;   // U^n joins the accumulator in the last middle stage
   } else {
     // the state buffer is only ever read; the stages alternate between
     // the spare buffer and X[2], which low-storage schemes do not use
@@ -1425,10 +1442,20 @@ StageParams<T> probe_stage(atns_ctx* c, int e, int* kind_out) {
   return p;
 }
 
+// The stage-halo buffer of the current step, for timing probes of contexts
+// with delayed halos.  The buffer is rewritten at the start of every
+// asynchronous step, so it is dead at a step boundary.
+template <typename T>
+atns_status probe_halos(atns_ctx* c) {
+  return c->hbuf ? prepare_halos<T>(c) : ATNS_OK;
+}
+
 template <typename T>
 atns_status time_shape(atns_ctx* c, int reps, float* ms_out) {
   // One step's mix of stage kernels -- first, middle and last RK stage, the
   // last with its ring write -- as timing probes.
+  atns_status st = probe_halos<T>(c);
+  if (st != ATNS_OK) return st;
   std::vector<std::pair<StageParams<T>, int>> seq;
   for (int e = 0; e < c->rk.stages; ++e) {
     int kind;
@@ -1463,7 +1490,7 @@ atns_status atns_autotune(atns_ctx* c, int32_t reps, const char* cache_path, int
   const std::string key = tune_key(c);
   int pick[3];
   // entries naming a shape the library does not provide are ignored
-  const bool cached = cache_lookup(cache_path, key, pick) && shape_supported(c->cfg.physics, pick[0], pick[1]) &&
+  const bool cached = cache_lookup(cache_path, key, pick) && shape_supported(c->cfg.physics, c->esz, pick[0], pick[1]) &&
                       pick[2] >= 1 && pick[2] <= 32767;
   if (!cached) {
     const bool ns = c->cfg.physics == ATNS_NS;
@@ -1472,7 +1499,7 @@ atns_status atns_autotune(atns_ctx* c, int32_t reps, const char* cache_path, int
     pick[0] = c->tile[0];
     pick[1] = c->tile[1];
     pick[2] = c->tile[2];
-    for (int i = 0; i < num_shapes(c->cfg.physics); ++i)
+    for (int i = 0; i < num_shapes(c->cfg.physics, c->esz); ++i)
       for (int tz : tzs) {
         if (c->cfg.ndim == 2 && tz != 4) continue;
         if (ns && tz < 8) continue;   // 8 extra planes per column: short ones waste work
@@ -1995,7 +2022,7 @@ atns_status atns_batch_member(atns_batch* b, int32_t i, atns_ctx** ctx) {
 
 atns_status atns_batch_set_tiles(atns_batch* b, int32_t physics, int32_t tx, int32_t ty, int32_t tz) {
   if (!b || (physics != ATNS_EULER && physics != ATNS_NS)) return bfail(b, ATNS_EINVAL, "bad physics");
-  if (!shape_supported(physics, tx, ty) || tz < 1) return bfail(b, ATNS_EINVAL, "unsupported tile shape");
+  if (!shape_supported(physics, b->esz, tx, ty) || tz < 1) return bfail(b, ATNS_EINVAL, "unsupported tile shape");
   BHIP(b, hipDeviceSynchronize());
   const int ph = physics == ATNS_NS ? 1 : 0;
   b->shape[ph][0] = tx;
@@ -2021,6 +2048,11 @@ namespace {
 template <typename T>
 atns_status batch_time(atns_batch* b, int mask, int reps, float* ms_out) {
   const int n = (int)b->m.size();
+  for (int i = 0; i < n; ++i) {   // members with delayed halos: their stage-halo buffers
+    const atns_status st = probe_halos<T>(b->m[i]);
+    if (st != ATNS_OK) return bfail(b, st, b->m[i]->err);
+  }
+  BHIP(b, hipDeviceSynchronize());
   std::vector<StageParams<T>> ps((size_t)b->stages * n);
   std::vector<int> kinds(b->stages);
   for (int e = 0; e < b->stages; ++e)
@@ -2100,7 +2132,7 @@ atns_status atns_batch_autotune(atns_batch* b, int32_t reps, int32_t* best) {
       continue;
     }
     std::vector<std::pair<float, std::array<int, 3>>> timed;
-    for (int i = 0; i < num_shapes(phys); ++i)
+    for (int i = 0; i < num_shapes(phys, b->esz); ++i)
       for (int tz : {4, 8, 16, 32}) {
         if (ph == 1 && tz < 8) continue;
         const int tx = shape_at(phys, i)[0], ty = shape_at(phys, i)[1];

@@ -310,53 +310,98 @@ __device__ __forceinline__ void fetch_col(const StageParams<T>& p, const BlockDe
   }
 }
 
-// Ring slots of block B whose boundary layer contains the column (lx, ly):
-// the x and y conditions only, the z condition is checked per plane.
-template <typename T>
-__device__ __forceinline__ unsigned ring_mask(const StageParams<T>& p, const BlockDev* __restrict__ B, int lx,
-                                              int ly) {
-  unsigned m = 0;
-  const int ns = (p.H == 4) ? kNumSlots : 6;
-  for (int s = 0; s < ns; ++s) {
-    if (B->lay[s] < 0) continue;
-    int d[3];
-    slot_dir(s, d);
-    const int dep = (s < 6) ? p.H : 2;
-    bool in = true;
-    if (d[0] > 0) in = in && lx >= B->s[0] - dep;
-    if (d[0] < 0) in = in && lx < dep;
-    if (d[1] > 0) in = in && ly >= B->s[1] - dep;
-    if (d[1] < 0) in = in && ly < dep;
-    if (in) m |= 1u << s;
-  }
-  return m;
+// The boundary layers an owned column (lx, ly) of block B belongs to in its
+// x and y conditions, resolved once per column: for the -x, +x, -y and +y
+// faces and the xy edge, the column's offset in that layer at plane 0 (-1
+// when the column is not in it).  A layer [ez][ey][ex] is stored
+// contiguously per variable (layout.hpp); x-faces are [s_z][s_y][H], y-faces
+// [s_z][H][s_x], xy edges [s_z][2][2].  Blocks narrower than 2H can put a
+// column in both faces of one axis; edges are 2 deep and blocks at least H = 4
+// wide, so a column is in at most one xy edge.
+struct RingColumn {
+  int off[5];   // -x face, +x face, -y face, +y face, xy edge
+  int slot[5];  // their ring slots
+};
+
+__device__ __forceinline__ RingColumn ring_column(const BlockDev* __restrict__ B, int H, int lx, int ly) {
+  RingColumn r;
+  const int sx = B->s[0], sy = B->s[1];
+  r.slot[0] = 0;
+  r.slot[1] = 1;
+  r.slot[2] = 2;
+  r.slot[3] = 3;
+  r.off[0] = (B->lay[0] >= 0 && lx < H) ? ly * H + lx : -1;
+  r.off[1] = (B->lay[1] >= 0 && lx >= sx - H) ? ly * H + (lx - (sx - H)) : -1;
+  r.off[2] = (B->lay[2] >= 0 && ly < H) ? ly * sx + lx : -1;
+  r.off[3] = (B->lay[3] >= 0 && ly >= sy - H) ? (ly - (sy - H)) * sx + lx : -1;
+  const int ex = lx < 2 ? 0 : (lx >= sx - 2 ? 1 : -1);
+  const int ey = ly < 2 ? 0 : (ly >= sy - 2 ? 1 : -1);
+  r.slot[4] = 6 + ex + 2 * ey;   // (+-x, +-y) edge slot
+  const int ix = ex == 0 ? lx : lx - (sx - 2), iy = ey == 0 ? ly : ly - (sy - 2);
+  r.off[4] = (ex >= 0 && ey >= 0 && B->lay[r.slot[4]] >= 0) ? iy * 2 + ix : -1;
+  return r;
 }
 
-// Write the values of owned point (lx, ly, lz) into every boundary layer of
-// block B that contains it, in ring slot `slot`; `mask` is ring_mask() of
-// the point's column.
+// Write u[5], the new value of owned point (lx, ly, lz), into every boundary
+// layer of block B in ring slot `slot` that contains it: the column's x/y
+// layers (rc) at plane lz, and, at the planes within H (faces) or 2 (edges)
+// of a z face, the z-face layer and the xz and yz edge layers.  lz is the
+// plane of the whole workgroup, so the z tests are uniform.  act: the thread
+// holds an owned point.  Readers find these values through the region
+// offsets of layout.hpp (roff), so the layer layout here is the one
+// build_layout() assigns.
 template <typename T>
-__device__ __forceinline__ void ring_store(const StageParams<T>& p, const BlockDev* __restrict__ B, unsigned mask,
-                                           int lx, int ly, int lz, const T u[5], T* slot) {
-  while (mask) {
-    const int s = __builtin_ctz(mask);
-    mask &= mask - 1;
-    int d[3];
-    slot_dir(s, d);
-    const int dep = (s < 6) ? p.H : 2;
-    if (d[2] > 0 && lz < B->s[2] - dep) continue;
-    if (d[2] < 0 && lz >= dep) continue;
-    const int ix = d[0] > 0 ? lx - (B->s[0] - dep) : lx;
-    const int iy = d[1] > 0 ? ly - (B->s[1] - dep) : ly;
-    const int iz = d[2] > 0 ? lz - (B->s[2] - dep) : lz;
-    const int ex = d[0] ? dep : B->s[0];
-    const int ey = d[1] ? dep : B->s[1];
-    const int ez = d[2] ? dep : B->s[2];
-    const long long li = ((long long)iz * ey + iy) * ex + ix;
-    const long long vs = (long long)ex * ey * ez;
-    T* w = slot + B->lay[s] + li;
+__device__ __forceinline__ void ring_write_col(const BlockDev* __restrict__ B, const RingColumn& rc, int H,
+                                               bool act, int lx, int ly, int lz, const T u[5],
+                                               T* __restrict__ slot) {
+  if (!act) return;
+  const int sx = B->s[0], sy = B->s[1], sz = B->s[2];
+  // x and y faces and the xy edge: the layer holds every plane of the block
+  const int zs[5] = {sy * H, sy * H, H * sx, H * sx, 4};
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    if (rc.off[j] < 0) continue;
+    const int vs = zs[j] * sz;
+    T* w = slot + B->lay[rc.slot[j]] + lz * zs[j] + rc.off[j];
 #pragma unroll
     for (int v = 0; v < 5; ++v) w[v * vs] = u[v];
+  }
+  // z faces and the xz / yz edges
+  const int izf = lz < H ? lz : (lz >= sz - H ? lz - (sz - H) : -1);
+  if (izf < 0) return;
+  for (int side = 0; side < 2; ++side) {   // a block lower than 2H has planes in both
+    const bool lo = side == 0;
+    if (lo ? lz >= H : lz < sz - H) continue;
+    const int s = lo ? 4 : 5;
+    if (B->lay[s] >= 0) {
+      const int iz = lo ? lz : lz - (sz - H);
+      const int vs = H * sy * sx;
+      T* w = slot + B->lay[s] + (iz * sy + ly) * sx + lx;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) w[v * vs] = u[v];
+    }
+    if (lo ? lz >= 2 : lz < sz - 2) continue;
+    const int iz2 = lo ? lz : lz - (sz - 2);
+    const int ex = lx < 2 ? 0 : (lx >= sx - 2 ? 1 : -1);
+    if (ex >= 0) {   // (+-x, +-z) edge, [2][s_y][2]
+      const int se = 10 + ex + 2 * (lo ? 0 : 1);
+      if (B->lay[se] >= 0) {
+        const int ix = ex == 0 ? lx : lx - (sx - 2);
+        T* w = slot + B->lay[se] + (iz2 * sy + ly) * 2 + ix;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) w[v * (4 * sy)] = u[v];
+      }
+    }
+    const int ey = ly < 2 ? 0 : (ly >= sy - 2 ? 1 : -1);
+    if (ey >= 0) {   // (+-y, +-z) edge, [2][2][s_x]
+      const int se = 14 + ey + 2 * (lo ? 0 : 1);
+      if (B->lay[se] >= 0) {
+        const int iy = ey == 0 ? ly : ly - (sy - 2);
+        T* w = slot + B->lay[se] + (iz2 * 2 + iy) * sx + lx;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) w[v * (4 * sx)] = u[v];
+      }
+    }
   }
 }
 
@@ -398,11 +443,12 @@ __device__ __forceinline__ void epilogue_pre(const StageParams<T>& p, long long 
       out[v] = r;
     } else if (KIND == kRK4First) {
       const T dr = dt * r;
-      p.acc[i] = Y[v] + cA * dr;
+      p.acc[i] = cA * dr;
       out[v] = Y[v] + cB * dr;
     } else if (KIND == kRK4Mid) {
       const T dr = dt * r;
-      p.acc[i] = accv[v] + cA * dr;
+      const T a = accv[v] + cA * dr;
+      p.acc[i] = p.fold ? u0v[v] + a : a;
       out[v] = u0v[v] + cB * dr;
     } else if (KIND == kRK4Last) {
       out[v] = accv[v] + cA * (dt * r);
@@ -434,12 +480,13 @@ __device__ __forceinline__ void epilogue(const StageParams<T>& p, long long g, c
       p.Yout[i] = r;
     } else if (KIND == kRK4First) {
       const T dr = dt * r;
-      p.acc[i] = Y[v] + cA * dr;
+      p.acc[i] = cA * dr;
       out[v] = Y[v] + cB * dr;
       p.Yout[i] = out[v];
     } else if (KIND == kRK4Mid) {
       const T dr = dt * r;
-      p.acc[i] = p.acc[i] + cA * dr;
+      const T a = p.acc[i] + cA * dr;
+      p.acc[i] = p.fold ? p.U0[i] + a : a;
       out[v] = p.U0[i] + cB * dr;
       p.Yout[i] = out[v];
     } else if (KIND == kRK4Last) {

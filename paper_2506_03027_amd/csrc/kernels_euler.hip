@@ -110,10 +110,10 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
   if (arole) fetch_col(p, B, cola, t.blk, t.x0 + ax, t.y0 + ay, t.z0, na);
 
   T* ring_slot = nullptr;
-  unsigned rmask = 0;
+  RingColumn rcol{};
   if (p.ring_write) {
     ring_slot = p.ring + (long long)((p.slot_now + 1) % p.D) * p.slot_stride;
-    if (act) rmask = ring_mask(p, B, lx, ly);
+    if (act) rcol = ring_column(B, p.H, lx, ly);
   }
 
   // global index of the thread's column at plane z0, and the stride per plane
@@ -189,7 +189,7 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
       T out[5];
       epilogue_pre<T, KIND>(p, g, uq[0], R, accv, u0v, out);
       if (iz + 1 < t.nz) epilogue_load<T, KIND>(p, g + gplane, accv, u0v);
-      if (ring_slot) ring_store(p, B, rmask, lx, ly, lz, out, ring_slot);
+      if (ring_slot) ring_write_col(B, rcol, p.H, true, lx, ly, lz, out, ring_slot);
     }
   }
 }

@@ -116,7 +116,7 @@ __global__ void ring_fill_kernel(const StageParams<T> p, const T* U, int slot) {
     T u[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = U[v * p.field + g];
-    ring_store(p, B, ring_mask(p, B, lx, ly), lx, ly, lz, u, dst);
+    ring_write_col(B, ring_column(B, p.H, lx, ly), p.H, true, lx, ly, lz, u, dst);
   }
 }
 

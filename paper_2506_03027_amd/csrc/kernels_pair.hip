@@ -41,14 +41,15 @@ struct PairLds {
 
 // The RK point update of a stage kind, as in the stage kernels' epilogue.
 template <typename T, int KIND>
-__device__ __forceinline__ void pair_update(T dt, T cA, T cB, T Y, T r, T accv, T u0v, T& out, T& acc) {
+__device__ __forceinline__ void pair_update(T dt, T cA, T cB, int fold, T Y, T r, T accv, T u0v, T& out, T& acc) {
   if (KIND == kRK4First) {
     const T dr = dt * r;
-    acc = Y + cA * dr;
+    acc = cA * dr;
     out = Y + cB * dr;
   } else if (KIND == kRK4Mid) {
     const T dr = dt * r;
-    acc = accv + cA * dr;
+    const T a = accv + cA * dr;
+    acc = fold ? u0v + a : a;
     out = u0v + cB * dr;
   } else {  // kRK4Last
     out = accv + cA * (dt * r);
@@ -126,10 +127,10 @@ __global__ void __launch_bounds__((TX + 4) * (TY + 4))
     if (e2) col = column_source(pA, B, lx, ly);
     if (rrole) rcol = column_source(pA, B, t.x0 + rx, t.y0 + ry);
     T* ring_slot = nullptr;
-    unsigned rmask = 0;
+    RingColumn rlay{};
     if (pB.ring_write) {
       ring_slot = pB.ring + (long long)((pB.slot_now + 1) % pB.D) * pB.slot_stride;
-      if (tile) rmask = ring_mask(pB, B, lx, ly);
+      if (tile) rlay = ring_column(B, pB.H, lx, ly);
     }
     const int z0 = t.z0, nz = t.nz;
     T Uq[5][5], Yq[5][5], aq[3][5];
@@ -251,7 +252,7 @@ __global__ void __launch_bounds__((TX + 4) * (TY + 4))
           for (int v = 0; v < 5; ++v) R[v] -= (w1 * (h3[v] - h1[v]) - w2 * (h4[v] - h0[v])) * ihz;
           T acc[5];
 #pragma unroll
-          for (int v = 0; v < 5; ++v) pair_update<T, KA>(dtA, cAA, cBA, Uq[2][v], R[v], accv[v], u0v[v], ya[v], acc[v]);
+          for (int v = 0; v < 5; ++v) pair_update<T, KA>(dtA, cAA, cBA, pA.fold, Uq[2][v], R[v], accv[v], u0v[v], ya[v], acc[v]);
 #pragma unroll
           for (int v = 0; v < 5; ++v) accv[v] = acc[v];
         } else if (cross && pair_valid(pB, B, lx, ly, m)) {
@@ -298,11 +299,11 @@ __global__ void __launch_bounds__((TX + 4) * (TY + 4))
           T acc;
           // the stage-B RK register input is stage A's, two planes back; the
           // middle stage's U^n is the stage-A input of plane p (pair 0)
-          pair_update<T, KB>(dtB, cAB, cBB, Yq[2][v], R[v], aq[0][v], Uq[0][v], out[v], acc);
+          pair_update<T, KB>(dtB, cAB, cBB, pB.fold, Yq[2][v], R[v], aq[0][v], Uq[0][v], out[v], acc);
           if (KB == kRK4Mid) pB.acc[v * pB.field + g] = acc;
           pB.Yout[v * pB.field + g] = out[v];
         }
-        if (ring_slot) ring_store(pB, B, rmask, lx, ly, p, out, ring_slot);
+        if (ring_slot) ring_write_col(B, rlay, pB.H, true, lx, ly, p, out, ring_slot);
       }
     }
   }

@@ -126,8 +126,9 @@ struct BatchTile {
 // Stage epilogue kinds.
 enum StageKind {
   kRhsOnly = 0,   // Yout = R
-  kRK4First = 1,  // acc = Y + cA dt R ; Yout = Y + cB dt R        (Y == U^n)
+  kRK4First = 1,  // acc = cA dt R     ; Yout = Y + cB dt R        (Y == U^n)
   kRK4Mid = 2,    // acc += cA dt R    ; Yout = U0 + cB dt R
+                  //   (fold: acc = U0 + (acc + cA dt R))
   kRK4Last = 3,   // Yout = acc + cA dt R                          (Yout == U)
   kLSFirst = 4,   // Q = dt R          ; Yout = Y + cB Q           (A_1 = 0)
   kLSMid = 5      // Q = cA Q + dt R   ; Yout = Y + cB Q
@@ -175,6 +176,11 @@ struct StageParams {
   double dt;
   double cA;             // epilogue coefficients (see stage kinds)
   double cB;
+  // Classical RK4 accumulates dt sum_j b_j R_j in acc starting from zero
+  // and adds U^n once, in the last middle stage (fold != 0), which reads U^n
+  // anyway: two roundings of state-sized sums per step instead of four, at
+  // no extra traffic.
+  int fold;
   int ring_write;        // write the boundary layers of the result
   // Halo assembly inside the first stage of a graph-captured step (fuse_halo
   // != 0): before its plane loop, each tile computes, for the halo points it

@@ -111,42 +111,63 @@ def _build(torch, name, nstep):
     return w, o, g, hist
 
 
-@pytest.mark.parametrize("name, nblocks", [("vortex3d_128", 8), ("tgv_256", 4)])
-def test_fullsize_rhs_sampled_against_pointwise_oracle(name, nblocks):
+@pytest.mark.parametrize("name, nblocks, inject", [("vortex3d_128", 8, False), ("tgv_256", 4, False),
+                                                   ("tgv_512", 6, True)])
+def test_fullsize_rhs_every_stage_sampled_against_pointwise_oracle(name, nblocks, inject):
+    """Every RK stage's right-hand side (each stage has its own AT halo
+    weights, Eqs. 8-15) on sampled points.  For the 512^3 workload (SAA,
+    L = 5) delays at the bound k = 4 are injected on every face and edge slot
+    of the sampled blocks, so the largest weights ||W_e(4)||_1 (up to about
+    1.5e3) enter the comparison."""
     torch = need_gpu()
     announce("fullsize rhs", name)
     nstep = 21
     w, o, g, hist = _build(torch, name, nstep)
     tiles = g.autotune(reps=2)           # the shape the benchmark would run
     print("tiles", tiles, flush=True)
-    R = g.rhs()
+    rng = np.random.default_rng(5)
+    pts = _sample_points(o, rng, nblocks)
+    if inject:
+        kin = o.delays(nstep).copy()
+        for b in {b for b, _ in pts}:
+            kin[b, :] = w["L"] - 1
+        g.set_delays(nstep, kin[None].astype(np.int8))
+        o.set_delays(nstep, kin)
     k = o.delays(nstep)
     assert k is not None and k.max() == w["L"] - 1
+    if inject:
+        assert all((k[b, :18] == w["L"] - 1).all() for b, _ in pts)
     U = hist.device_level(nstep)
     scale = _flux_scale(torch, U)
+    del U
     h = o.cfg.h
     tol = 64 * EPS32 * scale / min(h)
     if w["physics"] == "ns":
         tol *= 1.0 + 1.0 / (o.cfg.gas.re * min(h))
     order = 4
     levels = {m: hist.level(m) for m in range(nstep - 12, nstep + 1)}
-    worst = 0.0
-    rng = np.random.default_rng(5)
-    for b, p in _sample_points(o, rng, nblocks):
-        org, size = o.blocks.origins[b], o.blocks.sizes[b]
-        get = pointwise.block_accessor(levels[nstep], levels, nstep, org, size, p, k=k[b], W=o.W, e=0,
-                                       C=o.cfg.C, mode=w["mode"])
-        ref = pointwise.rhs_point(get, h, 3, w["physics"], o.cfg.gas, order)
-        gx, gy, gz = ((org[d] + p[d]) % w["n"][d] for d in range(3))
-        got = R[:, gz, gy, gx].double().cpu().numpy()
-        err = float(np.abs(got - np.array(ref)).max())
-        worst = max(worst, err)
-        assert err < tol, (name, b, p, err, tol)
-    print("fullsize rhs", name, "worst", worst, "tol", tol, flush=True)
+    for e in range(o.s):
+        R = g.rhs(stage=e)
+        worst = 0.0
+        for b, p in pts:
+            org, size = o.blocks.origins[b], o.blocks.sizes[b]
+            get = pointwise.block_accessor(levels[nstep], levels, nstep, org, size, p, k=k[b], W=o.W, e=e,
+                                           C=o.cfg.C, mode=w["mode"])
+            ref = pointwise.rhs_point(get, h, 3, w["physics"], o.cfg.gas, order)
+            gx, gy, gz = ((org[d] + p[d]) % w["n"][d] for d in range(3))
+            got = R[:, gz, gy, gx].double().cpu().numpy()
+            err = float(np.abs(got - np.array(ref)).max())
+            worst = max(worst, err)
+            assert err < tol, (name, e, b, p, err, tol)
+        del R
+        print("fullsize rhs", name, "stage", e, "worst", worst, "tol", tol, flush=True)
+    if inject:
+        g.set_delays(0, np.zeros((0, g.nblocks, 18), dtype=np.int8))
     g.close()
 
 
-@pytest.mark.parametrize("name, other", [("vortex3d_128", (16, 16, 8)), ("tgv_256", (32, 8, 16))])
+@pytest.mark.parametrize("name, other", [("vortex3d_128", (16, 16, 8)), ("tgv_256", (32, 8, 16)),
+                                         ("tgv_512", (16, 16, 16))])
 def test_fullsize_graph_steps_with_tuned_tiles_match_eager(name, other):
     torch = need_gpu()
     announce("fullsize steps", name)

@@ -6,6 +6,7 @@ import math
 import numpy as np
 import pytest
 
+from bounds import bf16_forward_bound
 from gpu_helpers import announce, need_gpu, pair, rel_max, set_both, to_np
 from oracle import at as oat, delays as odl, mlp as omlp
 from paper_2506_03027_amd import atns, inputs
@@ -36,6 +37,25 @@ def test_mlp_forward_matches_reference():
     scale = np.abs(ref).max()
     assert err.max() < 2e-3 * scale, err.max() / scale
     assert np.median(err) < 1e-5 * scale
+
+
+def test_mlp_forward_within_bf16_bound_of_plain_fp64():
+    # The GPU network (BF16 operands on the matrix cores, FP32 accumulation)
+    # against the plain FP64 forward pass, element by element, within the
+    # bound derived from BF16 operand rounding (tests/bounds.py).
+    torch = need_gpu()
+    announce("mlp forward vs plain fp64")
+    _, g = small_ctx(torch)
+    th = omlp.init(8)
+    th[omlp.NIN * omlp.NH: omlp.NIN * omlp.NH + 64] = 0.1
+    th32 = th.astype(np.float32)
+    g.mlp_set_params(th32)
+    X = np.random.default_rng(4).standard_normal((2000, 64)).astype(np.float32)
+    out = to_np(g.mlp_forward(torch.from_numpy(X)))
+    plain, _ = omlp.forward(th32.astype(np.float64), X.astype(np.float64))
+    bound = bf16_forward_bound(th32.astype(np.float64), X.astype(np.float64))
+    viol = np.abs(out - plain) - bound
+    assert viol.max() <= 0.0, float(viol.max())
 
 
 def test_mlp_gradient_matches_reference():

@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+from bounds import bf16_forward_bound
 from oracle import mlp
 
 
@@ -53,3 +54,21 @@ def test_features_of_constant_history_are_zero_but_delay():
     lv = [np.ones((5, 3)) * 2.5 for _ in range(4)]
     f = mlp.face_features(lv, 2, 4, 0, np.ones(5))
     assert np.all(f[:60] == 0) and f[60] == pytest.approx(2 / 3) and np.all(f[61:] == 0)
+
+
+def test_bf16_emulation_within_derived_bound_of_plain_forward():
+    # The learned-halo oracle of the corrected solver evaluates the network on
+    # BF16-rounded operands (the GPU's arithmetic); pin that path to the plain
+    # FP64 forward pass by the rounding bound of bounds.bf16_forward_bound.
+    th = mlp.init(4)
+    th[64 * 64:64 * 64 + 64] = 0.05
+    X = np.random.default_rng(3).standard_normal((500, 64))
+    plain, _ = mlp.forward(th, X)
+    emul, _ = mlp.forward(th, X, round_bf16=True)
+    bound = bf16_forward_bound(th, X)
+    err = np.abs(emul - plain)
+    assert np.all(err <= bound)
+    # the worst case is far from typical: errors sit well inside the bound,
+    # and the bound stays below the size of the outputs it bounds
+    assert np.median(err / bound) < 0.05
+    assert bound.max() < np.abs(plain).max()
