@@ -261,6 +261,23 @@ atns_status atns_step_async(atns_ctx* ctx, int32_t nsteps, int64_t spin_limit, i
  * kernel's 32-bit offsets; 512^3 fits). */
 atns_status atns_reduce(atns_ctx* ctx, double* host_out);
 
+/* atns_reduce for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops): the same FP64 diagnostics of a
+ * field the caller owns, with no context, no allocation and no host
+ * synchronization.  dev_U: device field in the field layout, float
+ * (ATNS_F32) or double (ATNS_F64), ndim 2 or 3, n[3] points (nz == 1 in 2-D,
+ * at least 5 per active axis), len[3] periodic box lengths.  dev_out: device
+ * array of 7 doubles, written in the order of atns_reduce (no finiteness
+ * check).  Enqueued on `stream` (hipStream_t or NULL).  The kernels' 1024
+ * workgroup partial sums (57 KiB of doubles) live in a fixed device array that
+ * every GPU the library runs on holds until the process ends; calls that
+ * overlap on one GPU share it and race, so order them on one stream.  Results
+ * equal atns_reduce's on the same field bit for bit.  Errors: EINVAL for null
+ * pointers, bad precision or ndim, or grids with 5 nx ny nz >= 2^31 (the
+ * kernels' 32-bit offsets); EHIP for a failed launch. */
+atns_status atns_reduce_noalloc(const void* dev_U, int32_t precision, int32_t ndim, const int32_t* n,
+                                const double* len, double* dev_out, void* stream);
+
 /* Number of blocks, and the ring depth D (levels kept), of a context. */
 atns_status atns_get_layout(const atns_ctx* ctx, int32_t* nblocks, int32_t* ring_depth);
 

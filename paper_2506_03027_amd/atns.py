@@ -37,7 +37,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "EN
 
 EXPORTS = ["atns_version", "atns_create", "atns_destroy", "atns_last_error", "atns_set_state",
            "atns_get_state", "atns_get_step", "atns_set_dt", "atns_set_delays", "atns_get_delays",
-           "atns_rhs", "atns_rk_step", "atns_step_async", "atns_set_fusion", "atns_set_halo_fusion", "atns_reduce", "atns_get_layout", "atns_set_graphs", "atns_profile_enable",
+           "atns_rhs", "atns_rk_step", "atns_step_async", "atns_set_fusion", "atns_set_halo_fusion", "atns_reduce", "atns_reduce_noalloc", "atns_get_layout", "atns_set_graphs", "atns_profile_enable",
            "atns_profile_read", "atns_set_tiles", "atns_get_tiles", "atns_autotune",
            "atns_mlp_set_params", "atns_mlp_get_params", "atns_mlp_set_scales", "atns_mlp_forward",
            "atns_mlp_grad", "atns_mlp_sample", "atns_mlp_train", "atns_mlp_enable", "atns_mlp_stats",
@@ -89,6 +89,7 @@ def lib():
             "atns_set_fusion": ([vp, i32], i32),
             "atns_set_halo_fusion": ([vp, i32], i32),
             "atns_reduce": ([vp, vp], i32),
+            "atns_reduce_noalloc": ([vp, i32, i32, vp, vp, vp, vp], i32),
             "atns_get_layout": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
             "atns_set_graphs": ([vp, i32], i32),
             "atns_profile_enable": ([vp, i32], i32),
@@ -137,6 +138,18 @@ def hbm_probe(src, dst, nbytes, stream=None):
     """Enqueue the library's streaming copy of nbytes from tensor src to dst."""
     _check(lib().atns_hbm_probe(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                 int(nbytes), stream))
+
+
+def reduce_noalloc(U, length, ndim, out, stream=None):
+    """atns_reduce_noalloc: the FP64 diagnostics of device field U (torch,
+    shape (5, nz, ny, nx), float32 or float64) into device tensor out (7
+    float64), enqueued on `stream`; nothing is allocated by the library."""
+    nz, ny, nx = U.shape[1:]
+    n = (ctypes.c_int32 * 3)(nx, ny, nz)
+    ln = (ctypes.c_double * 3)(*[float(x) for x in length])
+    prec = F64 if str(U.dtype) == "torch.float64" else F32
+    _check(lib().atns_reduce_noalloc(ctypes.c_void_p(U.data_ptr()), prec, int(ndim), n, ln,
+                                     ctypes.c_void_p(out.data_ptr()), stream))
 
 
 def host_weights(rk, mode, L):

@@ -94,7 +94,7 @@ struct atns_ctx {
   hipEvent_t order_ev = nullptr;
   double* d_partials = nullptr;
   double* d_diag = nullptr;
-  int nparts = 1024;
+  int nparts = kDiagMaxParts;
   double dt = 0.0;
   int64_t step = 0;
   bool state_set = false;
@@ -1290,6 +1290,33 @@ atns_status atns_reduce(atns_ctx* c, double* host_out) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   for (int i = 0; i < 7; ++i)
     if (!std::isfinite(host_out[i])) return fail(c, ATNS_ENONFINITE, "non-finite diagnostic");
+  return ATNS_OK;
+}
+
+atns_status atns_reduce_noalloc(const void* dev_U, int32_t precision, int32_t ndim, const int32_t* n,
+                                const double* len, double* dev_out, void* stream) {
+  if (!dev_U || !n || !len || !dev_out) return fail(nullptr, ATNS_EINVAL, "null argument");
+  if (precision != ATNS_F32 && precision != ATNS_F64) return fail(nullptr, ATNS_EINVAL, "bad precision");
+  if (ndim != 2 && ndim != 3) return fail(nullptr, ATNS_EINVAL, "ndim must be 2 or 3");
+  if (ndim == 2 && n[2] != 1) return fail(nullptr, ATNS_EINVAL, "2D needs nz == 1");
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] < 1 || !(len[d] > 0)) return fail(nullptr, ATNS_EINVAL, "bad grid or box length");
+    if (d < ndim && n[d] < 5) return fail(nullptr, ATNS_EINVAL, "the CD4 vorticity needs 5 points per axis");
+  }
+  if (5.0 * n[0] * n[1] * n[2] >= 2147483648.0)
+    return fail(nullptr, ATNS_EINVAL, "grid too large for the reduction (5 nx ny nz >= 2^31)");
+  double inv12h[3], h[3];
+  for (int d = 0; d < 3; ++d) {
+    h[d] = len[d] / n[d];
+    inv12h[d] = 1.0 / (12.0 * h[d]);
+  }
+  const double dV = h[0] * h[1] * (ndim == 3 ? h[2] : len[2]);
+  const int nn[3] = {n[0], n[1], n[2]};
+  const hipError_t e =
+      precision == ATNS_F32
+          ? launch_diag_noalloc<float>((const float*)dev_U, nn, ndim, inv12h, dV, dev_out, (hipStream_t)stream)
+          : launch_diag_noalloc<double>((const double*)dev_U, nn, ndim, inv12h, dV, dev_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(nullptr, ATNS_EHIP, std::string("atns_reduce_noalloc: ") + hipGetErrorString(e));
   return ATNS_OK;
 }
 

@@ -1,6 +1,9 @@
 // Small kernels: the per-step delay draw, the ring fill of a given state, and
 // the FP64 diagnostics (conserved totals, kinetic energy, enstrophy).
+#include <mutex>
+
 #include "kernels_common.hpp"
+#include "launch.hpp"
 
 namespace atns {
 
@@ -365,5 +368,49 @@ template hipError_t launch_diag<float>(const float*, const int*, int, const doub
                                        double*, hipStream_t);
 template hipError_t launch_diag<double>(const double*, const int*, int, const double*, double, double*, int,
                                         double*, hipStream_t);
+
+// Diagnostics without allocation (atns_reduce_noalloc): the workgroup
+// partials go to `scratch`, a fixed device array that each GPU holds for the
+// life of the process.  Host code never uses the array's name as an address:
+// the first call on a device, with that device current, resolves the array's
+// device address there (hipGetSymbolAddress) and keeps it per device.  Every
+// call fully rewrites the partials it reads, so nothing is cleared; calls that
+// overlap on one GPU share the array and race.
+static __device__ __align__(256) double scratch[kDiagMaxParts * 7];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t diag_scratch_address(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_diag_noalloc(const T* U, const int n[3], int ndim, const double inv12h[3], double dV,
+                               double* out, hipStream_t s) {
+  double* part = nullptr;
+  const hipError_t e = diag_scratch_address(&part);
+  if (e != hipSuccess) return e;
+  return launch_diag<T>(U, n, ndim, inv12h, dV, part, kDiagMaxParts, out, s);
+}
+template hipError_t launch_diag_noalloc<float>(const float*, const int*, int, const double*, double, double*,
+                                               hipStream_t);
+template hipError_t launch_diag_noalloc<double>(const double*, const int*, int, const double*, double, double*,
+                                                hipStream_t);
 
 }  // namespace atns

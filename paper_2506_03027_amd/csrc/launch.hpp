@@ -48,6 +48,12 @@ hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nbl
                          unsigned long long seed, int algo, hipStream_t s, const long long* nstep = nullptr);
 template <typename T>
 hipError_t launch_ring_fill(const StageParams<T>& p, const T* U, int slot, int nblocks, hipStream_t s);
+// Workgroups (and FP64 partial sets of 7) of the diagnostics reduction; the
+// allocation-free form keeps its partials in a fixed device array of this size.
+constexpr int kDiagMaxParts = 1024;
+template <typename T>
+hipError_t launch_diag_noalloc(const T* U, const int n[3], int ndim, const double inv12h[3], double dV,
+                               double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_diag(const T* U, const int n[3], int ndim, const double inv12h[3], double dV,
                        double* partials, int nparts, double* out, hipStream_t s);
