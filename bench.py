@@ -243,6 +243,118 @@ def stored_traffic(workload):
     return rec.get("traffic_bytes_per_launch")
 
 
+def traffic_summary(workload, fetch_db, write_db, commands):
+    """The counter record profiles/traffic_<workload>.json from two rocprofv3
+    runs of this script (--pmc FETCH_SIZE, then --pmc WRITE_SIZE, KiB per
+    dispatch): the stage kernel's average per launch and the halo kernel's
+    per step, each counter scaled by what it reads for the copy probe's 1 GiB
+    copy (1 GiB fetched and 1 GiB written)."""
+    import sqlite3
+
+    def per_kernel(db, counter):
+        # keyed by (kernel name, workgroups): the tile autotuner launches the
+        # stage kernel at other tile shapes and sizes before the timed steps
+        c = sqlite3.connect(db)
+        rows = c.execute("select kernel_name, grid_size / workgroup_size, dispatch_id, sum(value) "
+                         "from counters_collection where counter_name = ? "
+                         "group by kernel_name, dispatch_id", (counter,)).fetchall()
+        out = {}
+        for name, wg, _, v in rows:
+            out.setdefault((name.split("(")[0], wg), []).append(v)
+        return out
+
+    f, wr = per_kernel(fetch_db, "FETCH_SIZE"), per_kernel(write_db, "WRITE_SIZE")
+    pick = lambda d, key: [v for k, vs in d.items() if key in k[0] for v in vs]
+    probe_kib = PROBE_BYTES / 1024.0
+    fprobe, wprobe = np.mean(pick(f, "copy_probe_kernel")), np.mean(pick(wr, "copy_probe_kernel"))
+    fs, ws = probe_kib / fprobe, probe_kib / wprobe
+    w = inputs.WORKLOADS[workload]
+    kname = "ns_stage_kernel" if w["physics"] == "ns" else "euler_stage_kernel"
+    # the benchmark's tile shape and launch size: the group with most dispatches
+    groups = {}
+    for (k, wg), vs in f.items():
+        if kname in k:
+            shape = ", ".join(k.split("<", 1)[1].split(">", 1)[0].split(", ")[:3])
+            groups.setdefault((shape, wg), []).append(((k, wg), vs))
+    best = max(groups, key=lambda g: sum(len(vs) for _, vs in groups[g]))
+    per_kind = {}
+    fall, wall = [], []
+    for key, vs in groups[best]:
+        kind = key[0].split("<", 1)[1].split(">", 1)[0]
+        per_kind[kind] = {"fetch_kib_raw": float(np.mean(vs)), "dispatches": len(vs),
+                          "write_kib_raw": float(np.mean(wr.get(key, [0.0])))}
+        fall += vs
+        wall += wr.get(key, [])
+    fk, wk = np.mean(fall), np.mean(wall)
+    npts = w["n"][0] * w["n"][1] * w["n"][2]
+    stages = n_stages(w)
+    halo = [(a, b) for a, b in zip(pick(f, "halo_kernel"), pick(wr, "halo_kernel"))]
+    rec = {"workload": workload, "kernel": "%s<%s> at %d workgroups" % (kname, best[0], best[1]),
+           "kernel_hash": kernel_source_hash(), "commands": commands,
+           "run_from": "/tmp, with TMPDIR=/tmp", "copy_probe_kib": probe_kib,
+           "copy_probe_fetch_kib_raw": float(fprobe), "copy_probe_write_kib_raw": float(wprobe),
+           "fetch_scale": fs, "write_scale": ws,
+           "fetch_kib_raw_per_dispatch": float(fk), "write_kib_raw_per_dispatch": float(wk), "per_kind": per_kind,
+           "traffic_bytes_per_launch": float((fk * fs + wk * ws) * 1024.0),
+           "algorithmic_bytes_per_launch": stage_kernel_bytes_per_point(w, stages, 4) * npts}
+    if halo:
+        rec["halo_kernel_per_step_bytes"] = float(np.mean([(a * fs + b * ws) * 1024.0 for a, b in halo]))
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    with open(path, "w") as fo:
+        json.dump(rec, fo, indent=1)
+    print(json.dumps({"written": path, "traffic_bytes_per_launch": rec["traffic_bytes_per_launch"],
+                      "algorithmic_bytes_per_launch": rec["algorithmic_bytes_per_launch"]}))
+
+
+def trace_summary(db, top=14):
+    """Markdown summary of a rocprofv3 --kernel-trace database: calls, total
+    and average duration (microseconds) per kernel and launch size
+    (workgroups). A run on a fresh node tunes the tile shape first and
+    launches the stage kernel at several shapes and sizes; those launches
+    are totalled on one line, and the table keeps the stage kernel at the
+    shape and size most used (the benchmark's) beside every other kernel."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, grid_x / workgroup_x, count(*), sum(duration), avg(duration) from kernels "
+                     "group by name, grid_x / workgroup_x").fetchall()
+
+    def shape_of(name):
+        args = name.split("<", 1)[1].split(">", 1)[0].split(", ")
+        return ", ".join(args[:3])
+
+    chosen, tuning = {}, []
+    for key in ("ns_stage_kernel", "euler_stage_kernel"):
+        sel = [r for r in rows if key in r[0]]
+        if not sel:
+            continue
+        groups = {}
+        for r in sel:
+            groups.setdefault((shape_of(r[0]), r[1]), []).append(r)
+        best = max(groups, key=lambda g: sum(r[2] for r in groups[g]))
+        chosen[key] = (best, groups[best])
+        tuning += [r for g, rs in groups.items() if g != best for r in rs]
+    kept = [r for r in rows if r not in tuning]
+    tot = sum(r[3] for r in kept)
+    kept.sort(key=lambda r: -r[3])
+    lines = ["| kernel | workgroups | calls | total us | average us | % |", "|---|---|---|---|---|---|"]
+    for name, wg, n, t, a in kept[:top]:
+        lines.append("| `%s` | %d | %d | %.1f | %.3f | %.1f |" % (name.split("(")[0], wg, n, t / 1e3, a / 1e3,
+                                                                 100.0 * t / tot))
+    if tuning:
+        lines.append("")
+        lines.append("Tile tuning (stage kernel at other shapes and sizes, not in the table): %d launches, %.1f us." % (
+            sum(r[2] for r in tuning), sum(r[3] for r in tuning) / 1e3))
+    for key, ((shape, wg), grp) in chosen.items():
+        n = sum(r[2] for r in grp)
+        t = sum(r[3] for r in grp)
+        lines.append("")
+        lines.append("`%s<%s>` at %d workgroups, all stage kinds: %d calls, average %.3f us per launch." % (
+            key, shape, wg, n, t / n / 1e3))
+        for r in sorted(grp, key=lambda r: r[0]):
+            lines.append("- `%s`: %d calls, average %.3f us" % (r[0].split("(")[0], r[2], r[4] / 1e3))
+    print("\n".join(lines))
+
+
 def host_info():
     """CPU model and core counts of the host the oracle is timed on."""
     model = None
@@ -758,6 +870,12 @@ def main():
     ap.add_argument("--series-out", default=None, help="CSV file for --series")
     ap.add_argument("--series-ref", action="store_true",
                     help="with --series: also run the FP64 synchronous solver and compare the series")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"), default=None,
+                    help="write profiles/traffic_<workload>.json from two rocprofv3 --pmc runs (FETCH_SIZE, "
+                         "WRITE_SIZE) of this script; no GPU work")
+    ap.add_argument("--traffic-commands", nargs="*", default=[], help="the two rocprofv3 commands, for the record")
+    ap.add_argument("--trace-summary", default=None, metavar="DB",
+                    help="print a markdown table of a rocprofv3 --kernel-trace database; no GPU work")
     ap.add_argument("--free-running", action="store_true",
                     help="free-running asynchronous steps (one persistent workgroup per block) next to the "
                          "scheduled graph-captured steps on the same workload")
@@ -766,6 +884,12 @@ def main():
         print("bench.py measures one GPU: the library has no multi-GPU path (--gpus 1 only)",
               file=sys.stderr)
         sys.exit(2)
+    if a.trace_summary:
+        trace_summary(a.trace_summary)
+        return
+    if a.traffic_summary:
+        traffic_summary(a.workload, a.traffic_summary[0], a.traffic_summary[1], a.traffic_commands)
+        return
     single = a.workload != "batch48" and not a.free_running and not a.series
     # the oracle's timing runs before anything touches the GPU (it forks workers)
     cpu = cpu_oracle_timing(inputs.WORKLOADS[a.workload]) if (single and not a.no_cpu) else None
