@@ -21,6 +21,9 @@ arXiv 2506.03027 (Arumugam, Goswami, Vadlamani, Aditya):
                  in SA / AS / AT modes and the RK step (Sec. 3.2, Alg. 1-3).
 * ``diagnostics`` -- conserved totals, kinetic energy and enstrophy (Sec. 5.2).
 * ``mlp``     -- FP64 reference of the learned-halo MLP (forward, backward).
+* ``filter``  -- the tenth-order Pade low-pass filter (Sec. 2, Sec. 5.2) and
+                 its block-local application with synchronous, AT or AS
+                 halos (a reading; the paper does not define it across PEs).
 
 Everything is float64 numpy or exact ``fractions.Fraction`` arithmetic.
 
@@ -40,7 +43,14 @@ What pins it (tests/test_oracle_*.py, all on the CPU):
   LSERK2-CD2-AT2), AT with zero delay converging to SA, conservation under SA,
   a brute-force pointwise halo rule, the delay patterns of Alg. 2 and
   Alg. 3 and SplitMix64's published outputs;
-* mlp -- central-difference gradients, BF16 rounding, the fallback rule.
+* mlp -- central-difference gradients, BF16 rounding, the fallback rule;
+* filter -- the coefficients at alpha = 0 (binomial closed form of
+  1 - sin^10(w/2)) and alpha = 1/2 (identity), affine in between; the
+  transfer function on Fourier modes of the periodic filter; exactness of
+  the block filter on degree-9 polynomials and not on degree 10; agreement
+  with the periodic filter far from block faces; one axis per pass; the AT
+  halo exact for time polynomials of degree C-1; alpha = 1/2 steps equal to
+  unfiltered steps.
 
 Parity unpinned: the TGV kinetic-energy and enstrophy time series beyond
 t = 0 (the paper shows them only as plots, without data), and the

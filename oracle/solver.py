@@ -40,6 +40,7 @@ import numpy as np
 
 from . import at as atmod
 from . import delays as dl
+from . import filter as filt
 from . import flow
 from . import rk as rkmod
 
@@ -57,7 +58,8 @@ def even_split(n, nb):
 class Config:
     def __init__(self, n, length, ndim=3, nblk=(1, 1, 1), physics="euler",
                  gamma=1.4, mach=0.1, re=1600.0, pr=0.71, rk="rk4", mode="sa",
-                 algo="caa", L=1, seed=0, C=atmod.AT4_C, dt=None, split=None, order=4):
+                 algo="caa", L=1, seed=0, C=atmod.AT4_C, dt=None, split=None, order=4,
+                 filter_alpha=None):
         self.n = tuple(n)
         self.length = tuple(length)
         self.ndim = ndim
@@ -75,6 +77,8 @@ class Config:
         self.split = split or [even_split(self.n[d], self.nblk[d]) for d in range(3)]
         self.h = tuple(self.length[d] / self.n[d] for d in range(3))
         self.H = flow.halo_depth(physics)
+        # tenth-order Pade filter after every step (None: off); see filter.py
+        self.filter_alpha = filter_alpha
 
 
 class Blocks:
@@ -154,6 +158,14 @@ class Oracle:
         self.mlp_counts = [0, 0]
         if cfg.mode in (atmod.AT, atmod.AS):
             self.W = atmod.halo_table(cfg.rk, cfg.mode, cfg.C, cfg.L - 1)
+        if cfg.filter_alpha is not None:
+            for b in range(len(self.blocks)):
+                for d in range(cfg.ndim):
+                    if self.blocks.sizes[b][d] < filt.HALO:
+                        raise ValueError("block smaller than the filter's halo depth")
+            # weights of the delayed levels for the filter's halo at level n+1
+            self.Wf = np.array([[float(x) for x in filt.next_level_weights(k, cfg.C)]
+                                for k in range(cfg.L)])
         # float coefficients for the literal Eq. (8) recursion
         self._lit = {}
 
@@ -297,6 +309,8 @@ class Oracle:
                 Q = float(A[m]) * Q + dt * self.rhs(Y, m, k, bufs)
                 Y = Y + float(B[m]) * Q
             Unew = Y
+        if cfg.filter_alpha is not None:
+            Unew = self.filter_state(Unew, k)
         self.n += 1
         self.U = Unew
         self.history[self.n] = Unew.copy()
@@ -305,3 +319,44 @@ class Oracle:
         for m in list(self.history):
             if m < self.n - keep:
                 del self.history[m]
+
+    # ---------------------------------------------------------------- filter
+    def filter_state(self, U, k=None):
+        """The block-local tenth-order filter of ``filter.py`` applied to the
+        new level U (= U^{n+1} of the step in progress, self.n = n): x, y and
+        (3-D) z passes; halos synchronous when k is None, else from the
+        delayed levels (AT: extrapolated to n+1, AS: the newest level)."""
+        V = np.array(U, dtype=np.float64)
+        for d in range(self.cfg.ndim):
+            V = self._filter_pass(V, d, k)
+        return V
+
+    def _filter_pass(self, V, d, k):
+        cfg = self.cfg
+        Hf = filt.HALO
+        ax = 3 - d                     # array axis of grid axis d ([var][z][y][x])
+        out = np.empty_like(V)
+        for b in range(len(self.blocks)):
+            s = self.blocks.sizes[b]
+            own = [np.arange(s[0]), np.arange(s[1]), np.arange(s[2])]
+            ext = list(own)
+            ext[d] = np.arange(-Hf, s[d] + Hf)
+            E = V[(slice(None),) + self.blocks.global_index(b, ext)].copy()
+            if k is not None:
+                for side, v in ((0, 2 * d), (1, 2 * d + 1)):
+                    hr = list(own)
+                    hr[d] = np.arange(-Hf, 0) if side == 0 else np.arange(s[d], s[d] + Hf)
+                    gidx = (slice(None),) + self.blocks.global_index(b, hr)
+                    kk = int(k[b, v])
+                    if cfg.mode == atmod.AT:
+                        vals = np.zeros(V[gidx].shape)
+                        for l in range(cfg.C):
+                            vals = vals + self.Wf[kk, l] * self.history[self.n - kk - l][gidx]
+                    else:
+                        vals = self.history[self.n - kk][gidx]
+                    pos = [slice(None)] * 4
+                    pos[ax] = slice(0, Hf) if side == 0 else slice(s[d] + Hf, s[d] + 2 * Hf)
+                    E[tuple(pos)] = vals
+            F = filt.filter_block_lines(np.moveaxis(E, ax, -1), cfg.filter_alpha)
+            out[(slice(None),) + self.blocks.global_index(b, own)] = np.moveaxis(F, -1, ax)
+        return out
