@@ -43,8 +43,9 @@
  *  10 (-x,-z) 11 (+x,-z) 12 (-x,+z) 13 (+x,+z)
  *  14 (-y,-z) 15 (+y,-z) 16 (-y,+z) 17 (+y,+z)
  * Euler uses the six faces (halo depth 2).  Navier-Stokes uses faces of
- * depth 4 and the twelve 2x2 edge regions (viscous terms as repeated first
- * derivatives).  Delays are int8 arrays [nblocks][ATNS_NSLOTS].
+ * depth 4 (5 with the filter on) and the twelve 2x2 edge regions (viscous
+ * terms as repeated first derivatives).  Delays are int8 arrays
+ * [nblocks][ATNS_NSLOTS].
  */
 #ifndef ATNS_H
 #define ATNS_H
@@ -101,6 +102,14 @@ typedef struct {
   int32_t L;             /* delay bound: delays are 0..L-1 (Alg. 2, 3)        */
   uint64_t seed;         /* SAA delay stream seed                             */
   int32_t precision;     /* ATNS_F32 | ATNS_F64                               */
+  int32_t filter;        /* 0: off.  1: tenth-order Pade low-pass filter of
+                            the conserved variables after every step (Sec. 2;
+                            Sec. 5.2 uses it with alpha_f = 0.499), applied
+                            block by block, x then y then z, with the halo
+                            depth raised to 5 (see atns_filter_state).
+                            Navier-Stokes contexts only; not with batches,
+                            atns_step_async or the learned halo.           */
+  double filter_alpha;   /* alpha_f, -0.5 < alpha_f <= 0.5 (0.5: identity)  */
 } atns_config;
 
 /* Library version string (static storage). */
@@ -109,7 +118,9 @@ const char* atns_version(void);
 /* Create a context on the current HIP device.  Validates the configuration
  * (EINVAL: block smaller than the halo depth in an active direction, split
  * not summing to n, L < 1 or L > 16, unknown enums, ndim == 2 with nz != 1,
- * a Navier-Stokes grid with 5 nx ny nz >= 2^31 points)
+ * a Navier-Stokes grid with 5 nx ny nz >= 2^31 points; with the filter on:
+ * Euler physics, alpha_f outside (-0.5, 0.5], or a block longer than 256
+ * points along an active axis)
  * before any device call.  stream: a hipStream_t, or NULL.  On success *out
  * owns all device buffers: state and RK registers, the delayed-level ring
  * (C + 2L - 1 levels of each block's boundary layers in modes AT and AS,
@@ -200,8 +211,33 @@ atns_status atns_rhs(atns_ctx* ctx, int32_t stage, void* dev_R);
 /* Advance nsteps steps (asynchronous on the context stream).  Each step: the
  * delay draw, s fused stencil + RK-stage kernels (the halo of stage e from
  * the ring with the FP64 weights W[e][k][:]), and the ring write of U^{n+1}
- * in the last stage. */
+ * in the last stage.  With the filter on, the last stage leaves U^{n+1}
+ * unfiltered, the three filter passes of atns_filter_state follow (halos of
+ * the step's kind: synchronous steps read the neighbours' current values of
+ * each pass input, AT steps the neighbours' level n+1 extrapolated from the
+ * C delayed levels with the Lagrange weights of Eqs. 14-15 at delay k+1, AS
+ * steps the newest delayed level), and the filtered field's boundary layers
+ * go into the ring. */
 atns_status atns_rk_step(atns_ctx* ctx, int32_t nsteps);
+
+/* Apply the configured filter (Sec. 2; a reading, since the paper does not
+ * define it across PEs) to the current state in place, with synchronous
+ * halos, and rewrite the ring slot of the current step.  Along each axis in
+ * turn, every block solves
+ *   alpha f^[i-1] + f^[i] + alpha f^[i+1] = sum_{m=0..5} (a_m/2)(f[i+m] + f[i-m])
+ * on its own n points of each grid line, i = 0..n-1, the a_m fixed by
+ * T(pi) = 0 and tenth-order accuracy; the filtered values at i = -1 and
+ * i = n are replaced by the halo values there, so each block solves alone.
+ * The right-hand side reads five halo points beyond each face.  Arithmetic in
+ * FP64, result rounded to the state precision.  EINVAL when the context has
+ * no filter; ESTATE before a state is set.  Asynchronous on the context
+ * stream. */
+atns_status atns_filter_state(atns_ctx* ctx);
+
+/* The six right-hand-side coefficients a_0..a_5 of the tenth-order filter
+ * for alpha (host computation, no device).  EINVAL for alpha outside
+ * (-0.5, 0.5] or a null pointer. */
+atns_status atns_host_filter_coefficients(double alpha, double* a6);
 
 /* Fused RK4 stage pairs (on != 0): 3-D Euler contexts with classical RK4 in
  * single precision run stages 1-2 and stages 3-4 as two kernels instead of

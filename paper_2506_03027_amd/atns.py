@@ -43,7 +43,8 @@ EXPORTS = ["atns_version", "atns_create", "atns_destroy", "atns_last_error", "at
            "atns_mlp_grad", "atns_mlp_sample", "atns_mlp_train", "atns_mlp_enable", "atns_mlp_stats",
            "atns_hbm_probe", "atns_host_weights", "atns_host_delays", "atns_batch_create",
            "atns_batch_destroy", "atns_batch_last_error", "atns_batch_member", "atns_batch_set_tiles",
-           "atns_batch_autotune", "atns_batch_step", "atns_init_case", "atns_checkpoint", "atns_restore"]
+           "atns_batch_autotune", "atns_batch_step", "atns_init_case", "atns_checkpoint", "atns_restore",
+           "atns_filter_state", "atns_host_filter_coefficients"]
 MLP_PARAMS = 9360
 
 
@@ -59,7 +60,8 @@ class Config(ctypes.Structure):
                 ("physics", ctypes.c_int32), ("gamma", ctypes.c_double), ("mach", ctypes.c_double),
                 ("re", ctypes.c_double), ("pr", ctypes.c_double), ("rk", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("algo", ctypes.c_int32), ("L", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("filter", ctypes.c_int32),
+                ("filter_alpha", ctypes.c_double)]
 
 
 _lib = None
@@ -108,6 +110,8 @@ def lib():
             "atns_mlp_enable": ([vp, i32, dbl], i32),
             "atns_mlp_stats": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
             "atns_host_weights": ([i32, i32, i32, vp], i32),
+            "atns_filter_state": ([vp], i32),
+            "atns_host_filter_coefficients": ([dbl, vp], i32),
             "atns_host_delays": ([i32, i32, i64, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(i32)], i32),
             "atns_batch_create": ([ctypes.POINTER(Config), i32, vp, ctypes.POINTER(vp)], i32),
             "atns_batch_destroy": ([vp], i32),
@@ -166,8 +170,15 @@ def host_delays(algo, n, nblocks, L, seed, rk=RK4):
     return out, bool(sync.value)
 
 
+def host_filter_coefficients(alpha):
+    out = np.zeros(6, dtype=np.float64)
+    _check(lib().atns_host_filter_coefficients(float(alpha), out.ctypes.data))
+    return out
+
+
 def make_config(n, length, ndim=3, nblk=(1, 1, 1), physics=EULER, gamma=1.4, mach=0.1, re=1600.0,
-                pr=0.71, rk=RK4, mode=SA, algo=CAA, L=1, seed=0, precision=F32, split=None):
+                pr=0.71, rk=RK4, mode=SA, algo=CAA, L=1, seed=0, precision=F32, split=None,
+                filter_alpha=None):
     cfg = Config()
     cfg.ndim = ndim
     for d in range(3):
@@ -182,6 +193,9 @@ def make_config(n, length, ndim=3, nblk=(1, 1, 1), physics=EULER, gamma=1.4, mac
             cfg.split[d] = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
     cfg.physics, cfg.gamma, cfg.mach, cfg.re, cfg.pr = physics, gamma, mach, re, pr
     cfg.rk, cfg.mode, cfg.algo, cfg.L, cfg.seed, cfg.precision = rk, mode, algo, L, seed, precision
+    # the tenth-order filter after every step when filter_alpha is given
+    cfg.filter = 0 if filter_alpha is None else 1
+    cfg.filter_alpha = 0.0 if filter_alpha is None else float(filter_alpha)
     return cfg, keep
 
 
@@ -289,6 +303,10 @@ class Solver:
 
     def step(self, nsteps=1):
         _check(lib().atns_rk_step(self.ctx, int(nsteps)), self.ctx)
+
+    def filter_state(self):
+        """The configured filter applied to the current state (synchronous halos)."""
+        _check(lib().atns_filter_state(self.ctx), self.ctx)
 
     def step_async(self, nsteps, spin_limit=1 << 20):
         """Free-running asynchronous steps; returns the realized delays

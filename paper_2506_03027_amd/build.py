@@ -15,7 +15,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libatns.so")
 
 SOURCES = ["atns.cpp", "coeffs.cpp", "kernels_euler.hip", "kernels_pair.hip", "kernels_ns.hip", "kernels_misc.hip",
-           "mlp.hip"]
+           "kernels_filter.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -53,7 +53,10 @@ struct atns_ctx {
   int64_t inject0 = 0;
   int inject_n = 0;
   double* d_W = nullptr;
-  void* hbuf = nullptr;              // stage halos: stages x slot_stride
+  void* hbuf = nullptr;              // stage halos: stages (+1 filter) x slot_stride
+  double* d_finv = nullptr;          // filter: forward-elimination factors
+  double* d_fcp = nullptr;
+  double fah[6] = {0, 0, 0, 0, 0, 0};   // filter: a_0, a_1/2, ..., a_5/2
   HaloRegion* d_regions = nullptr;
   HaloWork* d_work = nullptr;
   int nwork = 0;
@@ -142,6 +145,14 @@ bool slot_used(const atns_ctx* c, int s) {
   return nz == 1 || (nz == 2 && c->cfg.physics == ATNS_NS);
 }
 
+// Face depth of the halo regions and ring layers: 2 (Euler CD4), 4
+// (Navier-Stokes: gradients, then flux derivatives), 5 with the filter (its
+// right-hand side reaches five points).
+int halo_depth(const atns_config* cfg) {
+  if (cfg->physics != ATNS_NS) return 2;
+  return cfg->filter ? 5 : 4;
+}
+
 atns_status validate(const atns_config* cfg, std::vector<int> split[3], atns_ctx* c) {
   if (!cfg) return fail(c, ATNS_EINVAL, "null config");
   if (cfg->ndim != 2 && cfg->ndim != 3) return fail(c, ATNS_EINVAL, "ndim must be 2 or 3");
@@ -156,7 +167,13 @@ atns_status validate(const atns_config* cfg, std::vector<int> split[3], atns_ctx
   if (!(cfg->gamma > 1.0)) return fail(c, ATNS_EINVAL, "gamma must exceed 1");
   if (cfg->physics == ATNS_NS && (!(cfg->mach > 0) || !(cfg->re > 0) || !(cfg->pr > 0)))
     return fail(c, ATNS_EINVAL, "Navier-Stokes needs mach, re, pr > 0");
-  const int H = cfg->physics == ATNS_NS ? 4 : 2;
+  if (cfg->filter != 0 && cfg->filter != 1) return fail(c, ATNS_EINVAL, "filter must be 0 or 1");
+  if (cfg->filter) {
+    if (cfg->physics != ATNS_NS) return fail(c, ATNS_EINVAL, "the filter is built for Navier-Stokes contexts");
+    if (!(cfg->filter_alpha > -0.5 && cfg->filter_alpha <= 0.5))
+      return fail(c, ATNS_EINVAL, "filter_alpha must lie in (-0.5, 0.5]");
+  }
+  const int H = halo_depth(cfg);
   for (int d = 0; d < 3; ++d) {
     if (cfg->n[d] < 1 || cfg->nblk[d] < 1 || cfg->nblk[d] > cfg->n[d])
       return fail(c, ATNS_EINVAL, "bad grid or block count");
@@ -178,6 +195,8 @@ atns_status validate(const atns_config* cfg, std::vector<int> split[3], atns_ctx
     for (int s : split[d]) {
       if (s < 1) return fail(c, ATNS_EINVAL, "empty block");
       if (active && s < H) return fail(c, ATNS_EINVAL, "block smaller than the halo depth");
+      if (active && cfg->filter && s > kFilterMaxLen)
+        return fail(c, ATNS_EINVAL, "block longer than the filter's line limit");
     }
   }
   if (cfg->ndim == 2 && (cfg->n[2] != 1 || cfg->nblk[2] != 1))
@@ -453,6 +472,10 @@ hipError_t launch_pair(atns_ctx* c, const StageParams<T>& pA, const StageParams<
 
 bool is_async(const atns_ctx* c, int64_t step) { return c->cfg.mode != ATNS_SA && step >= c->C; }
 
+// Slots of the stage-halo buffer: one per stage, and the filter's halo at
+// the new level when the filter is on.
+int halo_slots(const atns_ctx* c) { return c->rk.stages + (c->cfg.filter ? 1 : 0); }
+
 atns_status draw_delays(atns_ctx* c, int64_t step, int8_t* dst) {
   const int8_t* inj = nullptr;
   if (c->inject_n > 0 && step >= c->inject0 && step < c->inject0 + c->inject_n)
@@ -485,7 +508,7 @@ atns_status prepare_halos(atns_ctx* c) {
   if (st != ATNS_OK) return st;
   HIP_TRY(c, launch_halo<T>((const T*)c->ring, (T*)c->hbuf, c->d_regions, c->d_work, (int)c->work.size(),
                             c->d_delays, c->d_W, c->slot_stride, c->slot_stride, c->D,
-                            (int)(c->step % c->D), c->cfg.L, c->rk.stages, c->cfg.mode == ATNS_AS,
+                            (int)(c->step % c->D), c->cfg.L, halo_slots(c), c->cfg.mode == ATNS_AS,
                             c->stream));
   if (c->mlp_on && c->cfg.mode == ATNS_AT) {
     MlpFeatArgs<T> fa = feat_args<T>(c);
@@ -525,7 +548,8 @@ StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind, bool fuse
   p.async_halo = c->cfg.mode == ATNS_SA ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
   p.halo = kHaloSync;
   p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)e * c->slot_stride : nullptr;
-  p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
+  // with the filter on, the ring receives the filtered field after the passes
+  p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1) && !c->cfg.filter;
   if (e == 0 && fuse_halos(c)) {
     p.fuse_halo = 1;
     p.S = rk.stages;
@@ -570,7 +594,7 @@ atns_status enqueue_graph_halos(atns_ctx* c, hipStream_t s) {
   const DelayDraw dd{1, c->nb, c->cfg.algo == ATNS_SAA ? 1 : 0, (unsigned long long)c->cfg.seed};
   HIP_TRY(c, launch_halo<T>((const T*)c->ring, (T*)c->hbuf, c->d_regions, c->d_work, (int)c->work.size(),
                             c->d_delays, c->d_W, c->slot_stride, c->slot_stride, c->D, 0, c->cfg.L,
-                            c->rk.stages, c->cfg.mode == ATNS_AS, s, c->d_nstep, dd));
+                            halo_slots(c), c->cfg.mode == ATNS_AS, s, c->d_nstep, dd));
   if (c->mlp_on && c->cfg.mode == ATNS_AT) {
     MlpFeatArgs<T> fa = feat_args<T>(c);
     fa.nstep = c->d_nstep;
@@ -578,6 +602,47 @@ atns_status enqueue_graph_halos(atns_ctx* c, hipStream_t s) {
                            (long long)c->face_chunks.size(), c->d_delays, (T*)c->hbuf, c->slot_stride,
                            c->rk.stages, c->d_counters, s));
   }
+  return ATNS_OK;
+}
+
+// The filter passes on the state in X[fin] (x: X[fin] -> X[1-fin], y: ->
+// X[2], z: -> X[fin]; 2-D: X[fin] -> X[1-fin] -> X[fin]; the other RK
+// registers are free after the last stage), then the ring write of the
+// filtered field into slot `slot` (or, with nstep, the slot of *nstep).
+// halo: the step's HaloMode (ignored with nstep, which the kernels read).
+template <typename T>
+atns_status enqueue_filter(atns_ctx* c, int fin, int halo, const long long* nstep, int slot, hipStream_t s) {
+  T* U = (T*)c->X[fin];
+  T* bufs3[4] = {U, (T*)c->X[1 - fin], (T*)c->X[2], U};
+  T* bufs2[3] = {U, (T*)c->X[1 - fin], U};
+  T** bufs = c->cfg.ndim == 3 ? bufs3 : bufs2;
+  for (int d = 0; d < c->cfg.ndim; ++d) {
+    FilterArgs<T> f{};
+    f.in = bufs[d];
+    f.out = bufs[d + 1];
+    f.blocks = c->d_blocks;
+    f.fhalo = c->hbuf ? (const T*)c->hbuf + (size_t)c->rk.stages * c->slot_stride : nullptr;
+    f.inv = c->d_finv;
+    f.cp = c->d_fcp;
+    for (int i = 0; i < 3; ++i) f.n[i] = c->n[i];
+    f.field = c->field;
+    f.H = c->H;
+    f.dir = d;
+    f.halo = halo;
+    f.nstep = nstep;
+    f.C = c->C;
+    f.async_halo = c->cfg.mode == ATNS_SA ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
+    for (int m = 0; m < 6; ++m) f.ah[m] = c->fah[m];
+    f.alpha = c->cfg.filter_alpha;
+    const int pa = d == 0 ? 1 : 0, qa = d == 2 ? 1 : 2;
+    int max_lines = 1, max_len = 1;
+    for (const BlockDev& B : c->blocks) {
+      max_lines = std::max(max_lines, B.s[pa] * B.s[qa]);
+      max_len = std::max(max_len, B.s[d]);
+    }
+    HIP_TRY(c, launch_filter_pass<T>(f, c->nb, max_lines, max_len, s));
+  }
+  if (c->ring) HIP_TRY(c, launch_ring_fill<T>(base_params<T>(c), U, slot, c->nb, s, nstep));
   return ATNS_OK;
 }
 
@@ -607,6 +672,12 @@ atns_status capture_step(atns_ctx* c, hipGraphExec_t* out) {
               : launch_euler_stage<T>(p, (int)c->tiles.size(), kind, c->tile[0], c->tile[1], s);
     }
     if (r != hipSuccess) st = fail(c, ATNS_EHIP, std::string("stage launch in capture: ") + hipGetErrorString(r));
+  }
+  if (st == ATNS_OK && c->cfg.filter) {
+    // the last stage has advanced the counter: the passes and the ring
+    // write read the step as *nstep - 1 and the slot as *nstep mod D
+    const int fin = c->rk.low_storage ? ((c->cur + c->rk.stages) & 1) : c->cur;
+    st = enqueue_filter<T>(c, fin, kHaloSync, c->d_nstep, 0, s);
   }
   const hipError_t ec = hipStreamEndCapture(s, &graph);
   if (st != ATNS_OK) {
@@ -673,7 +744,7 @@ atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
     HIP_TRY(c, prof_begin(c, c->stream));
     for (int e = 0; e < rk.stages; ++e) {
       p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)e * c->slot_stride : nullptr;
-      p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1);
+      p.ring_write = (c->ring != nullptr) && (e == rk.stages - 1) && !c->cfg.filter;
       int kind;
       if (!rk.low_storage) {
         T* U = (T*)c->X[c->cur];
@@ -707,6 +778,11 @@ atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
     }
     HIP_TRY(c, prof_end(c, c->stream, pairs ? rk.stages / 2 : rk.stages));
     if (pairs) c->cur = 1 - c->cur;   // the new state went to X[1 - cur]
+    if (c->cfg.filter) {
+      atns_status st = enqueue_filter<T>(c, c->cur, p.halo, nullptr, c->D ? (int)((c->step + 1) % c->D) : 0,
+                                         c->stream);
+      if (st != ATNS_OK) return st;
+    }
     c->step += 1;
   }
   return ATNS_OK;
@@ -747,7 +823,7 @@ void release(atns_ctx* c) {
                   c->d_face_regions, c->d_face_chunks, c->d_W0at, c->net.params, c->net.w1, c->net.w2,
                   c->net.w3, c->d_adam_m, c->d_adam_v, c->d_grad, c->d_part, c->d_loss_part, c->d_loss,
                   c->d_X, c->d_Y, c->d_counters, c->d_prog, c->d_abort, c->d_btiles, c->d_tile_begin,
-                  c->d_reg_begin, c->d_async_ps};
+                  c->d_reg_begin, c->d_async_ps, c->d_finv, c->d_fcp};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   c->ring = nullptr;
@@ -779,7 +855,7 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
     c->h[d] = cfg->len[d] / cfg->n[d];
   }
   c->stream = (hipStream_t)stream;
-  c->H = cfg->physics == ATNS_NS ? 4 : 2;
+  c->H = halo_depth(cfg);
   c->rk = make_rk(cfg->rk);
   c->C = levels(cfg->rk);
   c->esz = cfg->precision == ATNS_F64 ? 8 : 4;
@@ -817,7 +893,7 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
     if (hipMalloc(&c->ring, (size_t)c->slot_stride * c->D * c->esz) != hipSuccess)
       return fail_free(ATNS_ENOMEM, "ring allocation failed");
     if (cfg->mode != ATNS_SA &&
-        hipMalloc(&c->hbuf, (size_t)c->slot_stride * c->rk.stages * c->esz) != hipSuccess)
+        hipMalloc(&c->hbuf, (size_t)c->slot_stride * halo_slots(c) * c->esz) != hipSuccess)
       return fail_free(ATNS_ENOMEM, "halo buffer allocation failed");
     {
       const std::vector<double> W0 = halo_weights(cfg->rk, ATNS_AT, cfg->L);   // stage 0 = first L*C entries
@@ -843,10 +919,25 @@ atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
         hipMemcpy(c->d_work, c->work.data(), c->work.size() * sizeof(HaloWork), hipMemcpyHostToDevice) !=
             hipSuccess)
       return fail_free(ATNS_EHIP, "halo table upload failed");
-    const std::vector<double> W = halo_weights(cfg->rk, cfg->mode == ATNS_AS ? ATNS_AS : ATNS_AT, cfg->L);
+    std::vector<double> W = halo_weights(cfg->rk, cfg->mode == ATNS_AS ? ATNS_AS : ATNS_AT, cfg->L);
+    if (cfg->filter) {   // the filter-halo row follows the stage rows
+      const std::vector<double> Wf = filter_halo_weights(cfg->rk, cfg->mode == ATNS_AS ? ATNS_AS : ATNS_AT, cfg->L);
+      W.insert(W.end(), Wf.begin(), Wf.end());
+    }
     if (hipMalloc((void**)&c->d_W, W.size() * sizeof(double)) != hipSuccess ||
         hipMemcpy(c->d_W, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
       return fail_free(ATNS_EHIP, "weight table upload failed");
+  }
+  if (cfg->filter) {
+    const std::vector<double> a = filter_coefficients(cfg->filter_alpha);
+    for (int m = 0; m < 6; ++m) c->fah[m] = m == 0 ? a[0] : 0.5 * a[m];
+    std::vector<double> inv, cp;
+    filter_thomas(cfg->filter_alpha, kFilterMaxLen, inv, cp);
+    if (hipMalloc((void**)&c->d_finv, kFilterMaxLen * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&c->d_fcp, kFilterMaxLen * sizeof(double)) != hipSuccess ||
+        hipMemcpy(c->d_finv, inv.data(), kFilterMaxLen * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_fcp, cp.data(), kFilterMaxLen * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return fail_free(ATNS_EHIP, "filter table upload failed");
   }
   const size_t dcount = (size_t)c->nb * kNumSlots;
   if (hipMalloc((void**)&c->d_blocks, c->blocks.size() * sizeof(BlockDev)) != hipSuccess ||
@@ -918,6 +1009,8 @@ uint64_t config_fingerprint(const atns_ctx* c) {
   mix(&g.L, sizeof g.L);
   mix(&g.seed, sizeof g.seed);
   mix(&g.precision, sizeof g.precision);
+  mix(&g.filter, sizeof g.filter);
+  if (g.filter) mix(&g.filter_alpha, sizeof g.filter_alpha);
   for (const BlockDev& B : c->blocks) {
     mix(B.o, sizeof B.o);
     mix(B.s, sizeof B.s);
@@ -1263,6 +1356,7 @@ atns_status atns_step_async(atns_ctx* c, int32_t nsteps, int64_t spin_limit, int
   if (c->rk.stages != 4 && c->rk.stages != 2)
     return fail(c, ATNS_EINVAL, "free-running steps need ATNS_RK4 or ATNS_LSERK2");
   if (c->mlp_on) return fail(c, ATNS_EINVAL, "the learned halo is not applied in free-running steps");
+  if (c->cfg.filter) return fail(c, ATNS_EINVAL, "the filter is not applied in free-running steps");
   if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
   if (!(c->dt > 0)) return fail(c, ATNS_ESTATE, "dt not set");
   if (c->step < c->C + c->cfg.L - 1) return fail(c, ATNS_ESTATE, "history shorter than C + L - 1 levels");
@@ -1712,6 +1806,7 @@ atns_status atns_mlp_enable(atns_ctx* c, int32_t on, double tau) {
   if (on && !c->mlp_ready) return fail(c, ATNS_ESTATE, "MLP parameters not set");
   if (on && c->cfg.mode != ATNS_AT) return fail(c, ATNS_EINVAL, "the learned halo needs mode ATNS_AT");
   if (on && c->C != kMaxC) return fail(c, ATNS_EINVAL, "the learned halo works with AT4 (C = 5 levels)");
+  if (on && c->cfg.filter) return fail(c, ATNS_EINVAL, "the learned halo is not combined with the filter");
   if (!(tau >= 0)) return fail(c, ATNS_EINVAL, "tau must be non-negative");
   c->mlp_on = on != 0;
   c->mlp_tau = tau;
@@ -1739,6 +1834,22 @@ atns_status atns_hbm_probe(const void* dev_src, void* dev_dst, int64_t bytes, vo
     return fail(nullptr, ATNS_EINVAL, "probe needs device buffers and a positive multiple of 16 bytes");
   const hipError_t e = launch_copy_probe(dev_src, dev_dst, bytes, (hipStream_t)stream);
   if (e != hipSuccess) return fail(nullptr, ATNS_EHIP, std::string("copy probe: ") + hipGetErrorString(e));
+  return ATNS_OK;
+}
+
+atns_status atns_filter_state(atns_ctx* c) {
+  if (!c) return fail(c, ATNS_EINVAL, "null context");
+  if (!c->cfg.filter) return fail(c, ATNS_EINVAL, "the context has no filter");
+  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+  const int slot = c->D ? (int)(c->step % c->D) : 0;
+  return c->esz == 4 ? enqueue_filter<float>(c, c->cur, kHaloSync, nullptr, slot, c->stream)
+                     : enqueue_filter<double>(c, c->cur, kHaloSync, nullptr, slot, c->stream);
+}
+
+atns_status atns_host_filter_coefficients(double alpha, double* a6) {
+  if (!a6 || !(alpha > -0.5 && alpha <= 0.5)) return fail(nullptr, ATNS_EINVAL, "bad filter request");
+  const std::vector<double> a = filter_coefficients(alpha);
+  for (int m = 0; m < 6; ++m) a6[m] = a[m];
   return ATNS_OK;
 }
 
@@ -1995,6 +2106,7 @@ atns_status atns_batch_create(const atns_config* cfgs, int32_t n, void* stream, 
     if (cfgs[i].rk != ATNS_RK4) return bfail(nullptr, ATNS_EINVAL, "batch members use classical RK4");
     if (cfgs[i].precision != cfgs[0].precision) return bfail(nullptr, ATNS_EINVAL, "batch members share precision");
     if (cfgs[i].ndim != 3) return bfail(nullptr, ATNS_EINVAL, "batch members are three-dimensional");
+    if (cfgs[i].filter) return bfail(nullptr, ATNS_EINVAL, "batch members run without the filter");
   }
   auto* b = new atns_batch();
   b->user = (hipStream_t)stream;

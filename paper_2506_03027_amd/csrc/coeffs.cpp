@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "atns.h"
 
@@ -144,6 +145,56 @@ std::vector<double> halo_weights(int rk, int mode, int L) {
         W[((size_t)e * L + k) * C + l] = (double)w;
       }
   return W;
+}
+
+std::vector<double> filter_coefficients(double alpha) {
+  // 6 x 6 system, Gaussian elimination with partial pivoting in long double
+  long double M[6][7];
+  for (int p = 0; p < 5; ++p) {
+    for (int m = 0; m < 6; ++m) {
+      long double v = 1.0L;
+      for (int q = 0; q < 2 * p; ++q) v *= (long double)m;
+      M[p][m] = v;   // m^{2p}, with 0^0 = 1
+    }
+    M[p][6] = (p == 0 ? 1.0L : 0.0L) + 2.0L * (long double)alpha;
+  }
+  for (int m = 0; m < 6; ++m) M[5][m] = (m & 1) ? -1.0L : 1.0L;
+  M[5][6] = 0.0L;
+  for (int col = 0; col < 6; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 6; ++r)
+      if (std::fabs((double)M[r][col]) > std::fabs((double)M[piv][col])) piv = r;
+    for (int j = 0; j < 7; ++j) std::swap(M[col][j], M[piv][j]);
+    for (int r = 0; r < 6; ++r) {
+      if (r == col) continue;
+      const long double f = M[r][col] / M[col][col];
+      for (int j = col; j < 7; ++j) M[r][j] -= f * M[col][j];
+    }
+  }
+  std::vector<double> a(6);
+  for (int m = 0; m < 6; ++m) a[m] = (double)(M[m][6] / M[m][m]);
+  return a;
+}
+
+std::vector<double> filter_halo_weights(int rk, int mode, int L) {
+  const int C = levels(rk);
+  std::vector<double> W((size_t)L * C, 0.0);
+  for (int k = 0; k < L; ++k)
+    for (int l = 0; l < C; ++l)
+      W[(size_t)k * C + l] = mode == ATNS_AT ? (double)basis_derivative(k + 1, l, 0, C) : (l == 0 ? 1.0 : 0.0);
+  return W;
+}
+
+void filter_thomas(double alpha, int n, std::vector<double>& inv, std::vector<double>& cp) {
+  inv.assign(n, 1.0);
+  cp.assign(n, alpha);
+  long double c = alpha;
+  for (int i = 1; i < n; ++i) {
+    const long double m = 1.0L / (1.0L - (long double)alpha * c);
+    c = (long double)alpha * m;
+    inv[i] = (double)m;
+    cp[i] = (double)c;
+  }
 }
 
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output i of the generator

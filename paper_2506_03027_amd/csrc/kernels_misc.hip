@@ -84,12 +84,17 @@ hipError_t launch_halo(const T* ring, T* halo, const HaloRegion* regions, const 
                                                      halo_stride, D, slot_now, L, nstep, dd)
   // the stage count identifies the scheme: RK4 and LSERK4 pair with AT4
   // (C = 5), LSERK2 with AT2 (C = 3)
+  // (one more slot than stages: the filter's halo at the new level)
   if (stages == 4) {
     if (stale) ATNS_HALO(4, 5, true); else ATNS_HALO(4, 5, false);
   } else if (stages == 5) {
     if (stale) ATNS_HALO(5, 5, true); else ATNS_HALO(5, 5, false);
+  } else if (stages == 6) {
+    if (stale) ATNS_HALO(6, 5, true); else ATNS_HALO(6, 5, false);
   } else if (stages == 2) {
     if (stale) ATNS_HALO(2, 3, true); else ATNS_HALO(2, 3, false);
+  } else if (stages == 3) {
+    if (stale) ATNS_HALO(3, 3, true); else ATNS_HALO(3, 3, false);
   } else {
     return hipErrorInvalidValue;
   }
@@ -105,7 +110,8 @@ template hipError_t launch_halo<double>(const double*, double*, const HaloRegion
 
 // Copy the boundary layers of every block of field U into ring slot `slot`.
 template <typename T>
-__global__ void ring_fill_kernel(const StageParams<T> p, const T* U, int slot) {
+__global__ void ring_fill_kernel(const StageParams<T> p, const T* U, int slot, const long long* nstep) {
+  if (nstep) slot = (int)(*nstep % p.D);
   const int b = blockIdx.y;
   const BlockDev* B = p.blocks + b;
   const long long cnt = (long long)B->s[0] * B->s[1] * B->s[2];
@@ -124,13 +130,16 @@ __global__ void ring_fill_kernel(const StageParams<T> p, const T* U, int slot) {
 }
 
 template <typename T>
-hipError_t launch_ring_fill(const StageParams<T>& p, const T* U, int slot, int nblocks, hipStream_t s) {
+hipError_t launch_ring_fill(const StageParams<T>& p, const T* U, int slot, int nblocks, hipStream_t s,
+                            const long long* nstep) {
   dim3 grid(64, nblocks), block(256);
-  ring_fill_kernel<T><<<grid, block, 0, s>>>(p, U, slot);
+  ring_fill_kernel<T><<<grid, block, 0, s>>>(p, U, slot, nstep);
   return hipGetLastError();
 }
-template hipError_t launch_ring_fill<float>(const StageParams<float>&, const float*, int, int, hipStream_t);
-template hipError_t launch_ring_fill<double>(const StageParams<double>&, const double*, int, int, hipStream_t);
+template hipError_t launch_ring_fill<float>(const StageParams<float>&, const float*, int, int, hipStream_t,
+                                            const long long*);
+template hipError_t launch_ring_fill<double>(const StageParams<double>&, const double*, int, int, hipStream_t,
+                                             const long long*);
 
 // ------------------------------------------------------------------ HBM probe
 // Plain streaming copy, 16 bytes per lane per iteration: the achievable HBM

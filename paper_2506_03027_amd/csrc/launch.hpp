@@ -46,8 +46,16 @@ hipError_t launch_init_case(T* U, const int n[3], const double h[3], const doubl
 hipError_t launch_copy_probe(const void* src, void* dst, long long bytes, hipStream_t s);
 hipError_t launch_delays(int8_t* out, const int8_t* inject, long long n, int nblocks, int L, int C,
                          unsigned long long seed, int algo, hipStream_t s, const long long* nstep = nullptr);
+// nstep set (graph-captured steps): the slot is *nstep mod D instead.
 template <typename T>
-hipError_t launch_ring_fill(const StageParams<T>& p, const T* U, int slot, int nblocks, hipStream_t s);
+hipError_t launch_ring_fill(const StageParams<T>& p, const T* U, int slot, int nblocks, hipStream_t s,
+                            const long long* nstep = nullptr);
+// One pass of the block-local filter along axis f.dir: max_lines, the most
+// lines of one block along the axis; max_len, the longest block side along
+// it (at most kFilterMaxLen; the launch's LDS holds max_len x 64 doubles).
+constexpr int kFilterMaxLen = 256;
+template <typename T>
+hipError_t launch_filter_pass(const FilterArgs<T>& f, int nblocks, int max_lines, int max_len, hipStream_t s);
 // Workgroups (and FP64 partial sets of 7) of the diagnostics reduction; the
 // allocation-free form keeps its partials in a fixed device array of this size.
 constexpr int kDiagMaxParts = 1024;

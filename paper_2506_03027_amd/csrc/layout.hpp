@@ -192,4 +192,32 @@ struct StageParams {
   DelayDraw dd;
 };
 
+// One pass of the tenth-order filter along axis dir: every block filters its
+// lines of `in` into `out` (distinct buffers).  Halo points beyond a face
+// come from `in` at the periodic neighbour position (synchronous) or from
+// the filter-halo slot `fhalo` of the stage-halo buffer (delayed halos, same
+// region layout as the stage halos).
+template <typename T>
+struct FilterArgs {
+  const T* in;
+  T* out;
+  const BlockDev* blocks;
+  const T* fhalo;        // filter-halo slot, or null when the context has none
+  const double* inv;     // forward-elimination factors, rows 0..kFilterMaxLen-1
+  const double* cp;
+  int n[3];
+  long long field;
+  int H;                 // face depth of the halo regions
+  int dir;
+  int halo;              // HaloMode of the step
+  // graph-captured steps: the step counter already advanced by the last
+  // stage, so the step is *nstep - 1 and halo = (step >= C) ? async_halo :
+  // kHaloSync
+  const long long* nstep;
+  int C;
+  int async_halo;
+  double ah[6];          // a_0, a_1/2, ..., a_5/2
+  double alpha;
+};
+
 }  // namespace atns

@@ -33,18 +33,19 @@ def pair(spec, precision="f64", dt=None):
     physics, rk, mode, algo, L, seed, re, mach, split.  rk "lserk2" is the
     second-order method (CD2, AT2 with three levels) on both sides."""
     s = dict(ndim=3, nblk=(1, 1, 1), physics="euler", rk="rk4", mode="sa", algo="caa", L=1,
-             seed=0, re=1600.0, mach=0.1, gamma=1.4, pr=0.71, split=None)
+             seed=0, re=1600.0, mach=0.1, gamma=1.4, pr=0.71, split=None, filter_alpha=None)
     s.update(spec)
     cfg = solver.Config(s["n"], s["length"], s["ndim"], s["nblk"], s["physics"], gamma=s["gamma"],
                         mach=s["mach"], re=s["re"], pr=s["pr"], rk=s["rk"], mode=s["mode"],
                         algo=s["algo"], L=s["L"], seed=s["seed"], dt=dt, split=s["split"],
-                        order=2 if s["rk"] == "lserk2" else 4, C=3 if s["rk"] == "lserk2" else 5)
+                        order=2 if s["rk"] == "lserk2" else 4, C=3 if s["rk"] == "lserk2" else 5,
+                        filter_alpha=s["filter_alpha"])
     o = solver.Oracle(cfg)
     g = atns.Solver(n=s["n"], length=s["length"], ndim=s["ndim"], nblk=s["nblk"],
                     physics=PHYS[s["physics"]], gamma=s["gamma"], mach=s["mach"], re=s["re"],
                     pr=s["pr"], rk=RK[s["rk"]], mode=MODE[s["mode"]], algo=ALGO[s["algo"]],
                     L=s["L"], seed=s["seed"], precision=atns.F64 if precision == "f64" else atns.F32,
-                    split=s["split"])
+                    split=s["split"], filter_alpha=s["filter_alpha"])
     if dt is not None:
         g.set_dt(dt)
     return o, g

@@ -166,3 +166,31 @@ def test_separable_field_point_values_equal_whole_field():
     for x, y, z in [(0, 0, 0), (11, 9, 7), (5, 3, 2), (7, 0, 6)]:
         assert [F[v][z, y, x] for v in range(5)] == inputs.separable_at(s, x, y, z)
     assert min(F[0].min(), F[4].min()) > 0.5
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.3, 0.499, 0.5, -0.49])
+def test_host_filter_coefficients_match_oracle(alpha):
+    from oracle import filter as ofilt
+    a = atns.host_filter_coefficients(alpha)
+    ref = np.array([float(x) for x in ofilt.coefficients(alpha)])
+    assert np.abs(a - ref).max() < 1e-15
+
+
+@pytest.mark.parametrize("bad", [
+    dict(filter_alpha=0.5000001),
+    dict(filter_alpha=-0.5),
+    dict(physics=atns.EULER, filter_alpha=0.499),          # Navier-Stokes only
+    dict(nblk=(8, 1, 1), filter_alpha=0.499),              # 4-point blocks < filter depth 5
+    dict(n=(300, 8, 8), nblk=(1, 1, 1), filter_alpha=0.3),  # lines longer than 256
+])
+def test_create_rejects_bad_filter_config_without_device(bad):
+    import ctypes
+    kw = dict(n=(32, 32, 32), length=(1.0, 1.0, 1.0), ndim=3, nblk=(2, 2, 2), physics=atns.NS)
+    kw.update(bad)
+    cfg, keep = atns.make_config(**kw)
+    ctx = ctypes.c_void_p()
+    assert atns.lib().atns_create(ctypes.byref(cfg), None, ctypes.byref(ctx)) == -1
+    assert ctx.value is None
+    out = np.zeros(6)
+    assert atns.lib().atns_host_filter_coefficients(0.6, out.ctypes.data) == -1
+    assert atns.lib().atns_filter_state(None) == -1
