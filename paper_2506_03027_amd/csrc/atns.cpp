@@ -8,6 +8,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -128,6 +130,37 @@ atns_status fail(atns_ctx* c, atns_status s, const std::string& msg) {
   if (c) c->err = msg;
   g_err = msg;
   return s;
+}
+
+// Entry points never let a C++ exception cross the C ABI (an uncaught one
+// would end the caller's process with std::terminate): host allocation
+// failures become ATNS_ENOMEM, anything else ATNS_EHIP, with the message.
+template <class F>
+atns_status guard_body(F&& f, std::string* err) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    if (err) *err = "host allocation failed";
+    g_err = "host allocation failed";
+    return ATNS_ENOMEM;
+  } catch (const std::exception& e) {
+    const std::string m = std::string("host exception: ") + e.what();
+    if (err) *err = m;
+    g_err = m;
+    return ATNS_EHIP;
+  } catch (...) {
+    if (err) *err = "host exception";
+    g_err = "host exception";
+    return ATNS_EHIP;
+  }
+}
+template <class F>
+atns_status guarded(const atns_ctx* c, F&& f) {
+  return guard_body(std::forward<F>(f), c ? &const_cast<atns_ctx*>(c)->err : nullptr);
+}
+template <class F>
+atns_status guarded(std::nullptr_t, F&& f) {
+  return guard_body(std::forward<F>(f), nullptr);
 }
 
 #define HIP_TRY(ctx, expr)                                                                  \
@@ -838,130 +871,134 @@ const char* atns_version(void) { return "atns 0.1 gfx950"; }
 const char* atns_last_error(const atns_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
 atns_status atns_create(const atns_config* cfg, void* stream, atns_ctx** out) {
-  if (!out) return fail(nullptr, ATNS_EINVAL, "null output pointer");
-  *out = nullptr;
-  auto* c = new atns_ctx();
-  std::vector<int> split[3];
-  atns_status st = validate(cfg, split, c);
-  if (st != ATNS_OK) {
-    delete c;
-    return st;
-  }
-  c->cfg = *cfg;
-  for (int d = 0; d < 3; ++d) {
-    c->split[d] = split[d];
-    c->cfg.split[d] = nullptr;
-    c->n[d] = cfg->n[d];
-    c->h[d] = cfg->len[d] / cfg->n[d];
-  }
-  c->stream = (hipStream_t)stream;
-  c->H = halo_depth(cfg);
-  c->rk = make_rk(cfg->rk);
-  c->C = levels(cfg->rk);
-  c->esz = cfg->precision == ATNS_F64 ? 8 : 4;
-  c->field = (long long)c->n[0] * c->n[1] * c->n[2];
-  build_layout(c);
-  default_tiles(c);
-  build_tiles(c, c->tile[0], c->tile[1], c->tile[2]);
-  // SA keeps a delayed-level ring only when L > 1 (history for the learned
-  // halo's training samples); the asynchronous modes always do.
-  // SA keeps C + L levels (training history); the asynchronous modes keep
-  // C + 2L - 1, so that free-running steps (atns_step_async), where a
-  // neighbour may run L - 1 steps ahead of a reader, never overwrite a level
-  // the reader still needs.  Scheduled delays need only C + L.
-  c->D = cfg->mode == ATNS_SA ? (cfg->L <= 1 ? 0 : c->C + cfg->L) : c->C + 2 * cfg->L - 1;
+  return guarded(nullptr, [&]() -> atns_status {
+    if (!out) return fail(nullptr, ATNS_EINVAL, "null output pointer");
+    *out = nullptr;
+    auto* c = new atns_ctx();
+    std::vector<int> split[3];
+    atns_status st = validate(cfg, split, c);
+    if (st != ATNS_OK) {
+      delete c;
+      return st;
+    }
+    c->cfg = *cfg;
+    for (int d = 0; d < 3; ++d) {
+      c->split[d] = split[d];
+      c->cfg.split[d] = nullptr;
+      c->n[d] = cfg->n[d];
+      c->h[d] = cfg->len[d] / cfg->n[d];
+    }
+    c->stream = (hipStream_t)stream;
+    c->H = halo_depth(cfg);
+    c->rk = make_rk(cfg->rk);
+    c->C = levels(cfg->rk);
+    c->esz = cfg->precision == ATNS_F64 ? 8 : 4;
+    c->field = (long long)c->n[0] * c->n[1] * c->n[2];
+    build_layout(c);
+    default_tiles(c);
+    build_tiles(c, c->tile[0], c->tile[1], c->tile[2]);
+    // SA keeps a delayed-level ring only when L > 1 (history for the learned
+    // halo's training samples); the asynchronous modes always do.
+    // SA keeps C + L levels (training history); the asynchronous modes keep
+    // C + 2L - 1, so that free-running steps (atns_step_async), where a
+    // neighbour may run L - 1 steps ahead of a reader, never overwrite a level
+    // the reader still needs.  Scheduled delays need only C + L.
+    c->D = cfg->mode == ATNS_SA ? (cfg->L <= 1 ? 0 : c->C + cfg->L) : c->C + 2 * cfg->L - 1;
 
-  auto fail_free = [&](atns_status s, const std::string& m) {
-    release(c);
-    g_err = m;
-    delete c;
-    return s;
-  };
-  if (hipGetDevice(&c->device) != hipSuccess) return fail_free(ATNS_EHIP, "no HIP device");
-  if (hipMalloc((void**)&c->d_nstep, sizeof(long long)) != hipSuccess ||
-      hipMalloc((void**)&c->d_done, sizeof(unsigned int)) != hipSuccess ||
-      hipMemset(c->d_done, 0, sizeof(unsigned int)) != hipSuccess)
-    return fail_free(ATNS_ENOMEM, "counter allocation failed");
-  if (!c->stream && hipStreamCreate(&c->gstream) != hipSuccess)
-    return fail_free(ATNS_EHIP, "stream creation failed");
-  if (hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming) != hipSuccess)
-    return fail_free(ATNS_EHIP, "event creation failed");
-  const size_t fbytes = (size_t)c->field * 5 * c->esz;
-  for (int i = 0; i < 4; ++i)
-    if (hipMalloc(&c->X[i], fbytes) != hipSuccess) return fail_free(ATNS_ENOMEM, "state allocation failed");
-  if (c->D) {
-    if (hipMalloc(&c->ring, (size_t)c->slot_stride * c->D * c->esz) != hipSuccess)
-      return fail_free(ATNS_ENOMEM, "ring allocation failed");
-    if (cfg->mode != ATNS_SA &&
-        hipMalloc(&c->hbuf, (size_t)c->slot_stride * halo_slots(c) * c->esz) != hipSuccess)
-      return fail_free(ATNS_ENOMEM, "halo buffer allocation failed");
-    {
-      const std::vector<double> W0 = halo_weights(cfg->rk, ATNS_AT, cfg->L);   // stage 0 = first L*C entries
-      if (hipMalloc((void**)&c->d_W0at, (size_t)cfg->L * c->C * sizeof(double)) != hipSuccess ||
-          hipMemcpy(c->d_W0at, W0.data(), (size_t)cfg->L * c->C * sizeof(double), hipMemcpyHostToDevice) !=
+    auto fail_free = [&](atns_status s, const std::string& m) {
+      release(c);
+      g_err = m;
+      delete c;
+      return s;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return fail_free(ATNS_EHIP, "no HIP device");
+    if (hipMalloc((void**)&c->d_nstep, sizeof(long long)) != hipSuccess ||
+        hipMalloc((void**)&c->d_done, sizeof(unsigned int)) != hipSuccess ||
+        hipMemset(c->d_done, 0, sizeof(unsigned int)) != hipSuccess)
+      return fail_free(ATNS_ENOMEM, "counter allocation failed");
+    if (!c->stream && hipStreamCreate(&c->gstream) != hipSuccess)
+      return fail_free(ATNS_EHIP, "stream creation failed");
+    if (hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming) != hipSuccess)
+      return fail_free(ATNS_EHIP, "event creation failed");
+    const size_t fbytes = (size_t)c->field * 5 * c->esz;
+    for (int i = 0; i < 4; ++i)
+      if (hipMalloc(&c->X[i], fbytes) != hipSuccess) return fail_free(ATNS_ENOMEM, "state allocation failed");
+    if (c->D) {
+      if (hipMalloc(&c->ring, (size_t)c->slot_stride * c->D * c->esz) != hipSuccess)
+        return fail_free(ATNS_ENOMEM, "ring allocation failed");
+      if (cfg->mode != ATNS_SA &&
+          hipMalloc(&c->hbuf, (size_t)c->slot_stride * halo_slots(c) * c->esz) != hipSuccess)
+        return fail_free(ATNS_ENOMEM, "halo buffer allocation failed");
+      {
+        const std::vector<double> W0 = halo_weights(cfg->rk, ATNS_AT, cfg->L);   // stage 0 = first L*C entries
+        if (hipMalloc((void**)&c->d_W0at, (size_t)cfg->L * c->C * sizeof(double)) != hipSuccess ||
+            hipMemcpy(c->d_W0at, W0.data(), (size_t)cfg->L * c->C * sizeof(double), hipMemcpyHostToDevice) !=
+                hipSuccess)
+          return fail_free(ATNS_EHIP, "weight table upload failed");
+        if (hipMalloc((void**)&c->d_faceinfo, c->faceinfo.size() * sizeof(FaceInfo)) != hipSuccess ||
+            hipMemcpy(c->d_faceinfo, c->faceinfo.data(), c->faceinfo.size() * sizeof(FaceInfo),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMalloc((void**)&c->d_face_regions, c->face_regions.size() * sizeof(int)) != hipSuccess ||
+            hipMemcpy(c->d_face_regions, c->face_regions.data(), c->face_regions.size() * sizeof(int),
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMalloc((void**)&c->d_face_chunks, c->face_chunks.size() * sizeof(HaloWork)) != hipSuccess ||
+            hipMemcpy(c->d_face_chunks, c->face_chunks.data(), c->face_chunks.size() * sizeof(HaloWork),
+                      hipMemcpyHostToDevice) != hipSuccess)
+          return fail_free(ATNS_EHIP, "face table upload failed");
+      }
+      if (hipMalloc((void**)&c->d_regions, c->regions.size() * sizeof(HaloRegion)) != hipSuccess ||
+          hipMalloc((void**)&c->d_work, c->work.size() * sizeof(HaloWork)) != hipSuccess ||
+          hipMemcpy(c->d_regions, c->regions.data(), c->regions.size() * sizeof(HaloRegion),
+                    hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(c->d_work, c->work.data(), c->work.size() * sizeof(HaloWork), hipMemcpyHostToDevice) !=
               hipSuccess)
+        return fail_free(ATNS_EHIP, "halo table upload failed");
+      std::vector<double> W = halo_weights(cfg->rk, cfg->mode == ATNS_AS ? ATNS_AS : ATNS_AT, cfg->L);
+      if (cfg->filter) {   // the filter-halo row follows the stage rows
+        const std::vector<double> Wf = filter_halo_weights(cfg->rk, cfg->mode == ATNS_AS ? ATNS_AS : ATNS_AT, cfg->L);
+        W.insert(W.end(), Wf.begin(), Wf.end());
+      }
+      if (hipMalloc((void**)&c->d_W, W.size() * sizeof(double)) != hipSuccess ||
+          hipMemcpy(c->d_W, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         return fail_free(ATNS_EHIP, "weight table upload failed");
-      if (hipMalloc((void**)&c->d_faceinfo, c->faceinfo.size() * sizeof(FaceInfo)) != hipSuccess ||
-          hipMemcpy(c->d_faceinfo, c->faceinfo.data(), c->faceinfo.size() * sizeof(FaceInfo),
-                    hipMemcpyHostToDevice) != hipSuccess ||
-          hipMalloc((void**)&c->d_face_regions, c->face_regions.size() * sizeof(int)) != hipSuccess ||
-          hipMemcpy(c->d_face_regions, c->face_regions.data(), c->face_regions.size() * sizeof(int),
-                    hipMemcpyHostToDevice) != hipSuccess ||
-          hipMalloc((void**)&c->d_face_chunks, c->face_chunks.size() * sizeof(HaloWork)) != hipSuccess ||
-          hipMemcpy(c->d_face_chunks, c->face_chunks.data(), c->face_chunks.size() * sizeof(HaloWork),
-                    hipMemcpyHostToDevice) != hipSuccess)
-        return fail_free(ATNS_EHIP, "face table upload failed");
     }
-    if (hipMalloc((void**)&c->d_regions, c->regions.size() * sizeof(HaloRegion)) != hipSuccess ||
-        hipMalloc((void**)&c->d_work, c->work.size() * sizeof(HaloWork)) != hipSuccess ||
-        hipMemcpy(c->d_regions, c->regions.data(), c->regions.size() * sizeof(HaloRegion),
-                  hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_work, c->work.data(), c->work.size() * sizeof(HaloWork), hipMemcpyHostToDevice) !=
-            hipSuccess)
-      return fail_free(ATNS_EHIP, "halo table upload failed");
-    std::vector<double> W = halo_weights(cfg->rk, cfg->mode == ATNS_AS ? ATNS_AS : ATNS_AT, cfg->L);
-    if (cfg->filter) {   // the filter-halo row follows the stage rows
-      const std::vector<double> Wf = filter_halo_weights(cfg->rk, cfg->mode == ATNS_AS ? ATNS_AS : ATNS_AT, cfg->L);
-      W.insert(W.end(), Wf.begin(), Wf.end());
+    if (cfg->filter) {
+      const std::vector<double> a = filter_coefficients(cfg->filter_alpha);
+      for (int m = 0; m < 6; ++m) c->fah[m] = m == 0 ? a[0] : 0.5 * a[m];
+      std::vector<double> inv, cp;
+      filter_thomas(cfg->filter_alpha, kFilterMaxLen, inv, cp);
+      if (hipMalloc((void**)&c->d_finv, kFilterMaxLen * sizeof(double)) != hipSuccess ||
+          hipMalloc((void**)&c->d_fcp, kFilterMaxLen * sizeof(double)) != hipSuccess ||
+          hipMemcpy(c->d_finv, inv.data(), kFilterMaxLen * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(c->d_fcp, cp.data(), kFilterMaxLen * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return fail_free(ATNS_EHIP, "filter table upload failed");
     }
-    if (hipMalloc((void**)&c->d_W, W.size() * sizeof(double)) != hipSuccess ||
-        hipMemcpy(c->d_W, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-      return fail_free(ATNS_EHIP, "weight table upload failed");
-  }
-  if (cfg->filter) {
-    const std::vector<double> a = filter_coefficients(cfg->filter_alpha);
-    for (int m = 0; m < 6; ++m) c->fah[m] = m == 0 ? a[0] : 0.5 * a[m];
-    std::vector<double> inv, cp;
-    filter_thomas(cfg->filter_alpha, kFilterMaxLen, inv, cp);
-    if (hipMalloc((void**)&c->d_finv, kFilterMaxLen * sizeof(double)) != hipSuccess ||
-        hipMalloc((void**)&c->d_fcp, kFilterMaxLen * sizeof(double)) != hipSuccess ||
-        hipMemcpy(c->d_finv, inv.data(), kFilterMaxLen * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c->d_fcp, cp.data(), kFilterMaxLen * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-      return fail_free(ATNS_EHIP, "filter table upload failed");
-  }
-  const size_t dcount = (size_t)c->nb * kNumSlots;
-  if (hipMalloc((void**)&c->d_blocks, c->blocks.size() * sizeof(BlockDev)) != hipSuccess ||
-      hipMalloc((void**)&c->d_tiles, c->tiles.size() * sizeof(TileDev)) != hipSuccess ||
-      hipMalloc((void**)&c->d_delays, dcount) != hipSuccess || hipMalloc((void**)&c->d_probe, dcount) != hipSuccess ||
-      hipMalloc((void**)&c->d_partials, (size_t)c->nparts * 7 * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&c->d_diag, 7 * sizeof(double)) != hipSuccess)
-    return fail_free(ATNS_ENOMEM, "table allocation failed");
-  if (hipMemcpy(c->d_blocks, c->blocks.data(), c->blocks.size() * sizeof(BlockDev), hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemcpy(c->d_tiles, c->tiles.data(), c->tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemset(c->d_delays, 0, dcount) != hipSuccess)
-    return fail_free(ATNS_EHIP, "table upload failed");
-  *out = c;
-  return ATNS_OK;
+    const size_t dcount = (size_t)c->nb * kNumSlots;
+    if (hipMalloc((void**)&c->d_blocks, c->blocks.size() * sizeof(BlockDev)) != hipSuccess ||
+        hipMalloc((void**)&c->d_tiles, c->tiles.size() * sizeof(TileDev)) != hipSuccess ||
+        hipMalloc((void**)&c->d_delays, dcount) != hipSuccess || hipMalloc((void**)&c->d_probe, dcount) != hipSuccess ||
+        hipMalloc((void**)&c->d_partials, (size_t)c->nparts * 7 * sizeof(double)) != hipSuccess ||
+        hipMalloc((void**)&c->d_diag, 7 * sizeof(double)) != hipSuccess)
+      return fail_free(ATNS_ENOMEM, "table allocation failed");
+    if (hipMemcpy(c->d_blocks, c->blocks.data(), c->blocks.size() * sizeof(BlockDev), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(c->d_tiles, c->tiles.data(), c->tiles.size() * sizeof(TileDev), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemset(c->d_delays, 0, dcount) != hipSuccess)
+      return fail_free(ATNS_EHIP, "table upload failed");
+    *out = c;
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_destroy(atns_ctx* ctx) {
-  if (!ctx) return ATNS_OK;
-  (void)hipStreamSynchronize(ctx->stream);
-  release(ctx);
-  delete ctx;
-  return ATNS_OK;
+  return guarded(ctx, [&]() -> atns_status {
+    if (!ctx) return ATNS_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx);
+    delete ctx;
+    return ATNS_OK;
+  });
 }
 
 }  // extern "C"
@@ -1032,196 +1069,222 @@ const char kCkptMagic[8] = {'A', 'T', 'N', 'S', 'C', 'K', 'P', '1'};
 extern "C" {
 
 atns_status atns_set_state(atns_ctx* c, const void* dev_U, int64_t step) {
-  if (!c || !dev_U) return fail(c, ATNS_EINVAL, "null argument");
-  if (step < 0) return fail(c, ATNS_EINVAL, "negative step");
-  HIP_TRY(c, hipMemcpyAsync(state_ptr(c), dev_U, (size_t)c->field * 5 * c->esz, hipMemcpyDeviceToDevice,
-                            c->stream));
-  return adopt_state(c, step);
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !dev_U) return fail(c, ATNS_EINVAL, "null argument");
+    if (step < 0) return fail(c, ATNS_EINVAL, "negative step");
+    HIP_TRY(c, hipMemcpyAsync(state_ptr(c), dev_U, (size_t)c->field * 5 * c->esz, hipMemcpyDeviceToDevice,
+                              c->stream));
+    return adopt_state(c, step);
+  });
 }
 
 atns_status atns_init_case(atns_ctx* c, int32_t case_id, const double* params, int32_t np, int64_t step) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  if (step < 0) return fail(c, ATNS_EINVAL, "negative step");
-  if (np < 0 || (np > 0 && !params)) return fail(c, ATNS_EINVAL, "bad parameter list");
-  // vortex parameters, in order, with their defaults: t, beta, mach, xc, yc
-  double vp[5] = {0.0, 5.0, 0.5, 5.0, 5.0};
-  if (case_id == ATNS_CASE_VORTEX) {
-    if (np > 5) return fail(c, ATNS_EINVAL, "the vortex takes at most 5 parameters");
-    for (int i = 0; i < np; ++i) vp[i] = params[i];
-  } else if (case_id == ATNS_CASE_TGV) {
-    if (np != 0) return fail(c, ATNS_EINVAL, "the Taylor-Green case takes no parameters");
-    if (c->cfg.ndim != 3) return fail(c, ATNS_EINVAL, "the Taylor-Green case is three-dimensional");
-    vp[2] = c->cfg.mach;
-  } else {
-    return fail(c, ATNS_EINVAL, "unknown case");
-  }
-  const int kind = case_id == ATNS_CASE_VORTEX ? 0 : 1;
-  const hipError_t e =
-      c->esz == 4 ? launch_init_case<float>((float*)state_ptr(c), c->n, c->h, c->cfg.len, kind, c->cfg.ndim,
-                                            c->cfg.gamma, vp[2], vp[1], vp[0], vp[3], vp[4], c->stream)
-                  : launch_init_case<double>((double*)state_ptr(c), c->n, c->h, c->cfg.len, kind, c->cfg.ndim,
-                                             c->cfg.gamma, vp[2], vp[1], vp[0], vp[3], vp[4], c->stream);
-  if (e != hipSuccess) return fail(c, ATNS_EHIP, std::string("init_case: ") + hipGetErrorString(e));
-  return adopt_state(c, step);
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    if (step < 0) return fail(c, ATNS_EINVAL, "negative step");
+    if (np < 0 || (np > 0 && !params)) return fail(c, ATNS_EINVAL, "bad parameter list");
+    // vortex parameters, in order, with their defaults: t, beta, mach, xc, yc
+    double vp[5] = {0.0, 5.0, 0.5, 5.0, 5.0};
+    if (case_id == ATNS_CASE_VORTEX) {
+      if (np > 5) return fail(c, ATNS_EINVAL, "the vortex takes at most 5 parameters");
+      for (int i = 0; i < np; ++i) vp[i] = params[i];
+    } else if (case_id == ATNS_CASE_TGV) {
+      if (np != 0) return fail(c, ATNS_EINVAL, "the Taylor-Green case takes no parameters");
+      if (c->cfg.ndim != 3) return fail(c, ATNS_EINVAL, "the Taylor-Green case is three-dimensional");
+      vp[2] = c->cfg.mach;
+    } else {
+      return fail(c, ATNS_EINVAL, "unknown case");
+    }
+    const int kind = case_id == ATNS_CASE_VORTEX ? 0 : 1;
+    const hipError_t e =
+        c->esz == 4 ? launch_init_case<float>((float*)state_ptr(c), c->n, c->h, c->cfg.len, kind, c->cfg.ndim,
+                                              c->cfg.gamma, vp[2], vp[1], vp[0], vp[3], vp[4], c->stream)
+                    : launch_init_case<double>((double*)state_ptr(c), c->n, c->h, c->cfg.len, kind, c->cfg.ndim,
+                                               c->cfg.gamma, vp[2], vp[1], vp[0], vp[3], vp[4], c->stream);
+    if (e != hipSuccess) return fail(c, ATNS_EHIP, std::string("init_case: ") + hipGetErrorString(e));
+    return adopt_state(c, step);
+  });
 }
 
 atns_status atns_checkpoint(atns_ctx* c, void* host_blob, size_t* bytes) {
-  if (!c || !bytes) return fail(c, ATNS_EINVAL, "null argument");
-  const size_t sb = (size_t)c->field * 5 * c->esz;
-  const size_t rb = c->ring ? (size_t)c->slot_stride * c->D * c->esz : 0;
-  const size_t need = sizeof(CkptHeader) + sb + rb;
-  if (!host_blob) {
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !bytes) return fail(c, ATNS_EINVAL, "null argument");
+    const size_t sb = (size_t)c->field * 5 * c->esz;
+    const size_t rb = c->ring ? (size_t)c->slot_stride * c->D * c->esz : 0;
+    const size_t need = sizeof(CkptHeader) + sb + rb;
+    if (!host_blob) {
+      *bytes = need;
+      return ATNS_OK;
+    }
+    if (*bytes < need) return fail(c, ATNS_EINVAL, "checkpoint buffer too small");
+    if (!c->state_set) return fail(c, ATNS_ESTATE, "no state to checkpoint");
+    CkptHeader h;
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.fingerprint = config_fingerprint(c);
+    h.step = c->step;
+    h.dt = c->dt;
+    h.state_bytes = sb;
+    h.ring_bytes = rb;
+    char* out = (char*)host_blob;
+    std::memcpy(out, &h, sizeof h);
+    HIP_TRY(c, hipMemcpyAsync(out + sizeof h, state_ptr(c), sb, hipMemcpyDeviceToHost, c->stream));
+    if (rb) HIP_TRY(c, hipMemcpyAsync(out + sizeof h + sb, c->ring, rb, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     *bytes = need;
     return ATNS_OK;
-  }
-  if (*bytes < need) return fail(c, ATNS_EINVAL, "checkpoint buffer too small");
-  if (!c->state_set) return fail(c, ATNS_ESTATE, "no state to checkpoint");
-  CkptHeader h;
-  std::memcpy(h.magic, kCkptMagic, 8);
-  h.fingerprint = config_fingerprint(c);
-  h.step = c->step;
-  h.dt = c->dt;
-  h.state_bytes = sb;
-  h.ring_bytes = rb;
-  char* out = (char*)host_blob;
-  std::memcpy(out, &h, sizeof h);
-  HIP_TRY(c, hipMemcpyAsync(out + sizeof h, state_ptr(c), sb, hipMemcpyDeviceToHost, c->stream));
-  if (rb) HIP_TRY(c, hipMemcpyAsync(out + sizeof h + sb, c->ring, rb, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  *bytes = need;
-  return ATNS_OK;
+  });
 }
 
 atns_status atns_restore(atns_ctx* c, const void* host_blob, size_t bytes) {
-  if (!c || !host_blob) return fail(c, ATNS_EINVAL, "null argument");
-  CkptHeader h;
-  if (bytes < sizeof h) return fail(c, ATNS_EINVAL, "not a restart record");
-  std::memcpy(&h, host_blob, sizeof h);
-  const size_t sb = (size_t)c->field * 5 * c->esz;
-  const size_t rb = c->ring ? (size_t)c->slot_stride * c->D * c->esz : 0;
-  if (std::memcmp(h.magic, kCkptMagic, 8) != 0) return fail(c, ATNS_EINVAL, "not a restart record");
-  if (h.fingerprint != config_fingerprint(c) || h.state_bytes != sb || h.ring_bytes != rb)
-    return fail(c, ATNS_EINVAL, "restart record of a different configuration");
-  if (bytes < sizeof h + sb + rb) return fail(c, ATNS_EINVAL, "truncated restart record");
-  const char* in = (const char*)host_blob;
-  HIP_TRY(c, hipMemcpyAsync(state_ptr(c), in + sizeof h, sb, hipMemcpyHostToDevice, c->stream));
-  if (rb) HIP_TRY(c, hipMemcpyAsync(c->ring, in + sizeof h + sb, rb, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (h.dt > 0 && h.dt != c->dt) drop_graphs(c);
-  if (h.dt > 0) c->dt = h.dt;
-  c->step = h.step;
-  c->state_set = true;
-  c->nstep_synced = false;
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !host_blob) return fail(c, ATNS_EINVAL, "null argument");
+    CkptHeader h;
+    if (bytes < sizeof h) return fail(c, ATNS_EINVAL, "not a restart record");
+    std::memcpy(&h, host_blob, sizeof h);
+    const size_t sb = (size_t)c->field * 5 * c->esz;
+    const size_t rb = c->ring ? (size_t)c->slot_stride * c->D * c->esz : 0;
+    if (std::memcmp(h.magic, kCkptMagic, 8) != 0) return fail(c, ATNS_EINVAL, "not a restart record");
+    if (h.fingerprint != config_fingerprint(c) || h.state_bytes != sb || h.ring_bytes != rb)
+      return fail(c, ATNS_EINVAL, "restart record of a different configuration");
+    if (bytes < sizeof h + sb + rb) return fail(c, ATNS_EINVAL, "truncated restart record");
+    const char* in = (const char*)host_blob;
+    HIP_TRY(c, hipMemcpyAsync(state_ptr(c), in + sizeof h, sb, hipMemcpyHostToDevice, c->stream));
+    if (rb) HIP_TRY(c, hipMemcpyAsync(c->ring, in + sizeof h + sb, rb, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (h.dt > 0 && h.dt != c->dt) drop_graphs(c);
+    if (h.dt > 0) c->dt = h.dt;
+    c->step = h.step;
+    c->state_set = true;
+    c->nstep_synced = false;
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_get_state(const atns_ctx* c, void* dst, int32_t on_host) {
-  if (!c || !dst) return fail(const_cast<atns_ctx*>(c), ATNS_EINVAL, "null argument");
-  atns_ctx* m = const_cast<atns_ctx*>(c);
-  const size_t bytes = (size_t)c->field * 5 * c->esz;
-  if (on_host) {
-    HIP_TRY(m, hipMemcpyAsync(dst, state_ptr(c), bytes, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(m, hipStreamSynchronize(c->stream));
-  } else {
-    HIP_TRY(m, hipMemcpyAsync(dst, state_ptr(c), bytes, hipMemcpyDeviceToDevice, c->stream));
-  }
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !dst) return fail(const_cast<atns_ctx*>(c), ATNS_EINVAL, "null argument");
+    atns_ctx* m = const_cast<atns_ctx*>(c);
+    const size_t bytes = (size_t)c->field * 5 * c->esz;
+    if (on_host) {
+      HIP_TRY(m, hipMemcpyAsync(dst, state_ptr(c), bytes, hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(m, hipStreamSynchronize(c->stream));
+    } else {
+      HIP_TRY(m, hipMemcpyAsync(dst, state_ptr(c), bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_get_step(const atns_ctx* c, int64_t* step) {
-  if (!c || !step) return fail(const_cast<atns_ctx*>(c), ATNS_EINVAL, "null argument");
-  *step = c->step;
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !step) return fail(const_cast<atns_ctx*>(c), ATNS_EINVAL, "null argument");
+    *step = c->step;
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_set_dt(atns_ctx* c, double dt) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  if (!(dt > 0) || !std::isfinite(dt)) return fail(c, ATNS_EINVAL, "dt must be positive and finite");
-  if (dt != c->dt) drop_graphs(c);
-  c->dt = dt;
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, ATNS_EINVAL, "dt must be positive and finite");
+    if (dt != c->dt) drop_graphs(c);
+    c->dt = dt;
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_set_delays(atns_ctx* c, int64_t step0, int32_t nsteps, const int8_t* host_k) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  if (nsteps < 0 || (nsteps > 0 && !host_k)) return fail(c, ATNS_EINVAL, "bad delay injection");
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (c->d_inject) {
-    HIP_TRY(c, hipFree(c->d_inject));
-    c->d_inject = nullptr;
-  }
-  c->inject_n = 0;
-  if (nsteps == 0) return ATNS_OK;
-  const size_t bytes = (size_t)nsteps * c->nb * kNumSlots;
-  if (hipMalloc((void**)&c->d_inject, bytes) != hipSuccess) return fail(c, ATNS_ENOMEM, "inject allocation");
-  HIP_TRY(c, hipMemcpy(c->d_inject, host_k, bytes, hipMemcpyHostToDevice));
-  c->inject0 = step0;
-  c->inject_n = nsteps;
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    if (nsteps < 0 || (nsteps > 0 && !host_k)) return fail(c, ATNS_EINVAL, "bad delay injection");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->d_inject) {
+      HIP_TRY(c, hipFree(c->d_inject));
+      c->d_inject = nullptr;
+    }
+    c->inject_n = 0;
+    if (nsteps == 0) return ATNS_OK;
+    const size_t bytes = (size_t)nsteps * c->nb * kNumSlots;
+    if (hipMalloc((void**)&c->d_inject, bytes) != hipSuccess) return fail(c, ATNS_ENOMEM, "inject allocation");
+    HIP_TRY(c, hipMemcpy(c->d_inject, host_k, bytes, hipMemcpyHostToDevice));
+    c->inject0 = step0;
+    c->inject_n = nsteps;
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_get_delays(atns_ctx* c, int64_t step, int8_t* host_k, int32_t* synchronous) {
-  if (!c || !host_k) return fail(c, ATNS_EINVAL, "null argument");
-  const size_t cnt = (size_t)c->nb * kNumSlots;
-  if (!is_async(c, step)) {
-    std::memset(host_k, 0, cnt);
-    if (synchronous) *synchronous = 1;
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !host_k) return fail(c, ATNS_EINVAL, "null argument");
+    const size_t cnt = (size_t)c->nb * kNumSlots;
+    if (!is_async(c, step)) {
+      std::memset(host_k, 0, cnt);
+      if (synchronous) *synchronous = 1;
+      return ATNS_OK;
+    }
+    atns_status st = draw_delays(c, step, c->d_probe);
+    if (st != ATNS_OK) return st;
+    HIP_TRY(c, hipMemcpyAsync(host_k, c->d_probe, cnt, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (synchronous) *synchronous = 0;
     return ATNS_OK;
-  }
-  atns_status st = draw_delays(c, step, c->d_probe);
-  if (st != ATNS_OK) return st;
-  HIP_TRY(c, hipMemcpyAsync(host_k, c->d_probe, cnt, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (synchronous) *synchronous = 0;
-  return ATNS_OK;
+  });
 }
 
 atns_status atns_rhs(atns_ctx* c, int32_t stage, void* dev_R) {
-  if (!c || !dev_R) return fail(c, ATNS_EINVAL, "null argument");
-  if (stage < 0 || stage >= c->rk.stages) return fail(c, ATNS_EINVAL, "stage outside 0..s-1");
-  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
-  const bool async = is_async(c, c->step);
-  auto go = [&](auto tag) -> atns_status {
-    using T = decltype(tag);
-    if (async) {
-      atns_status st = prepare_halos<T>(c);
-      if (st != ATNS_OK) return st;
-    }
-    StageParams<T> p = base_params<T>(c);
-    p.halo = !async ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
-    p.slot_now = c->D ? (int)(c->step % c->D) : 0;
-    p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)stage * c->slot_stride : nullptr;
-    p.ring_write = 0;
-    p.Y = (const T*)state_ptr(c);
-    p.Yout = (T*)dev_R;
-    HIP_TRY(c, prof_begin(c, c->stream));
-    HIP_TRY(c, launch_stage<T>(c, p, kRhsOnly));
-    HIP_TRY(c, prof_end(c, c->stream, 1));
-    return ATNS_OK;
-  };
-  return c->esz == 4 ? go(float{}) : go(double{});
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !dev_R) return fail(c, ATNS_EINVAL, "null argument");
+    if (stage < 0 || stage >= c->rk.stages) return fail(c, ATNS_EINVAL, "stage outside 0..s-1");
+    if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+    const bool async = is_async(c, c->step);
+    auto go = [&](auto tag) -> atns_status {
+      using T = decltype(tag);
+      if (async) {
+        atns_status st = prepare_halos<T>(c);
+        if (st != ATNS_OK) return st;
+      }
+      StageParams<T> p = base_params<T>(c);
+      p.halo = !async ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
+      p.slot_now = c->D ? (int)(c->step % c->D) : 0;
+      p.hbuf = c->hbuf ? (const T*)c->hbuf + (size_t)stage * c->slot_stride : nullptr;
+      p.ring_write = 0;
+      p.Y = (const T*)state_ptr(c);
+      p.Yout = (T*)dev_R;
+      HIP_TRY(c, prof_begin(c, c->stream));
+      HIP_TRY(c, launch_stage<T>(c, p, kRhsOnly));
+      HIP_TRY(c, prof_end(c, c->stream, 1));
+      return ATNS_OK;
+    };
+    return c->esz == 4 ? go(float{}) : go(double{});
+  });
 }
 
 atns_status atns_set_fusion(atns_ctx* c, int32_t on) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  c->fuse = on != 0;
-  drop_graphs(c);
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    c->fuse = on != 0;
+    drop_graphs(c);
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_set_halo_fusion(atns_ctx* c, int32_t on) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  c->halo_fusion = on != 0;
-  drop_graphs(c);
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    c->halo_fusion = on != 0;
+    drop_graphs(c);
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_rk_step(atns_ctx* c, int32_t nsteps) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  if (nsteps < 0) return fail(c, ATNS_EINVAL, "negative step count");
-  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
-  if (!(c->dt > 0)) return fail(c, ATNS_ESTATE, "dt not set");
-  return c->esz == 4 ? do_steps<float>(c, nsteps) : do_steps<double>(c, nsteps);
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    if (nsteps < 0) return fail(c, ATNS_EINVAL, "negative step count");
+    if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+    if (!(c->dt > 0)) return fail(c, ATNS_ESTATE, "dt not set");
+    return c->esz == 4 ? do_steps<float>(c, nsteps) : do_steps<double>(c, nsteps);
+  });
 }
 
 }  // extern "C"
@@ -1347,132 +1410,150 @@ atns_status step_async_impl(atns_ctx* c, int nsteps, long long spin_limit, int8_
 extern "C" {
 
 atns_status atns_step_async(atns_ctx* c, int32_t nsteps, int64_t spin_limit, int8_t* dev_log) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  if (nsteps < 0 || (nsteps > 0 && !dev_log) || spin_limit < 1)
-    return fail(c, ATNS_EINVAL, "need nsteps >= 0, a delay log for nsteps > 0 and spin_limit >= 1");
-  if (c->cfg.physics == ATNS_NS && c->cfg.ndim != 3)
-    return fail(c, ATNS_EINVAL, "free-running Navier-Stokes steps are built for 3-D contexts");
-  if (c->cfg.mode == ATNS_SA) return fail(c, ATNS_EINVAL, "free-running steps need mode ATNS_AT or ATNS_AS");
-  if (c->rk.stages != 4 && c->rk.stages != 2)
-    return fail(c, ATNS_EINVAL, "free-running steps need ATNS_RK4 or ATNS_LSERK2");
-  if (c->mlp_on) return fail(c, ATNS_EINVAL, "the learned halo is not applied in free-running steps");
-  if (c->cfg.filter) return fail(c, ATNS_EINVAL, "the filter is not applied in free-running steps");
-  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
-  if (!(c->dt > 0)) return fail(c, ATNS_ESTATE, "dt not set");
-  if (c->step < c->C + c->cfg.L - 1) return fail(c, ATNS_ESTATE, "history shorter than C + L - 1 levels");
-  if (nsteps == 0) return ATNS_OK;
-  return c->esz == 4 ? step_async_impl<float>(c, nsteps, spin_limit, dev_log)
-                     : step_async_impl<double>(c, nsteps, spin_limit, dev_log);
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    if (nsteps < 0 || (nsteps > 0 && !dev_log) || spin_limit < 1)
+      return fail(c, ATNS_EINVAL, "need nsteps >= 0, a delay log for nsteps > 0 and spin_limit >= 1");
+    if (c->cfg.physics == ATNS_NS && c->cfg.ndim != 3)
+      return fail(c, ATNS_EINVAL, "free-running Navier-Stokes steps are built for 3-D contexts");
+    if (c->cfg.mode == ATNS_SA) return fail(c, ATNS_EINVAL, "free-running steps need mode ATNS_AT or ATNS_AS");
+    if (c->rk.stages != 4 && c->rk.stages != 2)
+      return fail(c, ATNS_EINVAL, "free-running steps need ATNS_RK4 or ATNS_LSERK2");
+    if (c->mlp_on) return fail(c, ATNS_EINVAL, "the learned halo is not applied in free-running steps");
+    if (c->cfg.filter) return fail(c, ATNS_EINVAL, "the filter is not applied in free-running steps");
+    if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+    if (!(c->dt > 0)) return fail(c, ATNS_ESTATE, "dt not set");
+    if (c->step < c->C + c->cfg.L - 1) return fail(c, ATNS_ESTATE, "history shorter than C + L - 1 levels");
+    if (nsteps == 0) return ATNS_OK;
+    return c->esz == 4 ? step_async_impl<float>(c, nsteps, spin_limit, dev_log)
+                       : step_async_impl<double>(c, nsteps, spin_limit, dev_log);
+  });
 }
 
 atns_status atns_reduce(atns_ctx* c, double* host_out) {
-  if (!c || !host_out) return fail(c, ATNS_EINVAL, "null argument");
-  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
-  // the reduction kernel indexes the five fields with 32-bit offsets
-  if (5 * c->field >= (1ll << 31)) return fail(c, ATNS_EINVAL, "grid too large for the reduction (5 n^3 >= 2^31)");
-  double inv12h[3];
-  for (int d = 0; d < 3; ++d) inv12h[d] = 1.0 / (12.0 * c->h[d]);
-  const double dV = c->h[0] * c->h[1] * (c->cfg.ndim == 3 ? c->h[2] : c->cfg.len[2]);
-  if (c->esz == 4) {
-    HIP_TRY(c, launch_diag<float>((const float*)state_ptr(c), c->n, c->cfg.ndim, inv12h, dV, c->d_partials,
-                                  c->nparts, c->d_diag, c->stream));
-  } else {
-    HIP_TRY(c, launch_diag<double>((const double*)state_ptr(c), c->n, c->cfg.ndim, inv12h, dV, c->d_partials,
-                                   c->nparts, c->d_diag, c->stream));
-  }
-  HIP_TRY(c, hipMemcpyAsync(host_out, c->d_diag, 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  for (int i = 0; i < 7; ++i)
-    if (!std::isfinite(host_out[i])) return fail(c, ATNS_ENONFINITE, "non-finite diagnostic");
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !host_out) return fail(c, ATNS_EINVAL, "null argument");
+    if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+    // the reduction kernel indexes the five fields with 32-bit offsets
+    if (5 * c->field >= (1ll << 31)) return fail(c, ATNS_EINVAL, "grid too large for the reduction (5 n^3 >= 2^31)");
+    double inv12h[3];
+    for (int d = 0; d < 3; ++d) inv12h[d] = 1.0 / (12.0 * c->h[d]);
+    const double dV = c->h[0] * c->h[1] * (c->cfg.ndim == 3 ? c->h[2] : c->cfg.len[2]);
+    if (c->esz == 4) {
+      HIP_TRY(c, launch_diag<float>((const float*)state_ptr(c), c->n, c->cfg.ndim, inv12h, dV, c->d_partials,
+                                    c->nparts, c->d_diag, c->stream));
+    } else {
+      HIP_TRY(c, launch_diag<double>((const double*)state_ptr(c), c->n, c->cfg.ndim, inv12h, dV, c->d_partials,
+                                     c->nparts, c->d_diag, c->stream));
+    }
+    HIP_TRY(c, hipMemcpyAsync(host_out, c->d_diag, 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 7; ++i)
+      if (!std::isfinite(host_out[i])) return fail(c, ATNS_ENONFINITE, "non-finite diagnostic");
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_reduce_noalloc(const void* dev_U, int32_t precision, int32_t ndim, const int32_t* n,
                                 const double* len, double* dev_out, void* stream) {
-  if (!dev_U || !n || !len || !dev_out) return fail(nullptr, ATNS_EINVAL, "null argument");
-  if (precision != ATNS_F32 && precision != ATNS_F64) return fail(nullptr, ATNS_EINVAL, "bad precision");
-  if (ndim != 2 && ndim != 3) return fail(nullptr, ATNS_EINVAL, "ndim must be 2 or 3");
-  if (ndim == 2 && n[2] != 1) return fail(nullptr, ATNS_EINVAL, "2D needs nz == 1");
-  for (int d = 0; d < 3; ++d) {
-    if (n[d] < 1 || !(len[d] > 0)) return fail(nullptr, ATNS_EINVAL, "bad grid or box length");
-    if (d < ndim && n[d] < 5) return fail(nullptr, ATNS_EINVAL, "the CD4 vorticity needs 5 points per axis");
-  }
-  if (5.0 * n[0] * n[1] * n[2] >= 2147483648.0)
-    return fail(nullptr, ATNS_EINVAL, "grid too large for the reduction (5 nx ny nz >= 2^31)");
-  double inv12h[3], h[3];
-  for (int d = 0; d < 3; ++d) {
-    h[d] = len[d] / n[d];
-    inv12h[d] = 1.0 / (12.0 * h[d]);
-  }
-  const double dV = h[0] * h[1] * (ndim == 3 ? h[2] : len[2]);
-  const int nn[3] = {n[0], n[1], n[2]};
-  const hipError_t e =
-      precision == ATNS_F32
-          ? launch_diag_noalloc<float>((const float*)dev_U, nn, ndim, inv12h, dV, dev_out, (hipStream_t)stream)
-          : launch_diag_noalloc<double>((const double*)dev_U, nn, ndim, inv12h, dV, dev_out, (hipStream_t)stream);
-  if (e != hipSuccess) return fail(nullptr, ATNS_EHIP, std::string("atns_reduce_noalloc: ") + hipGetErrorString(e));
-  return ATNS_OK;
+  return guarded(nullptr, [&]() -> atns_status {
+    if (!dev_U || !n || !len || !dev_out) return fail(nullptr, ATNS_EINVAL, "null argument");
+    if (precision != ATNS_F32 && precision != ATNS_F64) return fail(nullptr, ATNS_EINVAL, "bad precision");
+    if (ndim != 2 && ndim != 3) return fail(nullptr, ATNS_EINVAL, "ndim must be 2 or 3");
+    if (ndim == 2 && n[2] != 1) return fail(nullptr, ATNS_EINVAL, "2D needs nz == 1");
+    for (int d = 0; d < 3; ++d) {
+      if (n[d] < 1 || !(len[d] > 0)) return fail(nullptr, ATNS_EINVAL, "bad grid or box length");
+      if (d < ndim && n[d] < 5) return fail(nullptr, ATNS_EINVAL, "the CD4 vorticity needs 5 points per axis");
+    }
+    if (5.0 * n[0] * n[1] * n[2] >= 2147483648.0)
+      return fail(nullptr, ATNS_EINVAL, "grid too large for the reduction (5 nx ny nz >= 2^31)");
+    double inv12h[3], h[3];
+    for (int d = 0; d < 3; ++d) {
+      h[d] = len[d] / n[d];
+      inv12h[d] = 1.0 / (12.0 * h[d]);
+    }
+    const double dV = h[0] * h[1] * (ndim == 3 ? h[2] : len[2]);
+    const int nn[3] = {n[0], n[1], n[2]};
+    const hipError_t e =
+        precision == ATNS_F32
+            ? launch_diag_noalloc<float>((const float*)dev_U, nn, ndim, inv12h, dV, dev_out, (hipStream_t)stream)
+            : launch_diag_noalloc<double>((const double*)dev_U, nn, ndim, inv12h, dV, dev_out, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, ATNS_EHIP, std::string("atns_reduce_noalloc: ") + hipGetErrorString(e));
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_get_layout(const atns_ctx* c, int32_t* nblocks, int32_t* ring_depth) {
-  if (!c) return fail(nullptr, ATNS_EINVAL, "null context");
-  if (nblocks) *nblocks = c->nb;
-  if (ring_depth) *ring_depth = c->D;
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(nullptr, ATNS_EINVAL, "null context");
+    if (nblocks) *nblocks = c->nb;
+    if (ring_depth) *ring_depth = c->D;
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_set_graphs(atns_ctx* c, int32_t on) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  HIP_TRY(c, hipDeviceSynchronize());
-  c->use_graph = on != 0;
-  if (!c->use_graph) drop_graphs(c);
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    HIP_TRY(c, hipDeviceSynchronize());
+    c->use_graph = on != 0;
+    if (!c->use_graph) drop_graphs(c);
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_profile_enable(atns_ctx* c, int32_t on) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->profiling = on != 0;
-  c->ev_used = 0;
-  c->ev_launches.clear();
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->profiling = on != 0;
+    c->ev_used = 0;
+    c->ev_launches.clear();
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_profile_read(atns_ctx* c, int64_t* launches, double* total_ms) {
-  if (!c || !launches || !total_ms) return fail(c, ATNS_EINVAL, "null argument");
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  double tot = 0.0;
-  int64_t n = 0;
-  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
-    float ms = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]));
-    tot += ms;
-    n += c->ev_launches[i / 2];
-  }
-  *launches = n;
-  *total_ms = tot;
-  c->ev_used = 0;
-  c->ev_launches.clear();
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !launches || !total_ms) return fail(c, ATNS_EINVAL, "null argument");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    int64_t n = 0;
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+      float ms = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]));
+      tot += ms;
+      n += c->ev_launches[i / 2];
+    }
+    *launches = n;
+    *total_ms = tot;
+    c->ev_used = 0;
+    c->ev_launches.clear();
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_set_tiles(atns_ctx* c, int32_t tx, int32_t ty, int32_t tz) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  if (!shape_supported(c->cfg.physics, c->esz, tx, ty) || tz < 1 || tz > 32767)
-    return fail(c, ATNS_EINVAL, "unsupported tile shape");
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->tile[0] = tx;
-  c->tile[1] = ty;
-  c->tile[2] = c->cfg.ndim == 2 ? 1 : tz;
-  return upload_tiles(c);
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    if (!shape_supported(c->cfg.physics, c->esz, tx, ty) || tz < 1 || tz > 32767)
+      return fail(c, ATNS_EINVAL, "unsupported tile shape");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->tile[0] = tx;
+    c->tile[1] = ty;
+    c->tile[2] = c->cfg.ndim == 2 ? 1 : tz;
+    return upload_tiles(c);
+  });
 }
 
 atns_status atns_get_tiles(const atns_ctx* c, int32_t* tx, int32_t* ty, int32_t* tz) {
-  if (!c || !tx || !ty || !tz) return fail(const_cast<atns_ctx*>(c), ATNS_EINVAL, "null argument");
-  *tx = c->tile[0];
-  *ty = c->tile[1];
-  *tz = c->tile[2];
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !tx || !ty || !tz) return fail(const_cast<atns_ctx*>(c), ATNS_EINVAL, "null argument");
+    *tx = c->tile[0];
+    *ty = c->tile[1];
+    *tz = c->tile[2];
+    return ATNS_OK;
+  });
 }
 
 }  // extern "C"
@@ -1605,48 +1686,50 @@ atns_status time_shape(atns_ctx* c, int reps, float* ms_out) {
 extern "C" {
 
 atns_status atns_autotune(atns_ctx* c, int32_t reps, const char* cache_path, int32_t* best) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
-  if (reps < 1) return fail(c, ATNS_EINVAL, "reps must be positive");
-  const std::string key = tune_key(c);
-  int pick[3];
-  // entries naming a shape the library does not provide are ignored
-  const bool cached = cache_lookup(cache_path, key, pick) && shape_supported(c->cfg.physics, c->esz, pick[0], pick[1]) &&
-                      pick[2] >= 1 && pick[2] <= 32767;
-  if (!cached) {
-    const bool ns = c->cfg.physics == ATNS_NS;
-    const int tzs[] = {4, 8, 16, 32};
-    float best_ms = 1e30f;
-    pick[0] = c->tile[0];
-    pick[1] = c->tile[1];
-    pick[2] = c->tile[2];
-    for (int i = 0; i < num_shapes(c->cfg.physics, c->esz); ++i)
-      for (int tz : tzs) {
-        if (c->cfg.ndim == 2 && tz != 4) continue;
-        if (ns && tz < 8) continue;   // 8 extra planes per column: short ones waste work
-        const int tx = shape_at(c->cfg.physics, i)[0], ty = shape_at(c->cfg.physics, i)[1];
-        atns_status st = atns_set_tiles(c, tx, ty, tz);
-        if (st != ATNS_OK) return st;
-        float ms = 0.f;
-        st = c->esz == 4 ? time_shape<float>(c, reps, &ms) : time_shape<double>(c, reps, &ms);
-        if (st != ATNS_OK) return st;
-        if (ms < best_ms) {
-          best_ms = ms;
-          pick[0] = tx;
-          pick[1] = ty;
-          pick[2] = c->tile[2];
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+    if (reps < 1) return fail(c, ATNS_EINVAL, "reps must be positive");
+    const std::string key = tune_key(c);
+    int pick[3];
+    // entries naming a shape the library does not provide are ignored
+    const bool cached = cache_lookup(cache_path, key, pick) && shape_supported(c->cfg.physics, c->esz, pick[0], pick[1]) &&
+                        pick[2] >= 1 && pick[2] <= 32767;
+    if (!cached) {
+      const bool ns = c->cfg.physics == ATNS_NS;
+      const int tzs[] = {4, 8, 16, 32};
+      float best_ms = 1e30f;
+      pick[0] = c->tile[0];
+      pick[1] = c->tile[1];
+      pick[2] = c->tile[2];
+      for (int i = 0; i < num_shapes(c->cfg.physics, c->esz); ++i)
+        for (int tz : tzs) {
+          if (c->cfg.ndim == 2 && tz != 4) continue;
+          if (ns && tz < 8) continue;   // 8 extra planes per column: short ones waste work
+          const int tx = shape_at(c->cfg.physics, i)[0], ty = shape_at(c->cfg.physics, i)[1];
+          atns_status st = atns_set_tiles(c, tx, ty, tz);
+          if (st != ATNS_OK) return st;
+          float ms = 0.f;
+          st = c->esz == 4 ? time_shape<float>(c, reps, &ms) : time_shape<double>(c, reps, &ms);
+          if (st != ATNS_OK) return st;
+          if (ms < best_ms) {
+            best_ms = ms;
+            pick[0] = tx;
+            pick[1] = ty;
+            pick[2] = c->tile[2];
+          }
         }
-      }
-    cache_store(cache_path, key, pick);
-  }
-  atns_status st = atns_set_tiles(c, pick[0], pick[1], pick[2]);
-  if (st != ATNS_OK) return st;
-  if (best) {
-    best[0] = pick[0];
-    best[1] = pick[1];
-    best[2] = pick[2];
-  }
-  return ATNS_OK;
+      cache_store(cache_path, key, pick);
+    }
+    atns_status st = atns_set_tiles(c, pick[0], pick[1], pick[2]);
+    if (st != ATNS_OK) return st;
+    if (best) {
+      best[0] = pick[0];
+      best[1] = pick[1];
+      best[2] = pick[2];
+    }
+    return ATNS_OK;
+  });
 }
 
 namespace {
@@ -1711,165 +1794,193 @@ atns_status sample_into(atns_ctx* c, int n, uint64_t seed, float* X, float* Y) {
 }  // namespace
 
 atns_status atns_mlp_set_params(atns_ctx* c, const float* host_params) {
-  if (!c || !host_params) return fail(c, ATNS_EINVAL, "null argument");
-  atns_status st = mlp_alloc(c);
-  if (st != ATNS_OK) return st;
-  HIP_TRY(c, hipMemcpyAsync(c->net.params, host_params, kMlpParams * sizeof(float), hipMemcpyHostToDevice,
-                            c->stream));
-  HIP_TRY(c, mlp_pack(c->net, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->d_adam_m, 0, kMlpParams * sizeof(float), c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->d_adam_v, 0, kMlpParams * sizeof(float), c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->adam_t = 0;
-  c->mlp_ready = true;
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !host_params) return fail(c, ATNS_EINVAL, "null argument");
+    atns_status st = mlp_alloc(c);
+    if (st != ATNS_OK) return st;
+    HIP_TRY(c, hipMemcpyAsync(c->net.params, host_params, kMlpParams * sizeof(float), hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, mlp_pack(c->net, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_adam_m, 0, kMlpParams * sizeof(float), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_adam_v, 0, kMlpParams * sizeof(float), c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->adam_t = 0;
+    c->mlp_ready = true;
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_mlp_get_params(atns_ctx* c, float* host_params) {
-  atns_status st = mlp_need(c);
-  if (st != ATNS_OK) return st;
-  if (!host_params) return fail(c, ATNS_EINVAL, "null argument");
-  HIP_TRY(c, hipMemcpyAsync(host_params, c->net.params, kMlpParams * sizeof(float), hipMemcpyDeviceToHost,
-                            c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    atns_status st = mlp_need(c);
+    if (st != ATNS_OK) return st;
+    if (!host_params) return fail(c, ATNS_EINVAL, "null argument");
+    HIP_TRY(c, hipMemcpyAsync(host_params, c->net.params, kMlpParams * sizeof(float), hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_mlp_set_scales(atns_ctx* c, const float* feat_scale, const float* targ_scale) {
-  if (!c || !feat_scale || !targ_scale) return fail(c, ATNS_EINVAL, "null argument");
-  for (int v = 0; v < 5; ++v)
-    if (!(feat_scale[v] > 0) || !(targ_scale[v] > 0) || !std::isfinite(feat_scale[v]) ||
-        !std::isfinite(targ_scale[v]))
-      return fail(c, ATNS_EINVAL, "scales must be positive and finite");
-  for (int v = 0; v < 5; ++v) {
-    c->mlp_s[v] = feat_scale[v];
-    c->mlp_r[v] = targ_scale[v];
-  }
-  drop_graphs(c);
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !feat_scale || !targ_scale) return fail(c, ATNS_EINVAL, "null argument");
+    for (int v = 0; v < 5; ++v)
+      if (!(feat_scale[v] > 0) || !(targ_scale[v] > 0) || !std::isfinite(feat_scale[v]) ||
+          !std::isfinite(targ_scale[v]))
+        return fail(c, ATNS_EINVAL, "scales must be positive and finite");
+    for (int v = 0; v < 5; ++v) {
+      c->mlp_s[v] = feat_scale[v];
+      c->mlp_r[v] = targ_scale[v];
+    }
+    drop_graphs(c);
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_mlp_forward(atns_ctx* c, const float* dev_X, int32_t n, float* dev_out) {
-  atns_status st = mlp_need(c);
-  if (st != ATNS_OK) return st;
-  if (!dev_X || !dev_out || n < 1) return fail(c, ATNS_EINVAL, "bad forward arguments");
-  HIP_TRY(c, mlp_forward(c->net, dev_X, n, dev_out, c->stream));
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    atns_status st = mlp_need(c);
+    if (st != ATNS_OK) return st;
+    if (!dev_X || !dev_out || n < 1) return fail(c, ATNS_EINVAL, "bad forward arguments");
+    HIP_TRY(c, mlp_forward(c->net, dev_X, n, dev_out, c->stream));
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_mlp_grad(atns_ctx* c, const float* dev_X, const float* dev_Y, int32_t n, float* dev_grad,
                           double* host_loss) {
-  atns_status st = mlp_need(c);
-  if (st != ATNS_OK) return st;
-  if (!dev_X || !dev_Y || !dev_grad || n < 1) return fail(c, ATNS_EINVAL, "bad gradient arguments");
-  st = mlp_batch(c, n);
-  if (st != ATNS_OK) return st;
-  HIP_TRY(c, mlp_grad(c->net, dev_X, dev_Y, n, c->d_part, c->d_loss_part, dev_grad, c->d_loss, c->stream));
-  if (host_loss) {
-    float l = 0.f;
-    HIP_TRY(c, hipMemcpyAsync(&l, c->d_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    *host_loss = l;
-  }
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    atns_status st = mlp_need(c);
+    if (st != ATNS_OK) return st;
+    if (!dev_X || !dev_Y || !dev_grad || n < 1) return fail(c, ATNS_EINVAL, "bad gradient arguments");
+    st = mlp_batch(c, n);
+    if (st != ATNS_OK) return st;
+    HIP_TRY(c, mlp_grad(c->net, dev_X, dev_Y, n, c->d_part, c->d_loss_part, dev_grad, c->d_loss, c->stream));
+    if (host_loss) {
+      float l = 0.f;
+      HIP_TRY(c, hipMemcpyAsync(&l, c->d_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      *host_loss = l;
+    }
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_mlp_sample(atns_ctx* c, int32_t n, uint64_t seed, float* dev_X, float* dev_Y) {
-  if (!c || !dev_X || !dev_Y || n < 1) return fail(c, ATNS_EINVAL, "bad sample arguments");
-  return sample_into(c, n, seed, dev_X, dev_Y);
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !dev_X || !dev_Y || n < 1) return fail(c, ATNS_EINVAL, "bad sample arguments");
+    return sample_into(c, n, seed, dev_X, dev_Y);
+  });
 }
 
 atns_status atns_mlp_train(atns_ctx* c, int32_t iters, int32_t batch, double lr, uint64_t seed, double* losses) {
-  atns_status st = mlp_need(c);
-  if (st != ATNS_OK) return st;
-  if (iters < 1 || batch < 64 || !(lr > 0)) return fail(c, ATNS_EINVAL, "bad training arguments");
-  st = mlp_batch(c, batch);
-  if (st != ATNS_OK) return st;
-  std::vector<float> lv(iters);
-  for (int i = 0; i < iters; ++i) {
-    st = sample_into(c, batch, seed + (uint64_t)i * 0x632BE59BD9B4E019ull, c->d_X, c->d_Y);
+  return guarded(c, [&]() -> atns_status {
+    atns_status st = mlp_need(c);
     if (st != ATNS_OK) return st;
-    HIP_TRY(c, mlp_grad(c->net, c->d_X, c->d_Y, batch, c->d_part, c->d_loss_part, c->d_grad, c->d_loss,
-                        c->stream));
-    if (losses) HIP_TRY(c, hipMemcpyAsync(&lv[i], c->d_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
-    c->adam_t += 1;
-    HIP_TRY(c, mlp_adam(c->net, c->d_adam_m, c->d_adam_v, c->d_grad, (float)lr, c->adam_t, c->stream));
-  }
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (losses)
-    for (int i = 0; i < iters; ++i) losses[i] = lv[i];
-  return ATNS_OK;
+    if (iters < 1 || batch < 64 || !(lr > 0)) return fail(c, ATNS_EINVAL, "bad training arguments");
+    st = mlp_batch(c, batch);
+    if (st != ATNS_OK) return st;
+    std::vector<float> lv(iters);
+    for (int i = 0; i < iters; ++i) {
+      st = sample_into(c, batch, seed + (uint64_t)i * 0x632BE59BD9B4E019ull, c->d_X, c->d_Y);
+      if (st != ATNS_OK) return st;
+      HIP_TRY(c, mlp_grad(c->net, c->d_X, c->d_Y, batch, c->d_part, c->d_loss_part, c->d_grad, c->d_loss,
+                          c->stream));
+      if (losses) HIP_TRY(c, hipMemcpyAsync(&lv[i], c->d_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+      c->adam_t += 1;
+      HIP_TRY(c, mlp_adam(c->net, c->d_adam_m, c->d_adam_v, c->d_grad, (float)lr, c->adam_t, c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (losses)
+      for (int i = 0; i < iters; ++i) losses[i] = lv[i];
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_mlp_enable(atns_ctx* c, int32_t on, double tau) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  if (on && !c->mlp_ready) return fail(c, ATNS_ESTATE, "MLP parameters not set");
-  if (on && c->cfg.mode != ATNS_AT) return fail(c, ATNS_EINVAL, "the learned halo needs mode ATNS_AT");
-  if (on && c->C != kMaxC) return fail(c, ATNS_EINVAL, "the learned halo works with AT4 (C = 5 levels)");
-  if (on && c->cfg.filter) return fail(c, ATNS_EINVAL, "the learned halo is not combined with the filter");
-  if (!(tau >= 0)) return fail(c, ATNS_EINVAL, "tau must be non-negative");
-  c->mlp_on = on != 0;
-  c->mlp_tau = tau;
-  drop_graphs(c);
-  return ATNS_OK;
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    if (on && !c->mlp_ready) return fail(c, ATNS_ESTATE, "MLP parameters not set");
+    if (on && c->cfg.mode != ATNS_AT) return fail(c, ATNS_EINVAL, "the learned halo needs mode ATNS_AT");
+    if (on && c->C != kMaxC) return fail(c, ATNS_EINVAL, "the learned halo works with AT4 (C = 5 levels)");
+    if (on && c->cfg.filter) return fail(c, ATNS_EINVAL, "the learned halo is not combined with the filter");
+    if (!(tau >= 0)) return fail(c, ATNS_EINVAL, "tau must be non-negative");
+    c->mlp_on = on != 0;
+    c->mlp_tau = tau;
+    drop_graphs(c);
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_mlp_stats(atns_ctx* c, int64_t* applied, int64_t* fallback) {
-  if (!c || !applied || !fallback) return fail(c, ATNS_EINVAL, "null argument");
-  if (!c->d_counters) {
-    *applied = *fallback = 0;
+  return guarded(c, [&]() -> atns_status {
+    if (!c || !applied || !fallback) return fail(c, ATNS_EINVAL, "null argument");
+    if (!c->d_counters) {
+      *applied = *fallback = 0;
+      return ATNS_OK;
+    }
+    unsigned long long h[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(h, c->d_counters, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_counters, 0, sizeof h, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    *applied = (int64_t)h[0];
+    *fallback = (int64_t)h[1];
     return ATNS_OK;
-  }
-  unsigned long long h[2] = {0, 0};
-  HIP_TRY(c, hipMemcpyAsync(h, c->d_counters, sizeof h, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->d_counters, 0, sizeof h, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  *applied = (int64_t)h[0];
-  *fallback = (int64_t)h[1];
-  return ATNS_OK;
+  });
 }
 
 atns_status atns_hbm_probe(const void* dev_src, void* dev_dst, int64_t bytes, void* stream) {
-  if (!dev_src || !dev_dst || bytes < 16 || bytes % 16 != 0)
-    return fail(nullptr, ATNS_EINVAL, "probe needs device buffers and a positive multiple of 16 bytes");
-  const hipError_t e = launch_copy_probe(dev_src, dev_dst, bytes, (hipStream_t)stream);
-  if (e != hipSuccess) return fail(nullptr, ATNS_EHIP, std::string("copy probe: ") + hipGetErrorString(e));
-  return ATNS_OK;
+  return guarded(nullptr, [&]() -> atns_status {
+    if (!dev_src || !dev_dst || bytes < 16 || bytes % 16 != 0)
+      return fail(nullptr, ATNS_EINVAL, "probe needs device buffers and a positive multiple of 16 bytes");
+    const hipError_t e = launch_copy_probe(dev_src, dev_dst, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, ATNS_EHIP, std::string("copy probe: ") + hipGetErrorString(e));
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_filter_state(atns_ctx* c) {
-  if (!c) return fail(c, ATNS_EINVAL, "null context");
-  if (!c->cfg.filter) return fail(c, ATNS_EINVAL, "the context has no filter");
-  if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
-  const int slot = c->D ? (int)(c->step % c->D) : 0;
-  return c->esz == 4 ? enqueue_filter<float>(c, c->cur, kHaloSync, nullptr, slot, c->stream)
-                     : enqueue_filter<double>(c, c->cur, kHaloSync, nullptr, slot, c->stream);
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    if (!c->cfg.filter) return fail(c, ATNS_EINVAL, "the context has no filter");
+    if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
+    const int slot = c->D ? (int)(c->step % c->D) : 0;
+    return c->esz == 4 ? enqueue_filter<float>(c, c->cur, kHaloSync, nullptr, slot, c->stream)
+                       : enqueue_filter<double>(c, c->cur, kHaloSync, nullptr, slot, c->stream);
+  });
 }
 
 atns_status atns_host_filter_coefficients(double alpha, double* a6) {
-  if (!a6 || !(alpha > -0.5 && alpha <= 0.5)) return fail(nullptr, ATNS_EINVAL, "bad filter request");
-  const std::vector<double> a = filter_coefficients(alpha);
-  for (int m = 0; m < 6; ++m) a6[m] = a[m];
-  return ATNS_OK;
+  return guarded(nullptr, [&]() -> atns_status {
+    if (!a6 || !(alpha > -0.5 && alpha <= 0.5)) return fail(nullptr, ATNS_EINVAL, "bad filter request");
+    const std::vector<double> a = filter_coefficients(alpha);
+    for (int m = 0; m < 6; ++m) a6[m] = a[m];
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_host_weights(int32_t rk, int32_t mode, int32_t L, double* out) {
-  if (!out || L < 1 || L > 16 || (rk != ATNS_RK4 && rk != ATNS_LSERK4 && rk != ATNS_LSERK2) ||
-      (mode != ATNS_AT && mode != ATNS_AS))
-    return fail(nullptr, ATNS_EINVAL, "bad weight-table request");
-  const std::vector<double> W = halo_weights(rk, mode, L);
-  std::memcpy(out, W.data(), W.size() * sizeof(double));
-  return ATNS_OK;
+  return guarded(nullptr, [&]() -> atns_status {
+    if (!out || L < 1 || L > 16 || (rk != ATNS_RK4 && rk != ATNS_LSERK4 && rk != ATNS_LSERK2) ||
+        (mode != ATNS_AT && mode != ATNS_AS))
+      return fail(nullptr, ATNS_EINVAL, "bad weight-table request");
+    const std::vector<double> W = halo_weights(rk, mode, L);
+    std::memcpy(out, W.data(), W.size() * sizeof(double));
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_host_delays(int32_t algo, int32_t rk, int64_t n, int32_t nblocks, int32_t L, uint64_t seed,
                              int8_t* out, int32_t* synchronous) {
-  if (!out || nblocks < 1 || L < 1 || L > 16 || (algo != ATNS_CAA && algo != ATNS_SAA) || n < 0 ||
-      (rk != ATNS_RK4 && rk != ATNS_LSERK4 && rk != ATNS_LSERK2))
-    return fail(nullptr, ATNS_EINVAL, "bad delay request");
-  const bool async = step_delays(algo, n, nblocks, L, levels(rk), seed, nullptr, out);
-  if (synchronous) *synchronous = async ? 0 : 1;
-  return ATNS_OK;
+  return guarded(nullptr, [&]() -> atns_status {
+    if (!out || nblocks < 1 || L < 1 || L > 16 || (algo != ATNS_CAA && algo != ATNS_SAA) || n < 0 ||
+        (rk != ATNS_RK4 && rk != ATNS_LSERK4 && rk != ATNS_LSERK2))
+      return fail(nullptr, ATNS_EINVAL, "bad delay request");
+    const bool async = step_delays(algo, n, nblocks, L, levels(rk), seed, nullptr, out);
+    if (synchronous) *synchronous = async ? 0 : 1;
+    return ATNS_OK;
+  });
 }
 
 }  // extern "C"
@@ -1896,6 +2007,11 @@ struct atns_batch {
 };
 
 namespace {
+
+template <class F>
+atns_status guarded(const atns_batch* b, F&& f) {
+  return guard_body(std::forward<F>(f), b ? &const_cast<atns_batch*>(b)->err : nullptr);
+}
 
 atns_status bfail(atns_batch* b, atns_status s, const std::string& msg) {
   if (b) b->err = msg;
@@ -2100,79 +2216,89 @@ void batch_release(atns_batch* b) {
 extern "C" {
 
 atns_status atns_batch_create(const atns_config* cfgs, int32_t n, void* stream, atns_batch** out) {
-  if (!out || !cfgs || n < 1) return bfail(nullptr, ATNS_EINVAL, "bad batch arguments");
-  *out = nullptr;
-  for (int i = 0; i < n; ++i) {
-    if (cfgs[i].rk != ATNS_RK4) return bfail(nullptr, ATNS_EINVAL, "batch members use classical RK4");
-    if (cfgs[i].precision != cfgs[0].precision) return bfail(nullptr, ATNS_EINVAL, "batch members share precision");
-    if (cfgs[i].ndim != 3) return bfail(nullptr, ATNS_EINVAL, "batch members are three-dimensional");
-    if (cfgs[i].filter) return bfail(nullptr, ATNS_EINVAL, "batch members run without the filter");
-  }
-  auto* b = new atns_batch();
-  b->user = (hipStream_t)stream;
-  b->esz = cfgs[0].precision == ATNS_F64 ? 8 : 4;
-  for (int i = 0; i < n; ++i) {
-    atns_ctx* c = nullptr;
-    atns_status st = atns_create(&cfgs[i], stream, &c);
-    if (st != ATNS_OK) {
+  return guarded(nullptr, [&]() -> atns_status {
+    if (!out || !cfgs || n < 1) return bfail(nullptr, ATNS_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+      if (cfgs[i].rk != ATNS_RK4) return bfail(nullptr, ATNS_EINVAL, "batch members use classical RK4");
+      if (cfgs[i].precision != cfgs[0].precision) return bfail(nullptr, ATNS_EINVAL, "batch members share precision");
+      if (cfgs[i].ndim != 3) return bfail(nullptr, ATNS_EINVAL, "batch members are three-dimensional");
+      if (cfgs[i].filter) return bfail(nullptr, ATNS_EINVAL, "batch members run without the filter");
+    }
+    auto* b = new atns_batch();
+    b->user = (hipStream_t)stream;
+    b->esz = cfgs[0].precision == ATNS_F64 ? 8 : 4;
+    for (int i = 0; i < n; ++i) {
+      atns_ctx* c = nullptr;
+      atns_status st = atns_create(&cfgs[i], stream, &c);
+      if (st != ATNS_OK) {
+        batch_release(b);
+        delete b;
+        return st;
+      }
+      c->batch_member = true;
+      b->m.push_back(c);
+    }
+    auto bad = [&](atns_status s, const char* m) {
       batch_release(b);
       delete b;
-      return st;
-    }
-    c->batch_member = true;
-    b->m.push_back(c);
-  }
-  auto bad = [&](atns_status s, const char* m) {
-    batch_release(b);
-    delete b;
-    return bfail(nullptr, s, m);
-  };
-  if (hipStreamCreate(&b->s[0]) != hipSuccess || hipStreamCreate(&b->s[1]) != hipSuccess ||
-      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->order, hipEventDisableTiming) != hipSuccess)
-    return bad(ATNS_EHIP, "batch stream creation failed");
-  std::vector<long long*> cnt;
-  for (atns_ctx* c : b->m) cnt.push_back(c->d_nstep);
-  if (hipMalloc((void**)&b->d_cnt, cnt.size() * sizeof(long long*)) != hipSuccess ||
-      hipMemcpy(b->d_cnt, cnt.data(), cnt.size() * sizeof(long long*), hipMemcpyHostToDevice) != hipSuccess)
-    return bad(ATNS_EHIP, "batch counter table failed");
-  for (int ph = 0; ph < 2; ++ph)
-    if (batch_tiles(b, ph) != ATNS_OK) return bad(ATNS_EHIP, "batch tile table failed");
-  *out = b;
-  return ATNS_OK;
+      return bfail(nullptr, s, m);
+    };
+    if (hipStreamCreate(&b->s[0]) != hipSuccess || hipStreamCreate(&b->s[1]) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->order, hipEventDisableTiming) != hipSuccess)
+      return bad(ATNS_EHIP, "batch stream creation failed");
+    std::vector<long long*> cnt;
+    for (atns_ctx* c : b->m) cnt.push_back(c->d_nstep);
+    if (hipMalloc((void**)&b->d_cnt, cnt.size() * sizeof(long long*)) != hipSuccess ||
+        hipMemcpy(b->d_cnt, cnt.data(), cnt.size() * sizeof(long long*), hipMemcpyHostToDevice) != hipSuccess)
+      return bad(ATNS_EHIP, "batch counter table failed");
+    for (int ph = 0; ph < 2; ++ph)
+      if (batch_tiles(b, ph) != ATNS_OK) return bad(ATNS_EHIP, "batch tile table failed");
+    *out = b;
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_batch_destroy(atns_batch* b) {
-  if (!b) return ATNS_OK;
-  (void)hipDeviceSynchronize();
-  batch_release(b);
-  delete b;
-  return ATNS_OK;
+  return guarded(b, [&]() -> atns_status {
+    if (!b) return ATNS_OK;
+    (void)hipDeviceSynchronize();
+    batch_release(b);
+    delete b;
+    return ATNS_OK;
+  });
 }
 
 const char* atns_batch_last_error(const atns_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
 
 atns_status atns_batch_member(atns_batch* b, int32_t i, atns_ctx** ctx) {
-  if (!b || !ctx || i < 0 || i >= (int)b->m.size()) return bfail(b, ATNS_EINVAL, "bad member index");
-  *ctx = b->m[i];
-  return ATNS_OK;
+  return guarded(b, [&]() -> atns_status {
+    if (!b || !ctx || i < 0 || i >= (int)b->m.size()) return bfail(b, ATNS_EINVAL, "bad member index");
+    *ctx = b->m[i];
+    return ATNS_OK;
+  });
 }
 
 atns_status atns_batch_set_tiles(atns_batch* b, int32_t physics, int32_t tx, int32_t ty, int32_t tz) {
-  if (!b || (physics != ATNS_EULER && physics != ATNS_NS)) return bfail(b, ATNS_EINVAL, "bad physics");
-  if (!shape_supported(physics, b->esz, tx, ty) || tz < 1) return bfail(b, ATNS_EINVAL, "unsupported tile shape");
-  BHIP(b, hipDeviceSynchronize());
-  const int ph = physics == ATNS_NS ? 1 : 0;
-  b->shape[ph][0] = tx;
-  b->shape[ph][1] = ty;
-  b->shape[ph][2] = tz;
-  return batch_tiles(b, ph);
+  return guarded(b, [&]() -> atns_status {
+    if (!b || (physics != ATNS_EULER && physics != ATNS_NS)) return bfail(b, ATNS_EINVAL, "bad physics");
+    if (!shape_supported(physics, b->esz, tx, ty) || tz < 1) return bfail(b, ATNS_EINVAL, "unsupported tile shape");
+    BHIP(b, hipDeviceSynchronize());
+    const int ph = physics == ATNS_NS ? 1 : 0;
+    b->shape[ph][0] = tx;
+    b->shape[ph][1] = ty;
+    b->shape[ph][2] = tz;
+    return batch_tiles(b, ph);
+  });
 }
 
 atns_status atns_batch_step(atns_batch* b, int32_t nsteps) {
-  if (!b || nsteps < 0) return bfail(b, ATNS_EINVAL, "bad arguments");
-  return b->esz == 4 ? batch_steps<float>(b, nsteps) : batch_steps<double>(b, nsteps);
+  return guarded(b, [&]() -> atns_status {
+    if (!b || nsteps < 0) return bfail(b, ATNS_EINVAL, "bad arguments");
+    return b->esz == 4 ? batch_steps<float>(b, nsteps) : batch_steps<double>(b, nsteps);
+  });
 }
 
 }  // extern "C"
@@ -2249,65 +2375,67 @@ atns_status batch_time(atns_batch* b, int mask, int reps, float* ms_out) {
 extern "C" {
 
 atns_status atns_batch_autotune(atns_batch* b, int32_t reps, int32_t* best) {
-  if (!b || reps < 1) return bfail(b, ATNS_EINVAL, "bad arguments");
-  for (atns_ctx* c : b->m)
-    if (!c->state_set) return bfail(b, ATNS_ESTATE, "member state not set");
-  BHIP(b, hipDeviceSynchronize());
-  // Every shape of each physics is timed with the batch kernels themselves
-  // over the combined tile list of all members of that physics (timing
-  // probes on the current states, which stay untouched).  The two physics
-  // share the device during a batch step, so the three fastest shapes of
-  // each are then timed in pairs, running concurrently, and the fastest pair
-  // is kept.
-  constexpr int kTop = 3;
-  std::vector<std::array<int, 3>> top[2];
-  auto timer = [&](int mask, float* ms) {
-    return b->esz == 4 ? batch_time<float>(b, mask, reps, ms) : batch_time<double>(b, mask, reps, ms);
-  };
-  for (int ph = 0; ph < 2; ++ph) {
-    const int phys = ph ? ATNS_NS : ATNS_EULER;
-    if (b->tl[ph].empty()) {
-      top[ph].push_back({b->shape[ph][0], b->shape[ph][1], b->shape[ph][2]});
-      continue;
+  return guarded(b, [&]() -> atns_status {
+    if (!b || reps < 1) return bfail(b, ATNS_EINVAL, "bad arguments");
+    for (atns_ctx* c : b->m)
+      if (!c->state_set) return bfail(b, ATNS_ESTATE, "member state not set");
+    BHIP(b, hipDeviceSynchronize());
+    // Every shape of each physics is timed with the batch kernels themselves
+    // over the combined tile list of all members of that physics (timing
+    // probes on the current states, which stay untouched).  The two physics
+    // share the device during a batch step, so the three fastest shapes of
+    // each are then timed in pairs, running concurrently, and the fastest pair
+    // is kept.
+    constexpr int kTop = 3;
+    std::vector<std::array<int, 3>> top[2];
+    auto timer = [&](int mask, float* ms) {
+      return b->esz == 4 ? batch_time<float>(b, mask, reps, ms) : batch_time<double>(b, mask, reps, ms);
+    };
+    for (int ph = 0; ph < 2; ++ph) {
+      const int phys = ph ? ATNS_NS : ATNS_EULER;
+      if (b->tl[ph].empty()) {
+        top[ph].push_back({b->shape[ph][0], b->shape[ph][1], b->shape[ph][2]});
+        continue;
+      }
+      std::vector<std::pair<float, std::array<int, 3>>> timed;
+      for (int i = 0; i < num_shapes(phys, b->esz); ++i)
+        for (int tz : {4, 8, 16, 32}) {
+          if (ph == 1 && tz < 8) continue;
+          const int tx = shape_at(phys, i)[0], ty = shape_at(phys, i)[1];
+          atns_status st = atns_batch_set_tiles(b, phys, tx, ty, tz);
+          if (st != ATNS_OK) return st;
+          float ms = 0.f;
+          if ((st = timer(1 << ph, &ms)) != ATNS_OK) return st;
+          timed.push_back({ms, {tx, ty, tz}});
+        }
+      std::stable_sort(timed.begin(), timed.end(),
+                       [](const auto& x, const auto& y) { return x.first < y.first; });
+      for (int i = 0; i < kTop && i < (int)timed.size(); ++i) top[ph].push_back(timed[i].second);
     }
-    std::vector<std::pair<float, std::array<int, 3>>> timed;
-    for (int i = 0; i < num_shapes(phys, b->esz); ++i)
-      for (int tz : {4, 8, 16, 32}) {
-        if (ph == 1 && tz < 8) continue;
-        const int tx = shape_at(phys, i)[0], ty = shape_at(phys, i)[1];
-        atns_status st = atns_batch_set_tiles(b, phys, tx, ty, tz);
+    float best_ms = 1e30f;
+    std::array<int, 3> pick[2] = {top[0][0], top[1][0]};
+    for (const auto& eu : top[0])
+      for (const auto& ns : top[1]) {
+        atns_status st = atns_batch_set_tiles(b, ATNS_EULER, eu[0], eu[1], eu[2]);
+        if (st == ATNS_OK) st = atns_batch_set_tiles(b, ATNS_NS, ns[0], ns[1], ns[2]);
         if (st != ATNS_OK) return st;
         float ms = 0.f;
-        if ((st = timer(1 << ph, &ms)) != ATNS_OK) return st;
-        timed.push_back({ms, {tx, ty, tz}});
+        if ((st = timer(3, &ms)) != ATNS_OK) return st;
+        if (ms < best_ms) {
+          best_ms = ms;
+          pick[0] = eu;
+          pick[1] = ns;
+        }
       }
-    std::stable_sort(timed.begin(), timed.end(),
-                     [](const auto& x, const auto& y) { return x.first < y.first; });
-    for (int i = 0; i < kTop && i < (int)timed.size(); ++i) top[ph].push_back(timed[i].second);
-  }
-  float best_ms = 1e30f;
-  std::array<int, 3> pick[2] = {top[0][0], top[1][0]};
-  for (const auto& eu : top[0])
-    for (const auto& ns : top[1]) {
-      atns_status st = atns_batch_set_tiles(b, ATNS_EULER, eu[0], eu[1], eu[2]);
-      if (st == ATNS_OK) st = atns_batch_set_tiles(b, ATNS_NS, ns[0], ns[1], ns[2]);
+    for (int ph = 0; ph < 2; ++ph) {
+      const atns_status st = atns_batch_set_tiles(b, ph ? ATNS_NS : ATNS_EULER, pick[ph][0], pick[ph][1], pick[ph][2]);
       if (st != ATNS_OK) return st;
-      float ms = 0.f;
-      if ((st = timer(3, &ms)) != ATNS_OK) return st;
-      if (ms < best_ms) {
-        best_ms = ms;
-        pick[0] = eu;
-        pick[1] = ns;
-      }
     }
-  for (int ph = 0; ph < 2; ++ph) {
-    const atns_status st = atns_batch_set_tiles(b, ph ? ATNS_NS : ATNS_EULER, pick[ph][0], pick[ph][1], pick[ph][2]);
-    if (st != ATNS_OK) return st;
-  }
-  if (best)
-    for (int ph = 0; ph < 2; ++ph)
-      for (int d = 0; d < 3; ++d) best[ph * 3 + d] = b->shape[ph][d];
-  return ATNS_OK;
+    if (best)
+      for (int ph = 0; ph < 2; ++ph)
+        for (int d = 0; d < 3; ++d) best[ph * 3 + d] = b->shape[ph][d];
+    return ATNS_OK;
+  });
 }
 
 }  // extern "C"
