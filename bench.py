@@ -160,6 +160,11 @@ def run_path(torch, w, precision, mode, steps, warmup, dt, U0=None, net=None):
     return {"ms": ms, "launches": launches, "kms": kms, "finite": finite, "tiles": tiles, "stats": stats, "U": U}
 
 
+# The learned halo runs only if, on held-out training samples, it lowers the
+# mean squared halo error of the AT extrapolation by at least this fraction.
+MLP_ACCEPT_DELTA = 0.1
+
+
 def train_halo_net(torch, w, dt, tau=10.0):
     """The learned halo's network, trained on FP64 synchronous Taylor-Green
     runs the solver generates at 256^3 in 16x16x8 blocks with the run's dt
@@ -802,15 +807,30 @@ def headline_main(a, torch, cpu):
     U_at = at.pop("U")
     # the learned halo, trained on the GPU by the library's kernels
     U_mlp = None
+    net = None
     if ns and w["rk"] == "rk4" and w["mode"] == "at" and not a.no_mlp:
         net = train_halo_net(torch, w, dt)
+        tr = net["training"]
+        ratio = tr["halo_mse_mlp"] / tr["halo_mse_at"]
+        if not ratio < 1.0 - MLP_ACCEPT_DELTA:
+            # nothing to gain: the correction kernel is not run
+            out["at_mlp"] = {"accepted": False, "halo_mse_ratio": ratio, "accept_delta": MLP_ACCEPT_DELTA,
+                             "ms_per_step": at["ms"] / a.steps, "value": value,
+                             "reason": "on held-out samples the trained network does not reduce the AT halo "
+                                       "error by the acceptance margin at this time step (the extrapolation "
+                                       "error is at the rounding level), so the step runs without it",
+                             "training": tr}
+            net = None
+    if net is not None:
         ml = run_path(torch, w, atns.F32, None, a.steps, warmup, dt, U0, net=net)
         U_mlp = ml.pop("U")
         face_pts = (ml["stats"][0] + ml["stats"][1]) / a.steps
         flops = face_pts * 2.0 * (64 * 64 + 64 * 64 + 16 * 64)
         extra_ms = (ml["ms"] - at["ms"]) / a.steps
         tflops = flops / (extra_ms * 1e-3) / 1e12 if extra_ms > 0 else None
-        out["at_mlp"] = {"value": npts * stages * a.steps / (ml["ms"] * 1e-3), "ms_per_step": ml["ms"] / a.steps,
+        out["at_mlp"] = {"accepted": True, "halo_mse_ratio": net["training"]["halo_mse_mlp"] /
+                         net["training"]["halo_mse_at"], "accept_delta": MLP_ACCEPT_DELTA,
+                         "value": npts * stages * a.steps / (ml["ms"] * 1e-3), "ms_per_step": ml["ms"] / a.steps,
                          "tau": net["tau"], "applied": ml["stats"][0], "fallback": ml["stats"][1],
                          "face_points_per_step": face_pts, "flops_per_step": flops,
                          "extra_ms_per_step": extra_ms, "achieved_tflops": tflops,
@@ -844,9 +864,16 @@ def headline_main(a, torch, cpu):
         if eq is not None:
             eq["fp32_at_err_vs_fp64_sa"] = l2["at"]
             eq["ratio"] = l2["at"] / eq["fp64_sa_disc_err_est"]
-            eq["note"] = ("the FP32 AT path departs from the FP64 synchronous solution by this fraction of the "
-                          "latter's own discretization error, so the two are at equal accuracy to within it and "
-                          "speedup_vs_fp64_sa is the speed-up at equal accuracy")
+            eq["equal_accuracy"] = eq["ratio"] <= 1.0
+            if eq["equal_accuracy"]:
+                eq["note"] = ("the FP32 AT path departs from the FP64 synchronous solution by less than the "
+                              "latter's own discretization error, so speedup_vs_fp64_sa is a speed-up at equal "
+                              "accuracy")
+            else:
+                eq["note"] = ("over this short horizon the FP64 synchronous solution's discretization error is "
+                              "far below FP32 rounding: the FP32 AT path departs from it by `ratio` times that "
+                              "error, so the two are not at equal accuracy and speedup_vs_fp64_sa compares equal "
+                              "grids and time steps, not equal errors")
             out["equal_accuracy"] = eq
         del U_ref
     if cpu is not None:

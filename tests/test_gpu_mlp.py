@@ -227,29 +227,58 @@ def test_training_reduces_loss_and_halo_error(trained):
     assert trained["mse_mlp"] < 0.6 * trained["mse_at"]
 
 
-def test_learned_halo_gain_in_the_solver(trained):
-    # AT and AT + MLP runs (SAA, L = 4, FP64) against the synchronous run of
-    # the same step: the correction must not make the solution worse.
+# The learned halo's gain, on a case shaped like the 512^3 workload's blocks
+# (32^3 Navier-Stokes blocks, SAA with L = 5, so delays reach 4) at a time
+# step where the AT4 extrapolation error (about 1e-3 relative after 30
+# steps) sits far above rounding: FP64 throughout, CFL 1.0.  The network is
+# trained on the solver's own synchronous FP64 history (20 rounds of 100
+# Adam iterations), then AT and AT + MLP runs are compared with the
+# synchronous run of the same steps.  Required: AT + MLP's relative L2
+# below (1 - DELTA) times AT's.
+GAIN_N = (64, 64, 64)
+GAIN_DELTA = 0.05
+
+
+def test_learned_halo_gain_on_32cubed_blocks_at_delay_bound():
     torch = need_gpu()
-    announce("mlp gain")
-    n, dt = TRAIN_N, trained["dt"]
+    announce("mlp gain, 32^3 blocks, L=5")
+    n, L = GAIN_N, 5
+    _, g = pair(dict(n=n, length=L3, nblk=(2, 2, 2), physics="ns", mode="sa", L=L, re=1600.0, mach=0.1), "f64")
     U0 = inputs.tgv_state(n)
+    dt = inputs.cfl_dt(U0, n, L3, 3, 1.4, 1.0)
+    g.set_dt(dt)
+    g.set_state(torch.from_numpy(U0))
+    g.step(12)
+    g.mlp_set_scales(np.ones(5), np.ones(5))
+    X, Y = g.mlp_sample(8192, 1)
+    X, Y = to_np(X), to_np(Y)
+    s = (np.sqrt((X[:, :60].reshape(-1, 4, 5, 3) ** 2).mean(axis=(0, 1, 3))) + 1e-30).astype(np.float32)
+    r = (np.sqrt((Y[:, :5] ** 2).mean(axis=0)) + 1e-30).astype(np.float32)
+    g.mlp_set_scales(s, r)
+    g.mlp_set_params(omlp.init(0).astype(np.float32) * np.float32(0.5))
+    for rnd in range(20):
+        g.step(2)
+        g.mlp_train(100, 1024, 1e-3, 100 + rnd)
+    theta = g.mlp_get_params()
+    g.close()
     out = {}
     for name, mode, use in (("sa", "sa", False), ("at", "at", False), ("mlp", "at", True)):
-        _, g = pair(dict(n=n, length=L3, nblk=(3, 3, 3), physics="ns", mode=mode, algo="saa", L=4,
-                         seed=3, re=1600.0, mach=0.1), "f64", dt=dt)
+        _, h = pair(dict(n=n, length=L3, nblk=(2, 2, 2), physics="ns", mode=mode, algo="saa", L=L, seed=3,
+                         re=1600.0, mach=0.1), "f64", dt=dt)
         if use:
-            g.mlp_set_params(trained["theta"])
-            g.mlp_set_scales(trained["s"], trained["r"])
-            g.mlp_enable(True, 10.0)
-        g.set_state(torch.from_numpy(U0))
-        g.step(30)
-        out[name] = to_np(g.get_state())
+            h.mlp_set_params(theta)
+            h.mlp_set_scales(s, r)
+            h.mlp_enable(True, 10.0)
+        h.set_state(torch.from_numpy(U0))
+        h.step(30)
+        out[name] = to_np(h.get_state())
         if use:
-            out["stats"] = g.mlp_stats()
-        g.close()
+            out["stats"] = h.mlp_stats()
+        h.close()
     e_at = np.linalg.norm(out["at"] - out["sa"]) / np.linalg.norm(out["sa"])
     e_mlp = np.linalg.norm(out["mlp"] - out["sa"]) / np.linalg.norm(out["sa"])
-    print("rel L2 vs SA after 30 steps: AT %.3e  AT+MLP %.3e  (applied, fallback) %s" % (e_at, e_mlp, out["stats"]))
+    print("rel L2 vs SA after 30 steps: AT %.4e  AT+MLP %.4e  gain %.3f  (applied, fallback) %s"
+          % (e_at, e_mlp, 1 - e_mlp / e_at, out["stats"]))
+    assert e_at > 1e-5                    # the delay error is far above rounding here
     assert out["stats"][0] > 0
-    assert e_mlp <= 1.05 * e_at
+    assert e_mlp < (1.0 - GAIN_DELTA) * e_at
