@@ -215,7 +215,7 @@ __device__ __forceinline__ void ns_flux(const NsGrad<T>& s, int d, T ire, T kap,
   out[4] = fma(s.et + s.pres, ud, -(ire * work));
 }
 
-template <typename T, int TX, int TY, int KIND, int NDIM>
+template <typename T, int TX, int TY, int KIND, int NDIM, bool CD2>
 __device__ __forceinline__ void ns_tile_lean(const StageParams<T>& p, const TileDev t) {
 #pragma clang fp contract(off)
   using S = NsShape<T, TX, TY>;
@@ -261,8 +261,9 @@ __device__ __forceinline__ void ns_tile_lean(const StageParams<T>& p, const Tile
   const T kap = (T)p.kappa;
   const T ire = (T)p.inv_re;
   const T ihx = (T)p.dscale[0], ihy = (T)p.dscale[1], ihz = (T)p.dscale[2];
-  // central-difference weights of the inner and outer neighbour pairs
-  const T w1 = p.cd2 ? T(1) : T(8), w2 = p.cd2 ? T(0) : T(1);
+  // central-difference weights of the inner and outer neighbour pairs, known
+  // at compile time (w2 = 1 multiplies away for CD4)
+  constexpr T w1 = CD2 ? T(1) : T(8), w2 = CD2 ? T(0) : T(1);
   const T two3 = (T)(2.0 / 3.0);
   const T igM2 = (T)(1.0 / p.mach2_gamma), igm1 = (T)(1.0 / (p.gamma - 1.0));
 
@@ -616,9 +617,12 @@ constexpr int ns_threads() {
 }
 template <typename T, int TX, int TY, int KIND, int NDIM>
 __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t) {
-  if constexpr (sizeof(T) == 4)
-    ns_tile_lean<T, TX, TY, KIND, NDIM>(p, t);
-  else
+  if constexpr (sizeof(T) == 4) {
+    if (p.cd2)
+      ns_tile_lean<T, TX, TY, KIND, NDIM, true>(p, t);
+    else
+      ns_tile_lean<T, TX, TY, KIND, NDIM, false>(p, t);
+  } else
     ns_tile_wide<T, TX, TY, KIND, NDIM>(p, t);
 }
 
