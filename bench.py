@@ -311,6 +311,57 @@ def traffic_summary(workload, fetch_db, write_db, commands):
                       "algorithmic_bytes_per_launch": rec["algorithmic_bytes_per_launch"]}))
 
 
+SQ_COUNTERS = {
+    "a": ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+          "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY"],
+    "b": ["SQ_WAVE_CYCLES", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_WAIT_ANY",
+          "SQ_INST_CYCLES_VMEM_RD", "SQ_LDS_BANK_CONFLICT", "SQ_THREAD_CYCLES_VALU"],
+}
+
+
+def sq_summary(workload, dbs, commands):
+    """The counter record profiles/sq_<workload>.json of the stage kernel at
+    the benchmark's tile shape and launch size, from two rocprofv3 --pmc runs
+    of this script (counter sets SQ_COUNTERS a and b): per-launch averages of
+    each counter, the same per owned point, and ratios that say where the
+    waves' time goes."""
+    import sqlite3
+    w = inputs.WORKLOADS[workload]
+    npts = w["n"][0] * w["n"][1] * w["n"][2]
+    kname = "ns_stage_kernel" if w["physics"] == "ns" else "euler_stage_kernel"
+    vals, chosen = {}, None
+    for db in dbs:
+        c = sqlite3.connect(db)
+        rows = c.execute("select kernel_name, grid_size / workgroup_size, dispatch_id, counter_name, sum(value) "
+                         "from counters_collection group by kernel_name, dispatch_id, counter_name").fetchall()
+        groups = {}
+        for name, wg, disp, cn, v in rows:
+            if kname not in name:
+                continue
+            shape = ", ".join(name.split("<", 1)[1].split(">", 1)[0].split(", ")[:3])
+            groups.setdefault((shape, wg), {}).setdefault(cn, {})[disp] = v
+        best = max(groups, key=lambda g: max(len(d) for d in groups[g].values()))
+        chosen = chosen or best
+        for cn, d in groups[best].items():
+            vals[cn] = float(np.mean(list(d.values())))
+    per_pt = {cn: v / npts for cn, v in vals.items()}
+    ratios = {}
+    if "SQ_WAVE_CYCLES" in vals:
+        wc = vals["SQ_WAVE_CYCLES"]
+        for cn in ("SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_WAIT_ANY",
+                   "SQ_WAIT_INST_ANY"):
+            if cn in vals:
+                ratios[cn + "/SQ_WAVE_CYCLES"] = vals[cn] / wc
+    rec = {"workload": workload, "kernel": "%s<%s> at %d workgroups, all stage kinds" % (kname, chosen[0], chosen[1]),
+           "kernel_hash": kernel_source_hash(), "commands": commands, "run_from": "/tmp, with TMPDIR=/tmp",
+           "owned_points": npts, "per_launch": vals, "per_owned_point": per_pt, "ratios": ratios}
+    path = os.path.join(ROOT, "profiles", "sq_%s.json" % workload)
+    with open(path, "w") as fo:
+        json.dump(rec, fo, indent=1)
+    print(json.dumps({"written": path, "ratios": ratios,
+                      "valu_per_point": per_pt.get("SQ_INSTS_VALU")}))
+
+
 def trace_summary(db, top=14):
     """Markdown summary of a rocprofv3 --kernel-trace database: calls, total
     and average duration (microseconds) per kernel and launch size
@@ -901,6 +952,10 @@ def main():
                     help="write profiles/traffic_<workload>.json from two rocprofv3 --pmc runs (FETCH_SIZE, "
                          "WRITE_SIZE) of this script; no GPU work")
     ap.add_argument("--traffic-commands", nargs="*", default=[], help="the two rocprofv3 commands, for the record")
+    ap.add_argument("--sq-summary", nargs=2, metavar=("DB_A", "DB_B"), default=None,
+                    help="write profiles/sq_<workload>.json from two rocprofv3 --pmc runs (SQ counter sets a, b)")
+    ap.add_argument("--sq-set", choices=sorted(SQ_COUNTERS), default=None,
+                    help="print the counters of one SQ set (for the rocprofv3 --pmc list) and exit")
     ap.add_argument("--trace-summary", default=None, metavar="DB",
                     help="print a markdown table of a rocprofv3 --kernel-trace database; no GPU work")
     ap.add_argument("--free-running", action="store_true",
@@ -916,6 +971,12 @@ def main():
         return
     if a.traffic_summary:
         traffic_summary(a.workload, a.traffic_summary[0], a.traffic_summary[1], a.traffic_commands)
+        return
+    if a.sq_set:
+        print(" ".join(SQ_COUNTERS[a.sq_set]))
+        return
+    if a.sq_summary:
+        sq_summary(a.workload, a.sq_summary, a.traffic_commands)
         return
     single = a.workload != "batch48" and not a.free_running and not a.series
     # the oracle's timing runs before anything touches the GPU (it forks workers)
