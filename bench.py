@@ -98,14 +98,14 @@ def stage_kernel_bytes_per_point(w, stages, esz):
     return (80.0 + 20.0 * f + 20.0 * f / stages) * scale
 
 
-def make_solver(w, precision, mode=None):
+def make_solver(w, precision, mode=None, filter_alpha=None):
     phys = atns.NS if w["physics"] == "ns" else atns.EULER
     m = {"sa": atns.SA, "as": atns.AS, "at": atns.AT}[mode or w["mode"]]
     algo = atns.SAA if w.get("algo", "saa") == "saa" else atns.CAA
     return atns.Solver(n=w["n"], length=w["length"], ndim=w["ndim"], nblk=w["nblk"], physics=phys,
                        mach=w.get("mach", 0.1), re=w.get("re", 1600.0),
                        rk=RK_ID[w["rk"]], mode=m, algo=algo,
-                       L=w["L"], seed=w.get("seed", 1), precision=precision)
+                       L=w["L"], seed=w.get("seed", 1), precision=precision, filter_alpha=filter_alpha)
 
 
 def initial_state(w):
@@ -127,14 +127,15 @@ def time_steps(torch, g, steps):
 TUNE_CACHE = os.environ.get("ATNS_TUNE_CACHE", os.path.join("/tmp", "atns_tune.txt"))
 
 
-def run_path(torch, w, precision, mode, steps, warmup, dt, U0=None, net=None):
+def run_path(torch, w, precision, mode, steps, warmup, dt, U0=None, net=None, filter_alpha=None):
     """One path of the workload from the initial field: the autotuned tiles,
     `warmup` untimed steps, `steps` timed graph-captured steps, then `steps`
     eager steps with the stage kernels bracketed by HIP events.  net (the
     learned halo: theta, s, r, tau) switches the correction on.  Returns the
     timings, the tiles, the learned-halo counts of the timed steps and the
-    final state (on the device)."""
-    g = make_solver(w, precision, mode)
+    final state (on the device).  filter_alpha switches the tenth-order
+    filter on."""
+    g = make_solver(w, precision, mode, filter_alpha)
     g.set_dt(dt)
     if U0 is None:
         g.init_case(atns.CASE_TGV if w["physics"] == "ns" else atns.CASE_VORTEX)
@@ -159,6 +160,9 @@ def run_path(torch, w, precision, mode, steps, warmup, dt, U0=None, net=None):
     g.close()
     return {"ms": ms, "launches": launches, "kms": kms, "finite": finite, "tiles": tiles, "stats": stats, "U": U}
 
+
+# Filter coefficient of the Taylor-Green runs of Sec. 5.2.
+FILTER_ALPHA = 0.499
 
 # The learned halo runs only if, on held-out training samples, it lowers the
 # mean squared halo error of the AT extrapolation by at least this fraction.
@@ -856,6 +860,19 @@ def headline_main(a, torch, cpu):
         "finite": at["finite"],
     }
     U_at = at.pop("U")
+    if ns and not a.no_filter:
+        # the same steps with the tenth-order filter after each (Sec. 5.2's
+        # alpha_f): three line-solve passes and the ring write of the
+        # filtered field, which the last stage then leaves out
+        fl = run_path(torch, w, atns.F32, None, a.steps, warmup, dt, U0, filter_alpha=FILTER_ALPHA)
+        fl.pop("U")
+        extra = (fl["ms"] - at["ms"]) / a.steps
+        fbytes = (3 * 2 * 20.0 + 20.0) * npts     # 3 passes read and write the state; the ring fill reads it
+        out["at_filtered"] = {"alpha": FILTER_ALPHA, "value": npts * stages * a.steps / (fl["ms"] * 1e-3),
+                              "ms_per_step": fl["ms"] / a.steps, "filter_ms_per_step": extra,
+                              "filter_bytes_per_step": fbytes,
+                              "filter_hbm_frac": (fbytes / (extra * 1e-3) / 1e9 / HBM_PEAK_GBS) if extra > 0 else None,
+                              "finite": fl["finite"]}
     # the learned halo, trained on the GPU by the library's kernels
     U_mlp = None
     net = None
@@ -943,6 +960,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-halo path")
+    ap.add_argument("--no-filter", action="store_true", help="skip the filtered path")
     ap.add_argument("--series", type=int, default=0,
                     help="run this many steps with the FP64 diagnostics reduced after every step")
     ap.add_argument("--series-out", default=None, help="CSV file for --series")

@@ -668,12 +668,13 @@ atns_status enqueue_filter(atns_ctx* c, int fin, int halo, const long long* nste
     for (int m = 0; m < 6; ++m) f.ah[m] = c->fah[m];
     f.alpha = c->cfg.filter_alpha;
     const int pa = d == 0 ? 1 : 0, qa = d == 2 ? 1 : 2;
-    int max_lines = 1, max_len = 1;
+    int max_lines = 1, max_len = 1, min_len = kFilterMaxLen;
     for (const BlockDev& B : c->blocks) {
       max_lines = std::max(max_lines, B.s[pa] * B.s[qa]);
       max_len = std::max(max_len, B.s[d]);
+      min_len = std::min(min_len, B.s[d]);
     }
-    HIP_TRY(c, launch_filter_pass<T>(f, c->nb, max_lines, max_len, s));
+    HIP_TRY(c, launch_filter_pass<T>(f, c->nb, max_lines, min_len, max_len, s));
   }
   if (c->ring) HIP_TRY(c, launch_ring_fill<T>(base_params<T>(c), U, slot, c->nb, s, nstep));
   return ATNS_OK;

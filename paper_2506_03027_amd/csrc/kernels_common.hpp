@@ -342,29 +342,25 @@ __device__ __forceinline__ RingColumn ring_column(const BlockDev* __restrict__ B
   return r;
 }
 
-// Write u[5], the new value of owned point (lx, ly, lz), into every boundary
-// layer of block B in ring slot `slot` that contains it: the column's x/y
-// layers (rc) at plane lz, and, at the planes within H (faces) or 2 (edges)
-// of a z face, the z-face layer and the xz and yz edge layers.  lz is the
-// plane of the whole workgroup, so the z tests are uniform.  act: the thread
-// holds an owned point.  Readers find these values through the region
-// offsets of layout.hpp (roff), so the layer layout here is the one
-// build_layout() assigns.
-template <typename T>
-__device__ __forceinline__ void ring_write_col(const BlockDev* __restrict__ B, const RingColumn& rc, int H,
-                                               bool act, int lx, int ly, int lz, const T u[5],
-                                               T* __restrict__ slot) {
-  if (!act) return;
+// Every boundary layer of block B in ring slot `slot` that contains owned
+// point (lx, ly, lz): the column's x/y layers (rc) at plane lz, and, at the
+// planes within H (faces) or 2 (edges) of a z face, the z-face layer and the
+// xz and yz edge layers.  put(w, vs) receives the address of variable 0 of
+// the point in one layer and the variable stride there.  lz is the plane of
+// the whole workgroup (or a compile-time plane), so the z tests are
+// uniform.  Readers find these values through the region offsets of
+// layout.hpp (roff), so the layer layout here is the one build_layout()
+// assigns.
+template <typename T, typename F>
+__device__ __forceinline__ void ring_visit(const BlockDev* __restrict__ B, const RingColumn& rc, int H, int lx,
+                                           int ly, int lz, T* __restrict__ slot, F&& put) {
   const int sx = B->s[0], sy = B->s[1], sz = B->s[2];
   // x and y faces and the xy edge: the layer holds every plane of the block
   const int zs[5] = {sy * H, sy * H, H * sx, H * sx, 4};
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
     if (rc.off[j] < 0) continue;
-    const int vs = zs[j] * sz;
-    T* w = slot + B->lay[rc.slot[j]] + lz * zs[j] + rc.off[j];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) w[v * vs] = u[v];
+    put(slot + B->lay[rc.slot[j]] + lz * zs[j] + rc.off[j], zs[j] * sz);
   }
   // z faces and the xz / yz edges
   const int izf = lz < H ? lz : (lz >= sz - H ? lz - (sz - H) : -1);
@@ -375,10 +371,7 @@ __device__ __forceinline__ void ring_write_col(const BlockDev* __restrict__ B, c
     const int s = lo ? 4 : 5;
     if (B->lay[s] >= 0) {
       const int iz = lo ? lz : lz - (sz - H);
-      const int vs = H * sy * sx;
-      T* w = slot + B->lay[s] + (iz * sy + ly) * sx + lx;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) w[v * vs] = u[v];
+      put(slot + B->lay[s] + (iz * sy + ly) * sx + lx, H * sy * sx);
     }
     if (lo ? lz >= 2 : lz < sz - 2) continue;
     const int iz2 = lo ? lz : lz - (sz - 2);
@@ -387,9 +380,7 @@ __device__ __forceinline__ void ring_write_col(const BlockDev* __restrict__ B, c
       const int se = 10 + ex + 2 * (lo ? 0 : 1);
       if (B->lay[se] >= 0) {
         const int ix = ex == 0 ? lx : lx - (sx - 2);
-        T* w = slot + B->lay[se] + (iz2 * sy + ly) * 2 + ix;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) w[v * (4 * sy)] = u[v];
+        put(slot + B->lay[se] + (iz2 * sy + ly) * 2 + ix, 4 * sy);
       }
     }
     const int ey = ly < 2 ? 0 : (ly >= sy - 2 ? 1 : -1);
@@ -397,12 +388,30 @@ __device__ __forceinline__ void ring_write_col(const BlockDev* __restrict__ B, c
       const int se = 14 + ey + 2 * (lo ? 0 : 1);
       if (B->lay[se] >= 0) {
         const int iy = ey == 0 ? ly : ly - (sy - 2);
-        T* w = slot + B->lay[se] + (iz2 * 2 + iy) * sx + lx;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) w[v * (4 * sx)] = u[v];
+        put(slot + B->lay[se] + (iz2 * 2 + iy) * sx + lx, 4 * sx);
       }
     }
   }
+}
+
+// Write u[5], the new value of owned point (lx, ly, lz), into every ring
+// layer that contains it.  act: the thread holds an owned point.
+template <typename T>
+__device__ __forceinline__ void ring_write_col(const BlockDev* __restrict__ B, const RingColumn& rc, int H,
+                                               bool act, int lx, int ly, int lz, const T u[5],
+                                               T* __restrict__ slot) {
+  if (!act) return;
+  ring_visit(B, rc, H, lx, ly, lz, slot, [&](T* w, int vs) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[v * vs] = u[v];
+  });
+}
+
+// The same for one variable v of the point.
+template <typename T>
+__device__ __forceinline__ void ring_write_var(const BlockDev* __restrict__ B, const RingColumn& rc, int H, int lx,
+                                               int ly, int lz, int v, T val, T* __restrict__ slot) {
+  ring_visit(B, rc, H, lx, ly, lz, slot, [&](T* w, int vs) { w[v * vs] = val; });
 }
 
 // 1 / a: IEEE division in FP64; in FP32 the hardware reciprocal estimate

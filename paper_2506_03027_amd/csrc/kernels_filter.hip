@@ -105,15 +105,164 @@ __global__ void __launch_bounds__(kFilterLines) filter_pass_kernel(const FilterA
   }
 }
 
+// The same pass when every block has LEN points along the pass axis: the
+// line (with its ten halo values) and the forward-eliminated values live in
+// registers, all of the line's loads are issued before any arithmetic, and
+// the arithmetic is that of filter_pass_kernel, in the same order.  Along x,
+// where a line is a row of contiguous values, the workgroup's 64 rows pass
+// through LDS so that loads and stores run along rows.
+template <typename T, int LEN, int DIR>
+__global__ void __launch_bounds__(kFilterLines) filter_pass_fixed_kernel(const FilterArgs<T> f) {
+  constexpr int RS = LEN + 1;                      // padded LDS row
+  constexpr int TL = DIR == 0 ? kFilterLines * RS : 1;
+  __shared__ T tile[TL];
+  __shared__ int rowoff[kFilterLines];             // row starts relative to the first row
+  const BlockDev* __restrict__ B = f.blocks + blockIdx.y;
+  constexpr int d = DIR;
+  const int pa = d == 0 ? 1 : 0, qa = d == 2 ? 1 : 2;
+  const int lines = B->s[pa] * B->s[qa];
+  const int l0 = blockIdx.x * kFilterLines;
+  if (l0 >= lines) return;                         // whole workgroup
+  // lanes past the block's last line work on that line and store nothing
+  const bool act = l0 + (int)threadIdx.x < lines;
+  const int li = act ? l0 + (int)threadIdx.x : lines - 1;
+  int loc[3];
+  loc[d] = 0;
+  loc[pa] = li % B->s[pa];
+  loc[qa] = li / B->s[pa];
+
+  int halo = f.halo;
+  if (f.nstep) halo = (*f.nstep - 1 >= f.C) ? f.async_halo : kHaloSync;
+  const bool sync = halo == kHaloSync || f.fhalo == nullptr;
+
+  const long long nxy = (long long)f.n[0] * f.n[1];
+  const long long st = d == 0 ? 1 : (d == 1 ? f.n[0] : nxy);
+  const long long g0 = (long long)(B->o[2] + loc[2]) * nxy + (long long)(B->o[1] + loc[1]) * f.n[0] +
+                       (B->o[0] + loc[0]);
+  const int rows = min(kFilterLines, lines - l0);  // rows of this workgroup (x pass)
+  // x pass: the first row's start (the same for every lane) and each row's
+  // offset from it, so the staging addresses are one base plus 32 bits
+  const long long gfirst = (long long)(B->o[2] + l0 / B->s[1]) * nxy + (long long)(B->o[1] + l0 % B->s[1]) * f.n[0] +
+                           B->o[0];
+  if (d == 0) {
+    rowoff[threadIdx.x] = (int)(g0 - gfirst);
+    __syncthreads();
+  }
+  const int H = f.H;
+  long long lay_lo = 0, lay_hi = 0, vs = 0, lo0 = 0, lstep = 0;
+  if (!sync) {
+    lay_lo = B->hoff[2 * d];
+    lay_hi = B->hoff[2 * d + 1];
+    if (d == 0) {
+      vs = (long long)B->s[2] * B->s[1] * H;
+      lo0 = ((long long)loc[2] * B->s[1] + loc[1]) * H;
+      lstep = 1;
+    } else if (d == 1) {
+      vs = (long long)B->s[2] * H * B->s[0];
+      lo0 = (long long)loc[2] * H * B->s[0] + loc[0];
+      lstep = B->s[0];
+    } else {
+      vs = (long long)H * B->s[1] * B->s[0];
+      lo0 = (long long)loc[1] * B->s[0] + loc[0];
+      lstep = (long long)B->s[1] * B->s[0];
+    }
+  }
+  const int od = B->o[d], nd = f.n[d];
+  const double al = f.alpha;
+
+  for (int v = 0; v < 5; ++v) {
+    const T* in = f.in + v * f.field;
+    T ph[LEN + 10];   // line positions -5 .. LEN+4
+    if (d == 0) {
+      // rows of this workgroup into LDS, each load instruction along rows
+      __syncthreads();
+      const T* in0 = in + gfirst;
+      const int c = threadIdx.x % LEN;
+#pragma unroll 8
+      for (int k = 0; k < LEN; ++k) {
+        const int r = k * (kFilterLines / LEN) + threadIdx.x / LEN;
+        if (r < rows) tile[r * RS + c] = in0[rowoff[r] + c];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < LEN + 10; ++j) {
+      const int i = j - 5;
+      if (i >= 0 && i < LEN)
+        ph[j] = d == 0 ? tile[threadIdx.x * RS + i] : in[g0 + i * st];
+      else if (sync)
+        ph[j] = in[g0 + (long long)(wrap(od + i, nd) - od) * st];
+      else if (i < 0)
+        ph[j] = f.fhalo[lay_lo + v * vs + lo0 + (long long)(i + H) * lstep];
+      else
+        ph[j] = f.fhalo[lay_hi + v * vs + lo0 + (long long)(i - LEN) * lstep];
+    }
+    double dq[LEN];
+    double dp = 0.0;
+#pragma unroll
+    for (int i = 0; i < LEN; ++i) {
+      double r = f.ah[0] * (double)ph[i + 5];
+#pragma unroll
+      for (int m = 1; m < 6; ++m) r = fma(f.ah[m], (double)ph[i + 5 + m] + (double)ph[i + 5 - m], r);
+      if (i == 0) r = fma(-al, (double)ph[4], r);
+      if (i == LEN - 1) r = fma(-al, (double)ph[LEN + 5], r);
+      dp = (r - al * dp) * f.inv[i];
+      dq[i] = dp;
+    }
+    T* out = f.out + v * f.field;
+    if (d == 0) __syncthreads();   // every lane has read its row from the tile
+    double x = 0.0;
+#pragma unroll
+    for (int i = LEN - 1; i >= 0; --i) {
+      x = i == LEN - 1 ? dq[i] : dq[i] - f.cp[i] * x;
+      const T val = (T)x;
+      if (d == 0)
+        tile[threadIdx.x * RS + i] = val;
+      else if (act)
+        out[g0 + i * st] = val;
+    }
+    if (d == 0) {
+      __syncthreads();
+      T* out0 = out + gfirst;
+      const int c = threadIdx.x % LEN;
+#pragma unroll 8
+      for (int k = 0; k < LEN; ++k) {
+        const int r = k * (kFilterLines / LEN) + threadIdx.x / LEN;
+        if (r < rows) out0[rowoff[r] + c] = tile[r * RS + c];
+      }
+    }
+  }
+}
+
 template <typename T>
-hipError_t launch_filter_pass(const FilterArgs<T>& f, int nblocks, int max_lines, int max_len, hipStream_t s) {
+hipError_t launch_filter_pass(const FilterArgs<T>& f, int nblocks, int max_lines, int min_len, int max_len,
+                              hipStream_t s) {
   if (max_len < 1 || max_len > kFilterMaxLen || max_lines < 1) return hipErrorInvalidValue;
   dim3 grid((max_lines + kFilterLines - 1) / kFilterLines, nblocks), block(kFilterLines);
+  if (filter_pass_fixed(min_len, max_len)) {
+#define ATNS_FILTER_FIXED(LEN)                                                             \
+  do {                                                                                     \
+    if (f.dir == 0)                                                                        \
+      filter_pass_fixed_kernel<T, LEN, 0><<<grid, block, 0, s>>>(f);                       \
+    else if (f.dir == 1)                                                                   \
+      filter_pass_fixed_kernel<T, LEN, 1><<<grid, block, 0, s>>>(f);                       \
+    else                                                                                   \
+      filter_pass_fixed_kernel<T, LEN, 2><<<grid, block, 0, s>>>(f);                       \
+  } while (0)
+    if (max_len == 8)
+      ATNS_FILTER_FIXED(8);
+    else if (max_len == 16)
+      ATNS_FILTER_FIXED(16);
+    else
+      ATNS_FILTER_FIXED(32);
+#undef ATNS_FILTER_FIXED
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)max_len * kFilterLines * sizeof(double);
   filter_pass_kernel<T><<<grid, block, lds, s>>>(f);
   return hipGetLastError();
 }
-template hipError_t launch_filter_pass<float>(const FilterArgs<float>&, int, int, int, hipStream_t);
-template hipError_t launch_filter_pass<double>(const FilterArgs<double>&, int, int, int, hipStream_t);
+template hipError_t launch_filter_pass<float>(const FilterArgs<float>&, int, int, int, int, hipStream_t);
+template hipError_t launch_filter_pass<double>(const FilterArgs<double>&, int, int, int, int, hipStream_t);
 
 }  // namespace atns

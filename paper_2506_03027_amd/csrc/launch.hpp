@@ -51,11 +51,17 @@ template <typename T>
 hipError_t launch_ring_fill(const StageParams<T>& p, const T* U, int slot, int nblocks, hipStream_t s,
                             const long long* nstep = nullptr);
 // One pass of the block-local filter along axis f.dir: max_lines, the most
-// lines of one block along the axis; max_len, the longest block side along
-// it (at most kFilterMaxLen; the launch's LDS holds max_len x 64 doubles).
+// lines of one block along the axis; min_len and max_len, the shortest and
+// longest block side along it (at most kFilterMaxLen).  Blocks of one common
+// side of 8, 16 or 32 take a register-only kernel; otherwise the launch's
+// LDS holds max_len x 64 doubles.
 constexpr int kFilterMaxLen = 256;
+inline bool filter_pass_fixed(int min_len, int max_len) {
+  return min_len == max_len && (max_len == 8 || max_len == 16 || max_len == 32);
+}
 template <typename T>
-hipError_t launch_filter_pass(const FilterArgs<T>& f, int nblocks, int max_lines, int max_len, hipStream_t s);
+hipError_t launch_filter_pass(const FilterArgs<T>& f, int nblocks, int max_lines, int min_len, int max_len,
+                              hipStream_t s);
 // Workgroups (and FP64 partial sets of 7) of the diagnostics reduction; the
 // allocation-free form keeps its partials in a fixed device array of this size.
 constexpr int kDiagMaxParts = 1024;

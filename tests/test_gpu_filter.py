@@ -37,13 +37,18 @@ def rough_state(n, seed, ndim=3):
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("alpha", [0.499, 0.3])
-@pytest.mark.parametrize("case", ["3d_uneven", "2d"])
+@pytest.mark.parametrize("case", ["3d_uneven", "3d_blocks32", "2d"])
 def test_filter_state_matches_oracle(case, alpha, precision):
+    # uneven blocks take the general kernel; blocks of one side 8, 16 or 32
+    # along an axis the register-only one (32^3 blocks here, 16 in 2-D x)
     need_gpu()
     announce("filter state", case, alpha, precision)
     if case == "3d_uneven":
         n = (32, 32, 24)
         spec = dict(n=n, length=L3, nblk=(2, 2, 2), split=([13, 19], [16, 16], [10, 14]))
+    elif case == "3d_blocks32":
+        n = (64, 64, 32)
+        spec = dict(n=n, length=L3, nblk=(2, 2, 1))
     else:
         n = (32, 24, 1)
         spec = dict(n=n, length=L3, ndim=2, nblk=(2, 2, 1))
@@ -62,7 +67,7 @@ def test_filter_state_matches_oracle(case, alpha, precision):
     g.close()
 
 
-def tgv_case(mode, rk, n=(24, 24, 24)):
+def tgv_case(mode, rk, n=(32, 32, 32)):
     """Taylor-Green field with a little grid-scale noise (1e-4 of each
     variable's mean magnitude), which the filter removes."""
     U0 = inputs.tgv_state(n, mach=0.1)
