@@ -880,7 +880,7 @@ def headline_main(a, torch, cpu):
         net = train_halo_net(torch, w, dt)
         tr = net["training"]
         ratio = tr["halo_mse_mlp"] / tr["halo_mse_at"]
-        if not ratio < 1.0 - MLP_ACCEPT_DELTA:
+        if not ratio < 1.0 - MLP_ACCEPT_DELTA and not a.force_mlp:
             # nothing to gain: the correction kernel is not run
             out["at_mlp"] = {"accepted": False, "halo_mse_ratio": ratio, "accept_delta": MLP_ACCEPT_DELTA,
                              "ms_per_step": at["ms"] / a.steps, "value": value,
@@ -896,7 +896,9 @@ def headline_main(a, torch, cpu):
         flops = face_pts * 2.0 * (64 * 64 + 64 * 64 + 16 * 64)
         extra_ms = (ml["ms"] - at["ms"]) / a.steps
         tflops = flops / (extra_ms * 1e-3) / 1e12 if extra_ms > 0 else None
-        out["at_mlp"] = {"accepted": True, "halo_mse_ratio": net["training"]["halo_mse_mlp"] /
+        out["at_mlp"] = {"accepted": not (net["training"]["halo_mse_mlp"] / net["training"]["halo_mse_at"] >=
+                                          1.0 - MLP_ACCEPT_DELTA), "forced": bool(a.force_mlp),
+                         "halo_mse_ratio": net["training"]["halo_mse_mlp"] /
                          net["training"]["halo_mse_at"], "accept_delta": MLP_ACCEPT_DELTA,
                          "value": npts * stages * a.steps / (ml["ms"] * 1e-3), "ms_per_step": ml["ms"] / a.steps,
                          "tau": net["tau"], "applied": ml["stats"][0], "fallback": ml["stats"][1],
@@ -961,6 +963,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-halo path")
     ap.add_argument("--no-filter", action="store_true", help="skip the filtered path")
+    ap.add_argument("--force-mlp", action="store_true",
+                    help="run the learned halo even when the acceptance test rejects it (to measure its cost)")
     ap.add_argument("--series", type=int, default=0,
                     help="run this many steps with the FP64 diagnostics reduced after every step")
     ap.add_argument("--series-out", default=None, help="CSV file for --series")
