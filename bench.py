@@ -806,6 +806,54 @@ def equal_accuracy(torch, w, dt, total, U_ref):
     return {"grid_2h": list(n2), "rel_l2_2h_vs_h": e2h, "fp64_sa_disc_err_est": e2h / 15.0}
 
 
+# Errors against the exact solution within this relative margin of each
+# other count as equal accuracy.
+EQUAL_ACCURACY_TOL = 0.05
+
+
+def equal_accuracy_vortex(torch):
+    """FP32 AT against FP64 SA where an exact solution exists: the 3-D
+    isentropic vortex of the 128^3 Euler workload (4 x 4 x 4 blocks of 32^3,
+    SAA L = 4) advanced to T = 1, FP32 AT plain and with compensated steps.
+    Every run is compared with the translated exact field; where an FP32
+    run's error equals FP64 SA's, the ratio of their step times is a speed-up
+    at equal accuracy."""
+    w = inputs.WORKLOADS["vortex3d_128"]
+    nsteps = int(math.ceil(1.0 / coarse_dt(w)))
+    dt = 1.0 / nsteps
+    exact = inputs.vortex_state(w["n"], w["length"], 3, t=1.0)
+    en = float(np.linalg.norm(exact))
+    res = {"workload": "vortex3d_128", "T": 1.0, "steps": nsteps, "dt": dt,
+           "reference": "exact translated vortex (periodic images not included)"}
+    for key, prec, mode, comp in (("fp32_at", atns.F32, "at", False), ("fp32_at_compensated", atns.F32, "at", True),
+                                  ("fp64_sa", atns.F64, "sa", False)):
+        g = make_solver(w, prec, mode)
+        g.set_compensation(comp)
+        g.set_dt(dt)
+        g.init_case(atns.CASE_VORTEX)
+        g.autotune(reps=5, cache=TUNE_CACHE)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.step(nsteps)
+        e1.record()
+        torch.cuda.synchronize()
+        U = g.get_state().double().cpu().numpy()
+        g.close()
+        res[key] = {"ms_per_step": e0.elapsed_time(e1) / nsteps,
+                    "rel_l2_vs_exact": float(np.linalg.norm(U - exact)) / en}
+    es = res["fp64_sa"]["rel_l2_vs_exact"]
+    for key in ("fp32_at", "fp32_at_compensated"):
+        r = res[key]
+        r["error_ratio_vs_fp64_sa"] = r["rel_l2_vs_exact"] / es
+        r["equal_accuracy"] = abs(r["error_ratio_vs_fp64_sa"] - 1.0) <= EQUAL_ACCURACY_TOL
+        r["speedup_vs_fp64_sa"] = res["fp64_sa"]["ms_per_step"] / r["ms_per_step"]
+    res["equal_accuracy_tolerance"] = EQUAL_ACCURACY_TOL
+    best = [k for k in ("fp32_at", "fp32_at_compensated") if res[k]["equal_accuracy"]]
+    res["speedup_at_equal_accuracy"] = max(res[k]["speedup_vs_fp64_sa"] for k in best) if best else None
+    return res
+
+
 def headline_main(a, torch, cpu):
     """FP32 AT (the metric), FP32 AT with the learned halo and FP64 SA on the
     workload from the same initial field, dt and step count; the L2 of each
@@ -906,6 +954,8 @@ def headline_main(a, torch, cpu):
                          "extra_ms_per_step": extra_ms, "achieved_tflops": tflops,
                          "mfma_frac_of_bf16_peak": (tflops / 2500.0) if tflops else None,
                          "training": net["training"]}
+    if not a.no_eqvortex:
+        out["equal_accuracy_vortex"] = equal_accuracy_vortex(torch)
     probe = hbm_probe(torch)
     out["hbm_probe"] = probe
     out["roofline"]["frac_of_probe"] = achieved / probe["GBps"]
@@ -963,6 +1013,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-halo path")
     ap.add_argument("--no-filter", action="store_true", help="skip the filtered path")
+    ap.add_argument("--no-eqvortex", action="store_true",
+                    help="skip the equal-accuracy comparison on the vortex with an exact solution")
     ap.add_argument("--force-mlp", action="store_true",
                     help="run the learned halo even when the acceptance test rejects it (to measure its cost)")
     ap.add_argument("--series", type=int, default=0,

@@ -220,6 +220,18 @@ atns_status atns_rhs(atns_ctx* ctx, int32_t stage, void* dev_R);
  * go into the ring. */
 atns_status atns_rk_step(atns_ctx* ctx, int32_t nsteps);
 
+/* Compensated classical RK4 steps (on != 0).  The accumulator then holds
+ * only the step's increments, and the last stage forms U^{n+1} = U^n +
+ * (increments + c) with Knuth's TwoSum, keeping the sum's rounding error c
+ * per point and variable for the next step (a device array the size of the
+ * state, allocated on the first call).  Single-precision state so carries
+ * the time integration to about twice its precision, at the cost of reading
+ * U^n and reading and writing c in the last stage.  c is cleared whenever a
+ * state is set (atns_set_state, atns_init_case, atns_restore); checkpoints
+ * do not hold it.  EINVAL for other integrators, with the filter, and later
+ * in atns_step_async.  Default off. */
+atns_status atns_set_compensation(atns_ctx* ctx, int32_t on);
+
 /* Apply the configured filter (Sec. 2; a reading, since the paper does not
  * define it across PEs) to the current state in place, with synchronous
  * halos, and rewrite the ring slot of the current step.  Along each axis in

@@ -44,7 +44,7 @@ EXPORTS = ["atns_version", "atns_create", "atns_destroy", "atns_last_error", "at
            "atns_hbm_probe", "atns_host_weights", "atns_host_delays", "atns_batch_create",
            "atns_batch_destroy", "atns_batch_last_error", "atns_batch_member", "atns_batch_set_tiles",
            "atns_batch_autotune", "atns_batch_step", "atns_init_case", "atns_checkpoint", "atns_restore",
-           "atns_filter_state", "atns_host_filter_coefficients"]
+           "atns_filter_state", "atns_host_filter_coefficients", "atns_set_compensation"]
 MLP_PARAMS = 9360
 
 
@@ -111,6 +111,7 @@ def lib():
             "atns_mlp_stats": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], i32),
             "atns_host_weights": ([i32, i32, i32, vp], i32),
             "atns_filter_state": ([vp], i32),
+            "atns_set_compensation": ([vp, i32], i32),
             "atns_host_filter_coefficients": ([dbl, vp], i32),
             "atns_host_delays": ([i32, i32, i64, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(i32)], i32),
             "atns_batch_create": ([ctypes.POINTER(Config), i32, vp, ctypes.POINTER(vp)], i32),
@@ -303,6 +304,11 @@ class Solver:
 
     def step(self, nsteps=1):
         _check(lib().atns_rk_step(self.ctx, int(nsteps)), self.ctx)
+
+    def set_compensation(self, on):
+        """Compensated classical RK4 steps (the state update's rounding error
+        carried to the next step)."""
+        _check(lib().atns_set_compensation(self.ctx, 1 if on else 0), self.ctx)
 
     def filter_state(self):
         """The configured filter applied to the current state (synchronous halos)."""

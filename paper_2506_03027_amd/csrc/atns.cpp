@@ -59,6 +59,8 @@ struct atns_ctx {
   double* d_finv = nullptr;          // filter: forward-elimination factors
   double* d_fcp = nullptr;
   double fah[6] = {0, 0, 0, 0, 0, 0};   // filter: a_0, a_1/2, ..., a_5/2
+  void* comp = nullptr;              // compensated RK4: rounding error carried per point
+  bool comp_on = false;
   HaloRegion* d_regions = nullptr;
   HaloWork* d_work = nullptr;
   int nwork = 0;
@@ -481,7 +483,8 @@ hipError_t launch_stage(atns_ctx* c, const StageParams<T>& p, int kind) {
 // Whether the RK4 stages run as two fused pairs: 3-D Euler, classical RK4,
 // single precision, and a tile shape the pair kernel is built for.
 bool pairs_apply(const atns_ctx* c) {
-  if (!c->fuse || c->cfg.physics != ATNS_EULER || c->cfg.ndim != 3 || c->cfg.rk != ATNS_RK4 || c->esz != 4)
+  if (!c->fuse || c->cfg.physics != ATNS_EULER || c->cfg.ndim != 3 || c->cfg.rk != ATNS_RK4 || c->esz != 4 ||
+      c->comp_on)
     return false;
   const int tx = c->tile[0], ty = c->tile[1];
   return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 16 && ty == 8) || (tx == 32 && ty == 16);
@@ -606,7 +609,10 @@ StageParams<T> graph_stage_params(const atns_ctx* c, int e, int* kind, bool fuse
     *kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
     p.cA = rk.b[e];
     p.cB = e < 3 ? rk.a[e + 1][e] : 0.0;
-    p.fold = e == 2 ? 1 : 0;   // U^n joins the accumulator in the last middle stage
+    // U^n joins the accumulator in the last middle stage, or, compensated,
+    // the last stage adds it with its carried rounding error
+    p.fold = (e == 2 && !c->comp_on) ? 1 : 0;
+    p.comp = c->comp_on ? (T*)c->comp : nullptr;
   } else {
     const int cur = (c->cur + e) & 1;
     p.Y = (const T*)c->X[cur];
@@ -793,7 +799,10 @@ atns_status do_steps_impl(atns_ctx* c, int nsteps, bool* on_graph) {
         kind = e == 0 ? kRK4First : (e == 3 ? kRK4Last : kRK4Mid);
         p.cA = rk.b[e];
         p.cB = e < 3 ? rk.a[e + 1][e] : 0.0;
-        p.fold = e == 2 ? 1 : 0;   // U^n joins the accumulator in the last middle stage
+        // U^n joins the accumulator in the last middle stage, or, compensated,
+        // the last stage adds it with its carried rounding error
+        p.fold = (e == 2 && !c->comp_on) ? 1 : 0;
+        p.comp = c->comp_on ? (T*)c->comp : nullptr;
       } else {
         p.Y = (const T*)c->X[c->cur];
         p.Yout = (T*)c->X[1 - c->cur];
@@ -857,7 +866,7 @@ void release(atns_ctx* c) {
                   c->d_face_regions, c->d_face_chunks, c->d_W0at, c->net.params, c->net.w1, c->net.w2,
                   c->net.w3, c->d_adam_m, c->d_adam_v, c->d_grad, c->d_part, c->d_loss_part, c->d_loss,
                   c->d_X, c->d_Y, c->d_counters, c->d_prog, c->d_abort, c->d_btiles, c->d_tile_begin,
-                  c->d_reg_begin, c->d_async_ps, c->d_finv, c->d_fcp};
+                  c->d_reg_begin, c->d_async_ps, c->d_finv, c->d_fcp, c->comp};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   c->ring = nullptr;
@@ -1012,6 +1021,7 @@ atns_status adopt_state(atns_ctx* c, int64_t step) {
   c->step = step;
   c->state_set = true;
   c->nstep_synced = false;
+  if (c->comp) HIP_TRY(c, hipMemsetAsync(c->comp, 0, (size_t)c->field * 5 * c->esz, c->stream));
   if (c->ring) {
     const int slot = (int)(step % c->D);
     if (c->esz == 4) {
@@ -1269,6 +1279,22 @@ atns_status atns_set_fusion(atns_ctx* c, int32_t on) {
   });
 }
 
+atns_status atns_set_compensation(atns_ctx* c, int32_t on) {
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    if (on && c->cfg.rk != ATNS_RK4) return fail(c, ATNS_EINVAL, "compensated steps are built for classical RK4");
+    if (on && c->cfg.filter) return fail(c, ATNS_EINVAL, "compensated steps are not combined with the filter");
+    if (on && !c->comp) {
+      const size_t bytes = (size_t)c->field * 5 * c->esz;
+      if (hipMalloc(&c->comp, bytes) != hipSuccess) return fail(c, ATNS_ENOMEM, "compensation allocation failed");
+      HIP_TRY(c, hipMemsetAsync(c->comp, 0, bytes, c->stream));
+    }
+    c->comp_on = on != 0;
+    drop_graphs(c);
+    return ATNS_OK;
+  });
+}
+
 atns_status atns_set_halo_fusion(atns_ctx* c, int32_t on) {
   return guarded(c, [&]() -> atns_status {
     if (!c) return fail(c, ATNS_EINVAL, "null context");
@@ -1422,6 +1448,7 @@ atns_status atns_step_async(atns_ctx* c, int32_t nsteps, int64_t spin_limit, int
       return fail(c, ATNS_EINVAL, "free-running steps need ATNS_RK4 or ATNS_LSERK2");
     if (c->mlp_on) return fail(c, ATNS_EINVAL, "the learned halo is not applied in free-running steps");
     if (c->cfg.filter) return fail(c, ATNS_EINVAL, "the filter is not applied in free-running steps");
+  if (c->comp_on) return fail(c, ATNS_EINVAL, "compensated steps are not built for free-running steps");
     if (!c->state_set) return fail(c, ATNS_ESTATE, "state not set");
     if (!(c->dt > 0)) return fail(c, ATNS_ESTATE, "dt not set");
     if (c->step < c->C + c->cfg.L - 1) return fail(c, ATNS_ESTATE, "history shorter than C + L - 1 levels");

@@ -426,6 +426,19 @@ __device__ __forceinline__ float recip<float>(float a) {
   return fmaf(r, fmaf(-a, r, 1.0f), r);
 }
 
+// u0 + d with the rounding error of the sum carried in c across steps
+// (Knuth's TwoSum on d + c): returns the new value and leaves in c the part
+// of u0 + d + c that the returned value misses.
+template <typename T>
+__device__ __forceinline__ T comp_add(T u0, T d, T& c) {
+#pragma clang fp contract(off)
+  const T y = d + c;
+  const T s = u0 + y;
+  const T bb = s - u0;
+  c = (u0 - (s - bb)) + (y - bb);
+  return s;
+}
+
 // Operands the RK epilogue reads at a point besides the stage input: the
 // accumulator / Q register and, for the middle RK4 stages, U^n.  Loaded one
 // plane ahead so their latency hides behind the stencil work.
@@ -435,7 +448,7 @@ __device__ __forceinline__ void epilogue_load(const StageParams<T>& p, long long
   for (int v = 0; v < 5; ++v) {
     const long long i = v * p.field + g;
     if (KIND == kRK4Mid || KIND == kRK4Last || KIND == kLSMid) accv[v] = p.acc[i];
-    if (KIND == kRK4Mid) u0v[v] = p.U0[i];
+    if (KIND == kRK4Mid || (KIND == kRK4Last && p.comp)) u0v[v] = p.U0[i];
   }
 }
 
@@ -460,7 +473,13 @@ __device__ __forceinline__ void epilogue_pre(const StageParams<T>& p, long long 
       p.acc[i] = p.fold ? u0v[v] + a : a;
       out[v] = u0v[v] + cB * dr;
     } else if (KIND == kRK4Last) {
-      out[v] = accv[v] + cA * (dt * r);
+      if (p.comp) {
+        T c = p.comp[i];
+        out[v] = comp_add<T>(u0v[v], accv[v] + cA * (dt * r), c);
+        p.comp[i] = c;
+      } else {
+        out[v] = accv[v] + cA * (dt * r);
+      }
     } else if (KIND == kLSFirst) {
       const T q = dt * r;
       p.acc[i] = q;
@@ -474,46 +493,6 @@ __device__ __forceinline__ void epilogue_pre(const StageParams<T>& p, long long 
   }
 }
 
-// RK epilogue at global index g; Y is the stage input at the point, R the
-// right-hand side.  Returns the written next value in out[] (for the ring).
-template <typename T, int KIND>
-__device__ __forceinline__ void epilogue(const StageParams<T>& p, long long g, const T Y[5],
-                                         const T R[5], T out[5]) {
-  const T dt = (T)p.dt, cA = (T)p.cA, cB = (T)p.cB;
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const long long i = v * p.field + g;
-    const T r = R[v];
-    if (KIND == kRhsOnly) {
-      out[v] = r;
-      p.Yout[i] = r;
-    } else if (KIND == kRK4First) {
-      const T dr = dt * r;
-      p.acc[i] = cA * dr;
-      out[v] = Y[v] + cB * dr;
-      p.Yout[i] = out[v];
-    } else if (KIND == kRK4Mid) {
-      const T dr = dt * r;
-      const T a = p.acc[i] + cA * dr;
-      p.acc[i] = p.fold ? p.U0[i] + a : a;
-      out[v] = p.U0[i] + cB * dr;
-      p.Yout[i] = out[v];
-    } else if (KIND == kRK4Last) {
-      out[v] = p.acc[i] + cA * (dt * r);
-      p.Yout[i] = out[v];
-    } else if (KIND == kLSFirst) {
-      const T q = dt * r;
-      p.acc[i] = q;
-      out[v] = Y[v] + cB * q;
-      p.Yout[i] = out[v];
-    } else {  // kLSMid
-      const T q = cA * p.acc[i] + dt * r;
-      p.acc[i] = q;
-      out[v] = Y[v] + cB * q;
-      p.Yout[i] = out[v];
-    }
-  }
-}
 
 // Free-running asynchronous steps (the body shared by the Euler and
 // Navier-Stokes kernels): workgroup b owns block b for the whole

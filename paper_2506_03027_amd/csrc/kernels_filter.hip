@@ -140,11 +140,16 @@ __global__ void __launch_bounds__(kFilterLines) filter_pass_fixed_kernel(const F
   const long long g0 = (long long)(B->o[2] + loc[2]) * nxy + (long long)(B->o[1] + loc[1]) * f.n[0] +
                        (B->o[0] + loc[0]);
   const int rows = min(kFilterLines, lines - l0);  // rows of this workgroup (x pass)
+  // x pass over single-precision rows that start on 16-byte boundaries: each
+  // lane reads and writes its own row four values at a time; other x passes
+  // stage the rows through LDS
+  const bool vec4 = d == 0 && sizeof(T) == 4 && LEN % 4 == 0 && (B->o[0] & 3) == 0 && (f.n[0] & 3) == 0;
+  const bool staged = d == 0 && !vec4;
   // x pass: the first row's start (the same for every lane) and each row's
   // offset from it, so the staging addresses are one base plus 32 bits
   const long long gfirst = (long long)(B->o[2] + l0 / B->s[1]) * nxy + (long long)(B->o[1] + l0 % B->s[1]) * f.n[0] +
                            B->o[0];
-  if (d == 0) {
+  if (staged) {
     rowoff[threadIdx.x] = (int)(g0 - gfirst);
     __syncthreads();
   }
@@ -173,7 +178,21 @@ __global__ void __launch_bounds__(kFilterLines) filter_pass_fixed_kernel(const F
   for (int v = 0; v < 5; ++v) {
     const T* in = f.in + v * f.field;
     T ph[LEN + 10];   // line positions -5 .. LEN+4
-    if (d == 0) {
+    if constexpr (sizeof(T) == 4) {
+      if (vec4) {
+        using V4 = float __attribute__((ext_vector_type(4)));
+        const V4* row = reinterpret_cast<const V4*>(in + g0);
+#pragma unroll
+        for (int q = 0; q < LEN / 4; ++q) {
+          const V4 x4 = row[q];
+          ph[5 + 4 * q] = x4.x;
+          ph[6 + 4 * q] = x4.y;
+          ph[7 + 4 * q] = x4.z;
+          ph[8 + 4 * q] = x4.w;
+        }
+      }
+    }
+    if (staged) {
       // rows of this workgroup into LDS, each load instruction along rows
       __syncthreads();
       const T* in0 = in + gfirst;
@@ -188,9 +207,9 @@ __global__ void __launch_bounds__(kFilterLines) filter_pass_fixed_kernel(const F
 #pragma unroll
     for (int j = 0; j < LEN + 10; ++j) {
       const int i = j - 5;
-      if (i >= 0 && i < LEN)
-        ph[j] = d == 0 ? tile[threadIdx.x * RS + i] : in[g0 + i * st];
-      else if (sync)
+      if (i >= 0 && i < LEN) {
+        if (!vec4) ph[j] = staged ? tile[threadIdx.x * RS + i] : in[g0 + i * st];
+      } else if (sync)
         ph[j] = in[g0 + (long long)(wrap(od + i, nd) - od) * st];
       else if (i < 0)
         ph[j] = f.fhalo[lay_lo + v * vs + lo0 + (long long)(i + H) * lstep];
@@ -210,18 +229,29 @@ __global__ void __launch_bounds__(kFilterLines) filter_pass_fixed_kernel(const F
       dq[i] = dp;
     }
     T* out = f.out + v * f.field;
-    if (d == 0) __syncthreads();   // every lane has read its row from the tile
+    if (staged) __syncthreads();   // every lane has read its row from the tile
     double x = 0.0;
+    T res[vec4 ? LEN : 1];
 #pragma unroll
     for (int i = LEN - 1; i >= 0; --i) {
       x = i == LEN - 1 ? dq[i] : dq[i] - f.cp[i] * x;
       const T val = (T)x;
-      if (d == 0)
+      if (vec4)
+        res[i] = val;
+      else if (staged)
         tile[threadIdx.x * RS + i] = val;
       else if (act)
         out[g0 + i * st] = val;
     }
-    if (d == 0) {
+    if constexpr (sizeof(T) == 4) {
+      if (vec4 && act) {
+        using V4 = float __attribute__((ext_vector_type(4)));
+        V4* row = reinterpret_cast<V4*>(out + g0);
+#pragma unroll
+        for (int q = 0; q < LEN / 4; ++q) row[q] = V4{res[4 * q], res[4 * q + 1], res[4 * q + 2], res[4 * q + 3]};
+      }
+    }
+    if (staged) {
       __syncthreads();
       T* out0 = out + gfirst;
       const int c = threadIdx.x % LEN;

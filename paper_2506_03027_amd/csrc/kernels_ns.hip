@@ -359,7 +359,9 @@ __device__ __forceinline__ void ns_tile_lean(const StageParams<T>& p, const Tile
   constexpr bool needA = KIND == kRK4Mid || KIND == kRK4Last || KIND == kLSMid;
   constexpr bool needU0 = KIND == kRK4Mid;
   T Yv[5] = {T(0), T(0), T(0), T(0), T(0)}, accv[5] = {T(0), T(0), T(0), T(0), T(0)};
-  T u0v[5] = {T(0), T(0), T(0), T(0), T(0)};
+  T u0v[5] = {T(0), T(0), T(0), T(0), T(0)}, cv[5] = {T(0), T(0), T(0), T(0), T(0)};
+  // the compensated last RK4 stage also reads U^n and the carried error
+  const bool comp = KIND == kRK4Last && p.comp != nullptr;
   auto epi_load = [&](int pz) {
     const long long zo = (long long)(B->o[2] + pz) * gplane;
 #pragma unroll
@@ -368,6 +370,10 @@ __device__ __forceinline__ void ns_tile_lean(const StageParams<T>& p, const Tile
       if (needY) Yv[v] = at_off(p.Y + o, toff);
       if (needA) accv[v] = at_off(p.acc + o, toff);
       if (needU0) u0v[v] = at_off(p.U0 + o, toff);
+      if (comp) {
+        u0v[v] = at_off(p.U0 + o, toff);
+        cv[v] = at_off(p.comp + o, toff);
+      }
     }
   };
   if (tact) epi_load(z0);
@@ -399,7 +405,13 @@ __device__ __forceinline__ void ns_tile_lean(const StageParams<T>& p, const Tile
           at_off(p.acc + o, toff) = p.fold ? u0v[v] + a : a;
           out[v] = fma(cB, dr, u0v[v]);
         } else if (KIND == kRK4Last) {
-          out[v] = fma(cA, dt * r, accv[v]);
+          if (comp) {
+            T c = cv[v];
+            out[v] = comp_add<T>(u0v[v], fma(cA, dt * r, accv[v]), c);
+            at_off(p.comp + o, toff) = c;
+          } else {
+            out[v] = fma(cA, dt * r, accv[v]);
+          }
         } else if (KIND == kLSFirst) {
           const T q = dt * r;
           at_off(p.acc + o, toff) = q;

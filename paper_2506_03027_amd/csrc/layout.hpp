@@ -181,6 +181,12 @@ struct StageParams {
   // anyway: two roundings of state-sized sums per step instead of four, at
   // no extra traffic.
   int fold;
+  // Compensated classical RK4 (comp != null, single-context steps): the
+  // accumulator holds the step's increments only (fold stays 0) and the last
+  // stage forms U^{n+1} = U^n + (increments + comp) with the sum's rounding
+  // error kept in comp for the next step (TwoSum), so the state is carried
+  // to about twice its precision.  U0 is U^n in the last stage too.
+  T* comp;
   int ring_write;        // write the boundary layers of the result
   // Halo assembly inside the first stage of a graph-captured step (fuse_halo
   // != 0): before its plane loop, each tile computes, for the halo points it

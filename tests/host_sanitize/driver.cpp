@@ -99,6 +99,7 @@ static void cpu_paths() {
   EXPECT(atns_rk_step(nullptr, 1) == ATNS_EINVAL, "step null");
   EXPECT(atns_rhs(nullptr, 0, nullptr) == ATNS_EINVAL, "rhs null");
   EXPECT(atns_filter_state(nullptr) == ATNS_EINVAL, "filter null");
+  EXPECT(atns_set_compensation(nullptr, 1) == ATNS_EINVAL, "compensation null");
   EXPECT(atns_set_dt(nullptr, 1.0) == ATNS_EINVAL, "dt null");
   size_t bytes = 0;
   EXPECT(atns_checkpoint(nullptr, nullptr, &bytes) == ATNS_EINVAL, "checkpoint null");
@@ -164,6 +165,9 @@ static void gpu_paths() {
   int32_t best[3];
   check(atns_autotune(c, 1, nullptr, best), "autotune", c);
   check(atns_rk_step(c, 2), "steps after tuning", c);
+  check(atns_set_compensation(c, 1), "compensation on", c);
+  check(atns_rk_step(c, 3), "compensated steps", c);
+  check(atns_set_compensation(c, 0), "compensation off", c);
   (void)hipFree(R);
   check(atns_destroy(c), "destroy", nullptr);
   std::printf("context lifecycle ok\n");
