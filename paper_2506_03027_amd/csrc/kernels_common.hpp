@@ -440,20 +440,23 @@ __device__ __forceinline__ T comp_add(T u0, T d, T& c) {
 }
 
 // Operands the RK epilogue reads at a point besides the stage input: the
-// accumulator / Q register and, for the middle RK4 stages, U^n.  Loaded one
-// plane ahead so their latency hides behind the stencil work.
-template <typename T, int KIND>
+// accumulator / Q register and, for the middle RK4 stages and the compensated
+// last one, U^n.  Loaded one plane ahead so their latency hides behind the
+// stencil work.  COMP (compensated last RK4 stage, p.comp != null) is a
+// template flag so that the plain last stage holds no registers for it.
+template <typename T, int KIND, bool COMP = false>
 __device__ __forceinline__ void epilogue_load(const StageParams<T>& p, long long g, T accv[5], T u0v[5]) {
+  static_assert(!COMP || KIND == kRK4Last, "compensation is a last-RK4-stage variant");
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     const long long i = v * p.field + g;
     if (KIND == kRK4Mid || KIND == kRK4Last || KIND == kLSMid) accv[v] = p.acc[i];
-    if (KIND == kRK4Mid || (KIND == kRK4Last && p.comp)) u0v[v] = p.U0[i];
+    if (KIND == kRK4Mid || COMP) u0v[v] = p.U0[i];
   }
 }
 
 // RK epilogue with preloaded operands (see epilogue_load).
-template <typename T, int KIND>
+template <typename T, int KIND, bool COMP = false>
 __device__ __forceinline__ void epilogue_pre(const StageParams<T>& p, long long g, const T Y[5], const T R[5],
                                              const T accv[5], const T u0v[5], T out[5]) {
   const T dt = (T)p.dt, cA = (T)p.cA, cB = (T)p.cB;
@@ -473,7 +476,7 @@ __device__ __forceinline__ void epilogue_pre(const StageParams<T>& p, long long 
       p.acc[i] = p.fold ? u0v[v] + a : a;
       out[v] = u0v[v] + cB * dr;
     } else if (KIND == kRK4Last) {
-      if (p.comp) {
+      if constexpr (COMP) {
         T c = p.comp[i];
         out[v] = comp_add<T>(u0v[v], accv[v] + cA * (dt * r), c);
         p.comp[i] = c;

@@ -37,7 +37,7 @@ __device__ __forceinline__ EulerLds<T, TX, TY>& euler_lds() {
 
 // FUSE: the kernel may assemble the step's halos in its first stage (the
 // per-launch stage kernels); the batch and free-running kernels never do.
-template <typename T, int TX, int TY, int KIND, bool FUSE = false>
+template <typename T, int TX, int TY, int KIND, bool FUSE = false, bool COMP = false>
 __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDev t) {
   // every apron point (4 per tile row and column) has a thread of its own
   static_assert(4 * (TX + TY) <= TX * TY, "tile shape too narrow for its apron");
@@ -120,7 +120,7 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
   const long long g0 = ((long long)(B->o[2] + t.z0) * p.n[1] + (B->o[1] + ly)) * p.n[0] + (B->o[0] + lx);
   const long long gplane = (long long)p.n[0] * p.n[1];
   T accv[5], u0v[5];
-  if (act) epilogue_load<T, KIND>(p, g0, accv, u0v);
+  if (act) epilogue_load<T, KIND, COMP>(p, g0, accv, u0v);
 
   for (int iz = 0; iz < t.nz; ++iz) {
     const int lz = t.z0 + iz;
@@ -187,17 +187,17 @@ __device__ __forceinline__ void euler_tile(const StageParams<T>& p, const TileDe
       }
       const long long g = g0 + iz * gplane;
       T out[5];
-      epilogue_pre<T, KIND>(p, g, uq[0], R, accv, u0v, out);
-      if (iz + 1 < t.nz) epilogue_load<T, KIND>(p, g + gplane, accv, u0v);
+      epilogue_pre<T, KIND, COMP>(p, g, uq[0], R, accv, u0v, out);
+      if (iz + 1 < t.nz) epilogue_load<T, KIND, COMP>(p, g + gplane, accv, u0v);
       if (ring_slot) ring_write_col(B, rcol, p.H, true, lx, ly, lz, out, ring_slot);
     }
   }
 }
 
-template <typename T, int TX, int TY, int KIND>
+template <typename T, int TX, int TY, int KIND, bool COMP = false>
 __global__ void __launch_bounds__(TX* TY) euler_stage_kernel(const StageParams<T> p) {
   const StageParams<T> q = resolve_step(p);
-  euler_tile<T, TX, TY, KIND, true>(q, p.tiles[blockIdx.x]);
+  euler_tile<T, TX, TY, KIND, true, COMP>(q, p.tiles[blockIdx.x]);
   if (p.step_end) finish_step(p.step_end, p.done);
 }
 
@@ -321,7 +321,12 @@ hipError_t launch_euler_shape(const StageParams<T>& p, int ntiles, int kind, hip
     case kRhsOnly: euler_stage_kernel<T, TX, TY, kRhsOnly><<<grid, block, 0, s>>>(p); break;
     case kRK4First: euler_stage_kernel<T, TX, TY, kRK4First><<<grid, block, 0, s>>>(p); break;
     case kRK4Mid: euler_stage_kernel<T, TX, TY, kRK4Mid><<<grid, block, 0, s>>>(p); break;
-    case kRK4Last: euler_stage_kernel<T, TX, TY, kRK4Last><<<grid, block, 0, s>>>(p); break;
+    case kRK4Last:
+      if (p.comp)
+        euler_stage_kernel<T, TX, TY, kRK4Last, true><<<grid, block, 0, s>>>(p);
+      else
+        euler_stage_kernel<T, TX, TY, kRK4Last><<<grid, block, 0, s>>>(p);
+      break;
     case kLSFirst: euler_stage_kernel<T, TX, TY, kLSFirst><<<grid, block, 0, s>>>(p); break;
     default: euler_stage_kernel<T, TX, TY, kLSMid><<<grid, block, 0, s>>>(p); break;
   }

@@ -215,7 +215,7 @@ __device__ __forceinline__ void ns_flux(const NsGrad<T>& s, int d, T ire, T kap,
   out[4] = fma(s.et + s.pres, ud, -(ire * work));
 }
 
-template <typename T, int TX, int TY, int KIND, int NDIM, bool CD2>
+template <typename T, int TX, int TY, int KIND, int NDIM, bool CD2, bool COMP>
 __device__ __forceinline__ void ns_tile_lean(const StageParams<T>& p, const TileDev t) {
 #pragma clang fp contract(off)
   using S = NsShape<T, TX, TY>;
@@ -357,11 +357,13 @@ __device__ __forceinline__ void ns_tile_lean(const StageParams<T>& p, const Tile
   // low-storage updates; the RK registers by stage kind as in epilogue_pre
   constexpr bool needY = KIND == kRK4First || KIND == kLSFirst || KIND == kLSMid || KIND == kRhsOnly;
   constexpr bool needA = KIND == kRK4Mid || KIND == kRK4Last || KIND == kLSMid;
+  // the compensated last RK4 stage (COMP) also reads U^n and the carried
+  // error, at the update itself rather than a plane ahead: their registers
+  // would not fit beside the z-queues
+  static_assert(!COMP || KIND == kRK4Last, "compensation is a last-RK4-stage variant");
   constexpr bool needU0 = KIND == kRK4Mid;
   T Yv[5] = {T(0), T(0), T(0), T(0), T(0)}, accv[5] = {T(0), T(0), T(0), T(0), T(0)};
-  T u0v[5] = {T(0), T(0), T(0), T(0), T(0)}, cv[5] = {T(0), T(0), T(0), T(0), T(0)};
-  // the compensated last RK4 stage also reads U^n and the carried error
-  const bool comp = KIND == kRK4Last && p.comp != nullptr;
+  T u0v[5] = {T(0), T(0), T(0), T(0), T(0)};
   auto epi_load = [&](int pz) {
     const long long zo = (long long)(B->o[2] + pz) * gplane;
 #pragma unroll
@@ -370,10 +372,6 @@ __device__ __forceinline__ void ns_tile_lean(const StageParams<T>& p, const Tile
       if (needY) Yv[v] = at_off(p.Y + o, toff);
       if (needA) accv[v] = at_off(p.acc + o, toff);
       if (needU0) u0v[v] = at_off(p.U0 + o, toff);
-      if (comp) {
-        u0v[v] = at_off(p.U0 + o, toff);
-        cv[v] = at_off(p.comp + o, toff);
-      }
     }
   };
   if (tact) epi_load(z0);
@@ -405,9 +403,9 @@ __device__ __forceinline__ void ns_tile_lean(const StageParams<T>& p, const Tile
           at_off(p.acc + o, toff) = p.fold ? u0v[v] + a : a;
           out[v] = fma(cB, dr, u0v[v]);
         } else if (KIND == kRK4Last) {
-          if (comp) {
-            T c = cv[v];
-            out[v] = comp_add<T>(u0v[v], fma(cA, dt * r, accv[v]), c);
+          if constexpr (COMP) {
+            T c = at_off(p.comp + o, toff);
+            out[v] = comp_add<T>(at_off(p.U0 + o, toff), fma(cA, dt * r, accv[v]), c);
             at_off(p.comp + o, toff) = c;
           } else {
             out[v] = fma(cA, dt * r, accv[v]);
@@ -627,15 +625,15 @@ template <typename T, int TX, int TY>
 constexpr int ns_threads() {
   return sizeof(T) == 4 ? TX * TY : (TX + 8) * (TY + 8);
 }
-template <typename T, int TX, int TY, int KIND, int NDIM>
+template <typename T, int TX, int TY, int KIND, int NDIM, bool COMP = false>
 __device__ __forceinline__ void ns_tile(const StageParams<T>& p, const TileDev t) {
   if constexpr (sizeof(T) == 4) {
     if (p.cd2)
-      ns_tile_lean<T, TX, TY, KIND, NDIM, true>(p, t);
+      ns_tile_lean<T, TX, TY, KIND, NDIM, true, COMP>(p, t);
     else
-      ns_tile_lean<T, TX, TY, KIND, NDIM, false>(p, t);
+      ns_tile_lean<T, TX, TY, KIND, NDIM, false, COMP>(p, t);
   } else
-    ns_tile_wide<T, TX, TY, KIND, NDIM>(p, t);
+    ns_tile_wide<T, TX, TY, KIND, NDIM, COMP>(p, t);
 }
 
 // Single precision: at least three waves per SIMD (at most 168 registers),
@@ -645,11 +643,11 @@ constexpr int ns_min_waves() {
   return sizeof(T) == 4 ? 3 : 1;
 }
 
-template <typename T, int TX, int TY, int KIND, int NDIM>
+template <typename T, int TX, int TY, int KIND, int NDIM, bool COMP = false>
 __global__ void __launch_bounds__((ns_threads<T, TX, TY>())) __attribute__((amdgpu_waves_per_eu(ns_min_waves<T>())))
 ns_stage_kernel(const StageParams<T> p) {
   const StageParams<T> q = resolve_step(p);
-  ns_tile<T, TX, TY, KIND, NDIM>(q, p.tiles[blockIdx.x]);
+  ns_tile<T, TX, TY, KIND, NDIM, COMP>(q, p.tiles[blockIdx.x]);
   if (p.step_end) finish_step(p.step_end, p.done);
 }
 
@@ -766,13 +764,13 @@ template hipError_t launch_ns_batch<float>(const StageParams<float>*, const Batc
 template hipError_t launch_ns_batch<double>(const StageParams<double>*, const BatchTile*, int, int, int, int, int,
                                             hipStream_t, int*);
 
-template <typename T, int KIND, int TX, int TY>
+template <typename T, int KIND, int TX, int TY, bool COMP = false>
 hipError_t launch_ns_kind(const StageParams<T>& p, int ntiles, hipStream_t s) {
   dim3 grid(ntiles), block(ns_threads<T, TX, TY>());
   if (p.ndim == 3)
-    ns_stage_kernel<T, TX, TY, KIND, 3><<<grid, block, 0, s>>>(p);
+    ns_stage_kernel<T, TX, TY, KIND, 3, COMP><<<grid, block, 0, s>>>(p);
   else
-    ns_stage_kernel<T, TX, TY, KIND, 2><<<grid, block, 0, s>>>(p);
+    ns_stage_kernel<T, TX, TY, KIND, 2, COMP><<<grid, block, 0, s>>>(p);
   return hipGetLastError();
 }
 
@@ -782,7 +780,9 @@ hipError_t launch_ns_shape(const StageParams<T>& p, int ntiles, int kind, hipStr
     case kRhsOnly: return launch_ns_kind<T, kRhsOnly, TX, TY>(p, ntiles, s);
     case kRK4First: return launch_ns_kind<T, kRK4First, TX, TY>(p, ntiles, s);
     case kRK4Mid: return launch_ns_kind<T, kRK4Mid, TX, TY>(p, ntiles, s);
-    case kRK4Last: return launch_ns_kind<T, kRK4Last, TX, TY>(p, ntiles, s);
+    case kRK4Last:
+      return p.comp ? launch_ns_kind<T, kRK4Last, TX, TY, true>(p, ntiles, s)
+                    : launch_ns_kind<T, kRK4Last, TX, TY>(p, ntiles, s);
     case kLSFirst: return launch_ns_kind<T, kLSFirst, TX, TY>(p, ntiles, s);
     default: return launch_ns_kind<T, kLSMid, TX, TY>(p, ntiles, s);
   }

@@ -34,7 +34,7 @@ __device__ __forceinline__ NsWideLds<T, TX, TY>& ns_wide_lds() {
   return s;
 }
 
-template <typename T, int TX, int TY, int KIND, int NDIM>
+template <typename T, int TX, int TY, int KIND, int NDIM, bool COMP = false>
 __device__ __forceinline__ void ns_tile_wide(const StageParams<T>& p, const TileDev t) {
   constexpr int EX = TX + 8, EY = TY + 8;
   constexpr bool three = (NDIM == 3);
@@ -169,7 +169,7 @@ __device__ __forceinline__ void ns_tile_wide(const StageParams<T>& p, const Tile
 #pragma unroll
       for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + gi];
     }
-    epilogue_load<T, KIND>(p, gi, accv, u0v);
+    epilogue_load<T, KIND, COMP>(p, gi, accv, u0v);
   }
 
   for (int f = f_begin; f < f_end; ++f) {
@@ -329,14 +329,14 @@ __device__ __forceinline__ void ns_tile_wide(const StageParams<T>& p, const Tile
 #pragma unroll
       for (int v = 0; v < 5; ++v) R[v] = three ? -(sXY[buf][v][y][x] + zd[v]) : -xyn[v];
       T out[5];
-      epilogue_pre<T, KIND>(p, gi, Yv, R, accv, u0v, out);
+      epilogue_pre<T, KIND, COMP>(p, gi, Yv, R, accv, u0v, out);
       if (pz + 1 < z0 + nz) {
         gi += gplane;
         if (needY) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) Yv[v] = p.Y[v * p.field + gi];
         }
-        epilogue_load<T, KIND>(p, gi, accv, u0v);
+        epilogue_load<T, KIND, COMP>(p, gi, accv, u0v);
       }
       if (ring_slot) ring_write_col(B, rcol, p.H, true, lx, ly, pz, out, ring_slot);
     }
