@@ -98,6 +98,18 @@ def stage_kernel_bytes_per_point(w, stages, esz):
     return (80.0 + 20.0 * f + 20.0 * f / stages) * scale
 
 
+def filter_bytes_per_point(w):
+    """Bytes per owned point the filter of one step with delayed halos must
+    move (3-D cubic blocks of side s, FP32): the state read and written once
+    (40 B), the 10 halo values per line of each of the three passes (600/s B),
+    the ring write of the filtered boundary layers (faces 5 deep, 2-wide edge
+    prisms: 30/s + 48/s^2 values per point, 5 variables), and the filter-halo
+    slot (5-deep faces, 30/s values per point) that the halo kernel writes
+    from the delayed levels it already reads for the stage halos."""
+    s = w["n"][0] // w["nblk"][0]
+    return 40.0 + 600.0 / s + 20.0 * (30.0 / s + 48.0 / s ** 2) + 20.0 * 30.0 / s
+
+
 def make_solver(w, precision, mode=None, filter_alpha=None):
     phys = atns.NS if w["physics"] == "ns" else atns.EULER
     m = {"sa": atns.SA, "as": atns.AS, "at": atns.AT}[mode or w["mode"]]
@@ -910,16 +922,22 @@ def headline_main(a, torch, cpu):
     U_at = at.pop("U")
     if ns and not a.no_filter:
         # the same steps with the tenth-order filter after each (Sec. 5.2's
-        # alpha_f): three line-solve passes and the ring write of the
-        # filtered field, which the last stage then leaves out
+        # alpha_f): one launch per step runs the three line-solve passes of
+        # each block and variable and writes the filtered boundary layers to
+        # the ring, which the last stage then leaves out
         fl = run_path(torch, w, atns.F32, None, a.steps, warmup, dt, U0, filter_alpha=FILTER_ALPHA)
         fl.pop("U")
         extra = (fl["ms"] - at["ms"]) / a.steps
-        fbytes = (3 * 2 * 20.0 + 20.0) * npts     # 3 passes read and write the state; the ring fill reads it
+        fbpp = filter_bytes_per_point(w)
+        fbytes = fbpp * npts
         out["at_filtered"] = {"alpha": FILTER_ALPHA, "value": npts * stages * a.steps / (fl["ms"] * 1e-3),
                               "ms_per_step": fl["ms"] / a.steps, "filter_ms_per_step": extra,
-                              "filter_bytes_per_step": fbytes,
+                              "filter_bytes_per_point": fbpp, "filter_bytes_per_step": fbytes,
                               "filter_hbm_frac": (fbytes / (extra * 1e-3) / 1e9 / HBM_PEAK_GBS) if extra > 0 else None,
+                              "basis": "the filter's algorithmic bytes per step (state in and out once, the "
+                                       "filter halo values of the three passes, the ring write of the filtered "
+                                       "boundary layers, the filter-halo slot the halo kernel writes) over the "
+                                       "filtered step's extra time",
                               "finite": fl["finite"]}
     # the learned halo, trained on the GPU by the library's kernels
     U_mlp = None

@@ -278,6 +278,19 @@ atns_status atns_set_fusion(atns_ctx* ctx, int32_t on);
  * Errors: ATNS_EINVAL for a null context. */
 atns_status atns_set_halo_fusion(atns_ctx* ctx, int32_t on);
 
+/* The filter of a step with delayed halos (AT or AS, step >= C) in one
+ * launch (on != 0; default on): with delayed halos no filter pass reads
+ * another block's values (Sec. 2's filter applied block-locally, the halo
+ * values coming from the delayed levels), so one workgroup per block and
+ * variable runs the x, y and z passes on an LDS copy of the block and writes
+ * the filtered boundary layers to the ring, in place of three per-axis
+ * launches and the ring fill.  Same arithmetic, so the same bits either way.
+ * Applied to 3-D contexts whose blocks are all cubes of side 8, 16 or 32
+ * (at most 16 in double precision); other contexts, synchronous steps and
+ * atns_filter_state() take the per-axis passes.  Errors: ATNS_EINVAL for a
+ * null context. */
+atns_status atns_set_filter_fusion(atns_ctx* ctx, int32_t on);
+
 /* Advance nsteps free-running asynchronous steps: the synchronization-
  * avoiding algorithm (Alg. 3) with delays that arise from the run itself
  * instead of a schedule.  One persistent workgroup per block advances its

@@ -37,7 +37,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "EN
 
 EXPORTS = ["atns_version", "atns_create", "atns_destroy", "atns_last_error", "atns_set_state",
            "atns_get_state", "atns_get_step", "atns_set_dt", "atns_set_delays", "atns_get_delays",
-           "atns_rhs", "atns_rk_step", "atns_step_async", "atns_set_fusion", "atns_set_halo_fusion", "atns_reduce", "atns_reduce_noalloc", "atns_get_layout", "atns_set_graphs", "atns_profile_enable",
+           "atns_rhs", "atns_rk_step", "atns_step_async", "atns_set_fusion", "atns_set_halo_fusion", "atns_set_filter_fusion", "atns_reduce", "atns_reduce_noalloc", "atns_get_layout", "atns_set_graphs", "atns_profile_enable",
            "atns_profile_read", "atns_set_tiles", "atns_get_tiles", "atns_autotune",
            "atns_mlp_set_params", "atns_mlp_get_params", "atns_mlp_set_scales", "atns_mlp_forward",
            "atns_mlp_grad", "atns_mlp_sample", "atns_mlp_train", "atns_mlp_enable", "atns_mlp_stats",
@@ -90,6 +90,7 @@ def lib():
             "atns_step_async": ([vp, i32, i64, vp], i32),
             "atns_set_fusion": ([vp, i32], i32),
             "atns_set_halo_fusion": ([vp, i32], i32),
+            "atns_set_filter_fusion": ([vp, i32], i32),
             "atns_reduce": ([vp, vp], i32),
             "atns_reduce_noalloc": ([vp, i32, i32, vp, vp, vp, vp], i32),
             "atns_get_layout": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
@@ -331,6 +332,11 @@ class Solver:
         """Halo assembly inside the first stage of graph-captured Euler steps
         (default off); results are the same bits either way."""
         _check(lib().atns_set_halo_fusion(self.ctx, 1 if on else 0), self.ctx)
+
+    def set_filter_fusion(self, on):
+        """The filter of steps with delayed halos as one launch per step
+        (default on); results are the same bits either way."""
+        _check(lib().atns_set_filter_fusion(self.ctx, 1 if on else 0), self.ctx)
 
     def set_graphs(self, on):
         _check(lib().atns_set_graphs(self.ctx, 1 if on else 0), self.ctx)

@@ -61,6 +61,7 @@ struct atns_ctx {
   double fah[6] = {0, 0, 0, 0, 0, 0};   // filter: a_0, a_1/2, ..., a_5/2
   void* comp = nullptr;              // compensated RK4: rounding error carried per point
   bool comp_on = false;
+  bool fused_filter = true;          // filter steps with delayed halos in one kernel
   HaloRegion* d_regions = nullptr;
   HaloWork* d_work = nullptr;
   int nwork = 0;
@@ -655,24 +656,41 @@ atns_status enqueue_filter(atns_ctx* c, int fin, int halo, const long long* nste
   T* bufs3[4] = {U, (T*)c->X[1 - fin], (T*)c->X[2], U};
   T* bufs2[3] = {U, (T*)c->X[1 - fin], U};
   T** bufs = c->cfg.ndim == 3 ? bufs3 : bufs2;
+  FilterArgs<T> f{};
+  f.blocks = c->d_blocks;
+  f.fhalo = c->hbuf ? (const T*)c->hbuf + (size_t)c->rk.stages * c->slot_stride : nullptr;
+  f.inv = c->d_finv;
+  f.cp = c->d_fcp;
+  for (int i = 0; i < 3; ++i) f.n[i] = c->n[i];
+  f.field = c->field;
+  f.H = c->H;
+  f.halo = halo;
+  f.nstep = nstep;
+  f.C = c->C;
+  f.async_halo = c->cfg.mode == ATNS_SA ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
+  for (int m = 0; m < 6; ++m) f.ah[m] = c->fah[m];
+  f.alpha = c->cfg.filter_alpha;
+  // Steps with delayed halos filter each block in one workgroup per variable
+  // (every block a cube of a size the fused kernel is built for).  Captured
+  // steps are the asynchronous ones (step >= C), so they always take it.
+  const int side = c->blocks.empty() ? 0 : c->blocks[0].s[0];
+  bool fused = c->cfg.ndim == 3 && c->ring && f.fhalo && c->cfg.mode != ATNS_SA && c->fused_filter &&
+               filter_fused_fits(side, (int)sizeof(T)) && (nstep || halo != kHaloSync);
+  for (const BlockDev& B : c->blocks) fused = fused && B.s[0] == side && B.s[1] == side && B.s[2] == side;
+  if (fused) {
+    f.in = U;
+    f.out = U;
+    f.ring = (T*)c->ring;
+    f.slot_stride = c->slot_stride;
+    f.D = c->D;
+    f.slot = slot;
+    HIP_TRY(c, launch_filter_fused<T>(f, c->nb, side, s));
+    return ATNS_OK;
+  }
   for (int d = 0; d < c->cfg.ndim; ++d) {
-    FilterArgs<T> f{};
     f.in = bufs[d];
     f.out = bufs[d + 1];
-    f.blocks = c->d_blocks;
-    f.fhalo = c->hbuf ? (const T*)c->hbuf + (size_t)c->rk.stages * c->slot_stride : nullptr;
-    f.inv = c->d_finv;
-    f.cp = c->d_fcp;
-    for (int i = 0; i < 3; ++i) f.n[i] = c->n[i];
-    f.field = c->field;
-    f.H = c->H;
     f.dir = d;
-    f.halo = halo;
-    f.nstep = nstep;
-    f.C = c->C;
-    f.async_halo = c->cfg.mode == ATNS_SA ? kHaloSync : (c->cfg.mode == ATNS_AS ? kHaloStale : kHaloAT);
-    for (int m = 0; m < 6; ++m) f.ah[m] = c->fah[m];
-    f.alpha = c->cfg.filter_alpha;
     const int pa = d == 0 ? 1 : 0, qa = d == 2 ? 1 : 2;
     int max_lines = 1, max_len = 1, min_len = kFilterMaxLen;
     for (const BlockDev& B : c->blocks) {
@@ -1299,6 +1317,15 @@ atns_status atns_set_halo_fusion(atns_ctx* c, int32_t on) {
   return guarded(c, [&]() -> atns_status {
     if (!c) return fail(c, ATNS_EINVAL, "null context");
     c->halo_fusion = on != 0;
+    drop_graphs(c);
+    return ATNS_OK;
+  });
+}
+
+atns_status atns_set_filter_fusion(atns_ctx* c, int32_t on) {
+  return guarded(c, [&]() -> atns_status {
+    if (!c) return fail(c, ATNS_EINVAL, "null context");
+    c->fused_filter = on != 0;
     drop_graphs(c);
     return ATNS_OK;
   });

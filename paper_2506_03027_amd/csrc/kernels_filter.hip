@@ -15,12 +15,43 @@
 // (synchronous steps: the neighbours' current values) or from the
 // filter-halo slot of the stage-halo buffer, assembled by halo_kernel from
 // the delayed levels (AT: extrapolated to the new level; AS: the newest).
+// With delayed halos no pass reads another block's values, so one workgroup
+// can run all three passes of a block from an LDS copy (filter_fused_kernel).
+#include <type_traits>
+
 #include "kernels_common.hpp"
 #include "launch.hpp"
 
 namespace atns {
 
 constexpr int kFilterLines = 64;   // lines (threads) per workgroup
+
+// The line solve of one pass, the arithmetic of filter_pass_kernel in the
+// same order: ph holds line positions -5 .. LEN+4 (the halo values at both
+// ends); put(i, value) receives the filtered values from the last point to
+// the first.
+template <typename T, int LEN, typename Put>
+__device__ __forceinline__ void filter_line(const T* ph, const FilterArgs<T>& f, Put&& put) {
+  const double al = f.alpha;
+  double dq[LEN];
+  double dp = 0.0;
+#pragma unroll
+  for (int i = 0; i < LEN; ++i) {
+    double r = f.ah[0] * (double)ph[i + 5];
+#pragma unroll
+    for (int m = 1; m < 6; ++m) r = fma(f.ah[m], (double)ph[i + 5 + m] + (double)ph[i + 5 - m], r);
+    if (i == 0) r = fma(-al, (double)ph[4], r);
+    if (i == LEN - 1) r = fma(-al, (double)ph[LEN + 5], r);
+    dp = (r - al * dp) * f.inv[i];
+    dq[i] = dp;
+  }
+  double x = 0.0;
+#pragma unroll
+  for (int i = LEN - 1; i >= 0; --i) {
+    x = i == LEN - 1 ? dq[i] : dq[i] - f.cp[i] * x;
+    put(i, (T)x);
+  }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kFilterLines) filter_pass_kernel(const FilterArgs<T> f) {
@@ -216,6 +247,8 @@ __global__ void __launch_bounds__(kFilterLines) filter_pass_fixed_kernel(const F
       else
         ph[j] = f.fhalo[lay_hi + v * vs + lo0 + (long long)(i - LEN) * lstep];
     }
+    // the arithmetic of filter_line, written out so that the stores can sit
+    // in the back substitution's own loop
     double dq[LEN];
     double dp = 0.0;
 #pragma unroll
@@ -263,6 +296,120 @@ __global__ void __launch_bounds__(kFilterLines) filter_pass_fixed_kernel(const F
     }
   }
 }
+
+// All three passes of one variable of one block, a cube of side LEN, with
+// delayed halos: workgroup (v, b), one thread per line of each pass.  The
+// block's values of variable v are read once into LDS (rows padded to
+// LEN + 1, so that the lines of every axis fall in distinct banks), the x, y
+// and z passes each solve the block's LEN^2 lines of their axis from LDS,
+// with the halo values from the filter-halo slot (the next pass's are
+// loaded while a pass computes), the z pass stores the result, and after a
+// barrier each thread writes the boundary values of its column to the ring.
+// Each line's arithmetic is filter_line, as in the per-axis passes, so the
+// results are the same bits.
+template <typename T, int LEN>
+__global__ void __launch_bounds__(LEN * LEN) filter_fused_kernel(const FilterArgs<T> f) {
+  constexpr int PY = LEN + 1, PZ = LEN * PY;
+  __shared__ T sU[LEN * PZ];
+  int halo = f.halo;
+  if (f.nstep) halo = (*f.nstep - 1 >= f.C) ? f.async_halo : kHaloSync;
+  if (halo == kHaloSync || f.fhalo == nullptr) return;   // the per-axis passes take this step
+  const int v = blockIdx.x;
+  const BlockDev* __restrict__ B = f.blocks + blockIdx.y;
+  const int tid = threadIdx.x;
+  const int a = tid % LEN, b = tid / LEN;   // the thread's line: (y, z), (x, z), (x, y)
+  const int H = f.H;
+  const long long nxy = (long long)f.n[0] * f.n[1];
+  const long long n0 = f.n[0];
+  const long long gb = v * f.field + (long long)B->o[2] * nxy + (long long)B->o[1] * n0 + B->o[0];
+  // the halo values of the thread's line of pass d: positions -5..-1 of the
+  // low face, LEN..LEN+4 of the high one.  Layers: x-faces [s_z][s_y][H],
+  // y-faces [s_z][H][s_x], z-faces [H][s_y][s_x], variables outermost.
+  auto halo_load = [&](auto dc, T hv[10]) {
+    constexpr int d = decltype(dc)::value;
+    constexpr int lstep = d == 0 ? 1 : (d == 1 ? LEN : LEN * LEN);
+    const long long vs = (long long)LEN * LEN * H;
+    const T* hlo = f.fhalo + B->hoff[2 * d] + v * vs;
+    const T* hhi = f.fhalo + B->hoff[2 * d + 1] + v * vs;
+    const int lo0 = d == 0 ? (b * LEN + a) * H : (d == 1 ? b * H * LEN + a : b * LEN + a);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      hv[j] = hlo[lo0 + (j - 5 + H) * lstep];
+      hv[5 + j] = hhi[lo0 + j * lstep];
+    }
+  };
+  T hv[10];
+  halo_load(std::integral_constant<int, 0>{}, hv);
+  {
+    // the block's values of variable v, each thread a row per load
+    const T* in = f.in + gb;
+    if constexpr (sizeof(T) == 4 && LEN % 4 == 0) {
+      using V4 = float __attribute__((ext_vector_type(4)));
+      constexpr int Q = LEN / 4;   // float4 per row
+#pragma unroll
+      for (int k = tid; k < LEN * LEN * Q; k += LEN * LEN) {
+        const int q = k % Q, y = (k / Q) % LEN, z = k / (Q * LEN);
+        const V4 x4 = *reinterpret_cast<const V4*>(in + z * nxy + y * n0 + 4 * q);
+        T* d = sU + z * PZ + y * PY + 4 * q;
+        d[0] = x4.x;
+        d[1] = x4.y;
+        d[2] = x4.z;
+        d[3] = x4.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = tid; k < LEN * LEN * LEN; k += LEN * LEN) {
+        const int x = k % LEN, y = (k / LEN) % LEN, z = k / (LEN * LEN);
+        sU[z * PZ + y * PY + x] = in[z * nxy + y * n0 + x];
+      }
+    }
+  }
+  __syncthreads();
+  T* out = f.out + gb;
+  auto pass = [&](auto dc) {
+    constexpr int d = decltype(dc)::value;
+    constexpr int sstep = d == 0 ? 1 : (d == 1 ? PY : PZ);   // LDS stride along the line
+    const int s0 = d == 0 ? b * PZ + a * PY : (d == 1 ? b * PZ + a : b * PY + a);
+    T ph[LEN + 10];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      ph[j] = hv[j];
+      ph[LEN + 5 + j] = hv[5 + j];
+    }
+#pragma unroll
+    for (int i = 0; i < LEN; ++i) ph[i + 5] = sU[s0 + i * sstep];
+    if constexpr (d < 2) halo_load(std::integral_constant<int, d + 1>{}, hv);
+    filter_line<T, LEN>(ph, f, [&](int i, T val) {
+      sU[s0 + i * sstep] = val;
+      if constexpr (d == 2) out[i * nxy + b * n0 + a] = val;
+    });
+    __syncthreads();
+  };
+  pass(std::integral_constant<int, 0>{});
+  pass(std::integral_constant<int, 1>{});
+  pass(std::integral_constant<int, 2>{});
+  // the filtered boundary layers of variable v into the ring slot of the new
+  // level: the thread's column (a, b)
+  T* slot = f.ring + (long long)(f.nstep ? (int)(*f.nstep % f.D) : f.slot) * f.slot_stride;
+  const RingColumn rc = ring_column(B, H, a, b);
+  for (int lz = 0; lz < LEN; ++lz) ring_write_var(B, rc, H, a, b, lz, v, sU[lz * PZ + b * PY + a], slot);
+}
+
+template <typename T>
+hipError_t launch_filter_fused(const FilterArgs<T>& f, int nblocks, int side, hipStream_t s) {
+  if (!filter_fused_fits(side, (int)sizeof(T))) return hipErrorInvalidValue;
+  dim3 grid(5, nblocks);
+  if (side == 8) {
+    filter_fused_kernel<T, 8><<<grid, 8 * 8, 0, s>>>(f);
+  } else if (side == 16) {
+    filter_fused_kernel<T, 16><<<grid, 16 * 16, 0, s>>>(f);
+  } else {
+    if constexpr (sizeof(T) == 4) filter_fused_kernel<T, 32><<<grid, 32 * 32, 0, s>>>(f);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_filter_fused<float>(const FilterArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_filter_fused<double>(const FilterArgs<double>&, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_filter_pass(const FilterArgs<T>& f, int nblocks, int max_lines, int min_len, int max_len,

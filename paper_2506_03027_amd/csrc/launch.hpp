@@ -62,6 +62,16 @@ inline bool filter_pass_fixed(int min_len, int max_len) {
 template <typename T>
 hipError_t launch_filter_pass(const FilterArgs<T>& f, int nblocks, int max_lines, int min_len, int max_len,
                               hipStream_t s);
+// All three passes of a step with delayed halos in one launch, and the ring
+// write of the filtered field: 3-D blocks that are all cubes of side 8, 16 or
+// 32 (16 at most in double precision).  Synchronous steps, whose y and z
+// passes read the neighbours' values of the pass before, take the per-axis
+// passes (with f.nstep the kernel checks, and returns on such a step).
+inline bool filter_fused_fits(int side, int esz) {
+  return (side == 8 || side == 16 || side == 32) && (esz == 4 || side <= 16);
+}
+template <typename T>
+hipError_t launch_filter_fused(const FilterArgs<T>& f, int nblocks, int side, hipStream_t s);
 // Workgroups (and FP64 partial sets of 7) of the diagnostics reduction; the
 // allocation-free form keeps its partials in a fixed device array of this size.
 constexpr int kDiagMaxParts = 1024;

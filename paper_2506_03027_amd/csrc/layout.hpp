@@ -224,6 +224,12 @@ struct FilterArgs {
   int async_halo;
   double ah[6];          // a_0, a_1/2, ..., a_5/2
   double alpha;
+  // fused kernel: the ring the filtered boundary layers go to, its slot
+  // (or, with nstep, *nstep mod D) and the slot size
+  T* ring;
+  long long slot_stride;
+  int D;
+  int slot;
 };
 
 }  // namespace atns

@@ -100,6 +100,7 @@ static void cpu_paths() {
   EXPECT(atns_rhs(nullptr, 0, nullptr) == ATNS_EINVAL, "rhs null");
   EXPECT(atns_filter_state(nullptr) == ATNS_EINVAL, "filter null");
   EXPECT(atns_set_compensation(nullptr, 1) == ATNS_EINVAL, "compensation null");
+  EXPECT(atns_set_filter_fusion(nullptr, 1) == ATNS_EINVAL, "filter fusion null");
   EXPECT(atns_set_dt(nullptr, 1.0) == ATNS_EINVAL, "dt null");
   size_t bytes = 0;
   EXPECT(atns_checkpoint(nullptr, nullptr, &bytes) == ATNS_EINVAL, "checkpoint null");
@@ -180,6 +181,8 @@ static void gpu_paths() {
   if (c) {
     check(atns_filter_state(c), "filter", c);
     check(atns_rk_step(c, 9), "filtered steps", c);
+    check(atns_set_filter_fusion(c, 0), "filter fusion off", c);
+    check(atns_rk_step(c, 2), "filtered steps, per-axis passes", c);
     check(atns_destroy(c), "destroy", nullptr);
   }
   std::printf("filter ok\n");
