@@ -304,7 +304,8 @@ __global__ void __launch_bounds__(kFilterLines) filter_pass_fixed_kernel(const F
 // and z passes each solve the block's LEN^2 lines of their axis from LDS,
 // with the halo values from the filter-halo slot (the next pass's are
 // loaded while a pass computes), the z pass stores the result, and after a
-// barrier each thread writes the boundary values of its column to the ring.
+// barrier the workgroup writes the block's boundary layers of variable v to
+// the ring, layer by layer in storage order.
 // Each line's arithmetic is filter_line, as in the per-axis passes, so the
 // results are the same bits.
 template <typename T, int LEN>
@@ -389,10 +390,32 @@ __global__ void __launch_bounds__(LEN * LEN) filter_fused_kernel(const FilterArg
   pass(std::integral_constant<int, 1>{});
   pass(std::integral_constant<int, 2>{});
   // the filtered boundary layers of variable v into the ring slot of the new
-  // level: the thread's column (a, b)
+  // level, walking each layer in its storage order ([5][ez][ey][ex], faces H
+  // deep, edges 2) so that every store is along contiguous memory
   T* slot = f.ring + (long long)(f.nstep ? (int)(*f.nstep % f.D) : f.slot) * f.slot_stride;
-  const RingColumn rc = ring_column(B, H, a, b);
-  for (int lz = 0; lz < LEN; ++lz) ring_write_var(B, rc, H, a, b, lz, v, sU[lz * PZ + b * PY + a], slot);
+  for (int sl = 0; sl < kNumSlots; ++sl) {
+    if (B->lay[sl] < 0) continue;
+    int dir[3];
+    slot_dir(sl, dir);
+    const int dep = sl < 6 ? H : 2;
+    int e[3], o[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      e[k] = dir[k] ? dep : LEN;
+      o[k] = dir[k] > 0 ? LEN - dep : 0;
+    }
+    const int cnt = e[0] * e[1] * e[2];
+    T* dst = slot + B->lay[sl] + (long long)v * cnt;
+    // i / e as the high half of i * ceil(2^32 / e): exact for e <= 32 and
+    // i < 2^27 (here i < LEN^3)
+    const unsigned m0 = 0xFFFFFFFFu / (unsigned)e[0] + 1u, m1 = 0xFFFFFFFFu / (unsigned)e[1] + 1u;
+    for (int idx = tid; idx < cnt; idx += LEN * LEN) {
+      const unsigned r = __umulhi((unsigned)idx, m0);
+      const unsigned iz = __umulhi(r, m1);
+      const int ix = idx - (int)r * e[0], iy = (int)r - (int)iz * e[1];
+      dst[idx] = sU[(o[2] + (int)iz) * PZ + (o[1] + iy) * PY + o[0] + ix];
+    }
+  }
 }
 
 template <typename T>
