@@ -217,7 +217,8 @@ atns_status atns_rhs(atns_ctx* ctx, int32_t stage, void* dev_R);
  * each pass input, AT steps the neighbours' level n+1 extrapolated from the
  * C delayed levels with the Lagrange weights of Eqs. 14-15 at delay k+1, AS
  * steps the newest delayed level), and the filtered field's boundary layers
- * go into the ring. */
+ * go into the ring (for steps with delayed halos in one launch, see
+ * atns_set_filter_fusion). */
 atns_status atns_rk_step(atns_ctx* ctx, int32_t nsteps);
 
 /* Compensated classical RK4 steps (on != 0).  The accumulator then holds
