@@ -719,14 +719,24 @@ def free_running_main(a, torch):
 
 def series_main(a, torch):
     """The workload run for a.series steps with the FP64 diagnostics (conserved
-    totals, kinetic energy, enstrophy) reduced on the GPU after every step."""
+    totals, kinetic energy, enstrophy) reduced on the GPU after every step; or,
+    with a.series_t, run to that time with the diagnostics every a.series
+    steps (the Taylor-Green runs of Sec. 5.2 through the dissipation peak,
+    with the filter when a.series_filter)."""
     w = inputs.WORKLOADS[a.workload]
-    g = make_solver(w, atns.F32)
+    if a.series_cfl:
+        w = dict(w, cfl=a.series_cfl)
+    if a.series_mode:
+        w = dict(w, mode=a.series_mode, L=w["L"] if a.series_mode != "sa" else 1)
+    alpha = FILTER_ALPHA if a.series_filter else None
+    g = make_solver(w, atns.F32, filter_alpha=alpha)
     n = w["n"]
     coarse = tuple(min(64, x) for x in n)
     U0 = (inputs.tgv_state(coarse, mach=w.get("mach", 0.1)) if w["physics"] == "ns"
           else inputs.vortex_state(coarse, w["length"], w["ndim"]))
     dt = inputs.cfl_dt(U0, n, w["length"], w["ndim"], 1.4, w["cfl"])
+    every = a.series if a.series_t else 1
+    nsteps = int(math.ceil(a.series_t / dt)) if a.series_t else a.series
     g.set_dt(dt)
     g.init_case(atns.CASE_TGV if w["physics"] == "ns" else atns.CASE_VORTEX)
     g.autotune(reps=10, cache=TUNE_CACHE)
@@ -734,11 +744,17 @@ def series_main(a, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     finite = True
-    for s in range(1, a.series + 1):
-        g.step(1)
+    s = 0
+    report = max(every, nsteps // 20)
+    while s < nsteps:
+        k = min(every, nsteps - s)
+        g.step(k)
+        s += k
         d, ok = g.reduce()
         finite = finite and ok
         rows.append((s, s * dt) + tuple(d))
+        if s % report < every:
+            print("[series] %s step %d t %.4f K %.6g" % (w["mode"], s, s * dt, d[5]), file=sys.stderr, flush=True)
         if not ok:
             break
     wall = time.perf_counter() - t0
@@ -749,13 +765,17 @@ def series_main(a, torch):
         # the same series from the FP64 synchronous solver (the scheme without
         # delays or FP32 rounding), step for step
         def sa_series(precision):
-            r = make_solver(dict(w, mode="sa", L=1), precision)
+            r = make_solver(dict(w, mode="sa", L=1), precision, filter_alpha=alpha)
             r.set_dt(dt)
             r.init_case(atns.CASE_TGV if w["physics"] == "ns" else atns.CASE_VORTEX)
             rr = [tuple(r.reduce()[0])]
-            for s in range(1, len(rows)):
-                r.step(1)
+            step_report = max(1, (len(rows) - 1) // 20)
+            for i in range(1, len(rows)):
+                r.step(int(rows[i][0] - rows[i - 1][0]))
                 rr.append(tuple(r.reduce()[0]))
+                if i % step_report == 0:
+                    print("[series] sa %s step %d" % ("f64" if precision == atns.F64 else "f32", int(rows[i][0])),
+                          file=sys.stderr, flush=True)
             r.close()
             return np.array(rr)
 
@@ -768,17 +788,34 @@ def series_main(a, torch):
                "fp32_sa_max_rel_diff_kinetic_energy": float(np.abs(Q32[:, 5] - Q[:, 5]).max() / abs(Q[0, 5])),
                "fp32_sa_max_rel_diff_enstrophy": float(np.abs(Q32[:, 6] - Q[:, 6]).max() / abs(Q[0, 6]))}
     if a.series_out:
-        np.savetxt(a.series_out, R, delimiter=",",
-                   header="step,t,mass,mom_x,mom_y,mom_z,energy,kinetic_energy,enstrophy", comments="")
+        hdr = "step,t,mass,mom_x,mom_y,mom_z,energy,kinetic_energy,enstrophy"
+        np.savetxt(a.series_out, R, delimiter=",", header=hdr, comments="")
+        if ref:
+            # the FP64 synchronous series beside it, same steps
+            root, ext = os.path.splitext(a.series_out)
+            np.savetxt(root + "_sa_f64" + (ext or ".csv"), np.hstack([R[:, :2], Q]), delimiter=",", header=hdr,
+                       comments="")
     K, E = R[:, 7], R[:, 8]
     out = {"workload": a.workload, "steps": int(R[-1, 0]), "dt": dt, "t_end": float(R[-1, 1]),
+           "mode": w["mode"], "cfl": w["cfl"], "filter_alpha": alpha, "reductions_every": every,
            "finite": bool(finite), "wall_s_with_per_step_reductions": wall,
            "kinetic_energy": {"t0": float(K[0]), "end": float(K[-1]),
                               "monotone_nonincreasing": bool(np.all(np.diff(K) <= 1e-12 * K[0]))},
            "enstrophy": {"t0": float(E[0]), "end": float(E[-1]), "max": float(E.max())},
            "mass_rel_drift": float(abs(R[-1, 2] - R[0, 2]) / abs(R[0, 2])),
-           "energy_rel_drift": float(abs(R[-1, 6] - R[0, 6]) / abs(R[0, 6])),
-           "dK_dt_fit_first_200_steps": float(np.polyfit(R[:201, 1], K[:201], 1)[0])}
+           "energy_rel_drift": float(abs(R[-1, 6] - R[0, 6]) / abs(R[0, 6]))}
+    if every == 1 and len(R) > 200:
+        out["dK_dt_fit_first_200_steps"] = float(np.polyfit(R[:201, 1], K[:201], 1)[0])
+    if w["physics"] == "ns":
+        # viscous dissipation 2 (1/Re) * enstrophy, and its peak
+        re = w.get("re", 1600.0)
+        i = int(np.argmax(E))
+        out["dissipation_peak"] = {"t": float(R[i, 1]), "value": float(2.0 * E[i] / re)}
+        if ref:
+            j = int(np.argmax(Q[:, 6]))
+            ref["dissipation_peak"] = {"t": float(R[j, 1]), "value": float(2.0 * Q[j, 6] / re)}
+            ref["max_abs_diff_dissipation_over_peak"] = float(np.abs(E - Q[:, 6]).max() / Q[:, 6].max())
+            ref["max_abs_diff_kinetic_energy_over_k0"] = float(np.abs(K - Q[:, 5]).max() / Q[0, 5])
     if ref:
         out["reference"] = ref
     print(json.dumps(out))
@@ -1040,6 +1077,15 @@ def main():
     ap.add_argument("--series-out", default=None, help="CSV file for --series")
     ap.add_argument("--series-ref", action="store_true",
                     help="with --series: also run the FP64 synchronous solver and compare the series")
+    ap.add_argument("--series-t", type=float, default=None,
+                    help="with --series: run to this time instead (--series then gives the steps between "
+                         "reductions)")
+    ap.add_argument("--series-cfl", type=float, default=None, help="with --series: CFL number of the run")
+    ap.add_argument("--series-mode", choices=["at", "as", "sa"], default=None,
+                    help="with --series: halo mode of the run (default: the workload's)")
+    ap.add_argument("--series-filter", action="store_true",
+                    help="with --series: the tenth-order filter (alpha_f = 0.499) after every step, on both "
+                         "solvers")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"), default=None,
                     help="write profiles/traffic_<workload>.json from two rocprofv3 --pmc runs (FETCH_SIZE, "
                          "WRITE_SIZE) of this script; no GPU work")
