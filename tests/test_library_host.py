@@ -194,3 +194,31 @@ def test_create_rejects_bad_filter_config_without_device(bad):
     out = np.zeros(6)
     assert atns.lib().atns_host_filter_coefficients(0.6, out.ctypes.data) == -1
     assert atns.lib().atns_filter_state(None) == -1
+
+
+def test_filter_byte_accounting_counts_the_ring_layers():
+    """bench.py's bytes per point of the filter with delayed halos: the state
+    in and out (40 B), ten halo values per line of each of three passes
+    (600/s B for cubic blocks of side s), the ring write of the filtered
+    boundary layers and the filter-halo slot.  The ring values are counted
+    here by walking the 18 face and edge layers with their extents (faces 5
+    deep with the filter, edges 2), independently of bench's closed form."""
+    import bench
+    from paper_2506_03027_amd import inputs
+    w = inputs.WORKLOADS["tgv_512"]
+    s = w["n"][0] // w["nblk"][0]
+    dirs = [(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+    dirs += [(a, b, 0) for b in (-1, 1) for a in (-1, 1)]
+    dirs += [(a, 0, c) for c in (-1, 1) for a in (-1, 1)]
+    dirs += [(0, b, c) for c in (-1, 1) for b in (-1, 1)]
+    ring = 0
+    for d in dirs:
+        dep = 5 if sum(map(abs, d)) == 1 else 2
+        n = 1
+        for k in range(3):
+            n *= dep if d[k] else s
+        ring += n
+    faces = 6 * 5 * s * s
+    want = 40.0 + 3 * 10 * 20.0 / s + 20.0 * ring / s ** 3 + 20.0 * faces / s ** 3
+    assert abs(bench.filter_bytes_per_point(w) - want) < 1e-12
+    assert abs(bench.filter_bytes_per_point(w) - 97.1875) < 1e-12
