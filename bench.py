@@ -726,10 +726,12 @@ def series_main(a, torch):
     w = inputs.WORKLOADS[a.workload]
     if a.series_cfl:
         w = dict(w, cfl=a.series_cfl)
+    if a.series_L:
+        w = dict(w, L=a.series_L)
     if a.series_mode:
         w = dict(w, mode=a.series_mode, L=w["L"] if a.series_mode != "sa" else 1)
     alpha = FILTER_ALPHA if a.series_filter else None
-    g = make_solver(w, atns.F32, filter_alpha=alpha)
+    g = make_solver(w, atns.F64 if a.series_f64 else atns.F32, filter_alpha=alpha)
     n = w["n"]
     coarse = tuple(min(64, x) for x in n)
     U0 = (inputs.tgv_state(coarse, mach=w.get("mach", 0.1)) if w["physics"] == "ns"
@@ -797,7 +799,8 @@ def series_main(a, torch):
                        comments="")
     K, E = R[:, 7], R[:, 8]
     out = {"workload": a.workload, "steps": int(R[-1, 0]), "dt": dt, "t_end": float(R[-1, 1]),
-           "mode": w["mode"], "cfl": w["cfl"], "filter_alpha": alpha, "reductions_every": every,
+           "mode": w["mode"], "L": w["L"], "precision": "f64" if a.series_f64 else "f32", "cfl": w["cfl"],
+           "filter_alpha": alpha, "reductions_every": every,
            "finite": bool(finite), "wall_s_with_per_step_reductions": wall,
            "kinetic_energy": {"t0": float(K[0]), "end": float(K[-1]),
                               "monotone_nonincreasing": bool(np.all(np.diff(K) <= 1e-12 * K[0]))},
@@ -1083,6 +1086,9 @@ def main():
     ap.add_argument("--series-cfl", type=float, default=None, help="with --series: CFL number of the run")
     ap.add_argument("--series-mode", choices=["at", "as", "sa"], default=None,
                     help="with --series: halo mode of the run (default: the workload's)")
+    ap.add_argument("--series-L", type=int, default=None,
+                    help="with --series: delay bound L of the run (delays up to L - 1)")
+    ap.add_argument("--series-f64", action="store_true", help="with --series: the run in FP64")
     ap.add_argument("--series-filter", action="store_true",
                     help="with --series: the tenth-order filter (alpha_f = 0.499) after every step, on both "
                          "solvers")
