@@ -737,7 +737,7 @@ def series_main(a, torch):
     U0 = (inputs.tgv_state(coarse, mach=w.get("mach", 0.1)) if w["physics"] == "ns"
           else inputs.vortex_state(coarse, w["length"], w["ndim"]))
     dt = inputs.cfl_dt(U0, n, w["length"], w["ndim"], 1.4, w["cfl"])
-    every = a.series if a.series_t else 1
+    every = max(1, a.series) if a.series_t else 1
     nsteps = int(math.ceil(a.series_t / dt)) if a.series_t else a.series
     g.set_dt(dt)
     g.init_case(atns.CASE_TGV if w["physics"] == "ns" else atns.CASE_VORTEX)
